@@ -1,0 +1,231 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle/soref.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only callers.  The product
+library (``paper_1903_04946_amd``) never imports this module.
+
+The oracle follows arXiv:1903.04946 (Roulet, Choi, Vanicek): composition
+coefficients (Sec. "Symmetric composition schemes"), splitting, pruning and
+unique coefficients (Sec. "Pruning splitting coefficients", Table II), the
+dynamic Fourier method (Sec. "Dynamic Fourier method"), the Jacobi-based
+potential exponential (Sec. "Molecular Hamiltonian in the diabatic basis")
+and the exact evolution operator (Eq. exact_evol_op) by dense
+diagonalisation on tiny grids.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "soref.cpp")
+
+STRANG, TRIPLE_JUMP, SUZUKI = 0, 1, 2
+VTV, TVT, VT, TV = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain -O2, OpenMP over independent loops)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["g++", "-O2", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp",
+               "-std=c++17", "-shared", "-fPIC", _SRC, "-o", _LIB_PATH + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("nsurf", ctypes.c_int),
+        ("inv_mass", ctypes.c_double * 3),
+        ("hbar", ctypes.c_double),
+        ("vtable", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        pp = ctypes.POINTER(_Problem)
+        L.orc_gammas.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_splitting.argtypes = [ctypes.c_int] * 4 + [dp, dp, ctypes.c_int]
+        L.orc_unique.argtypes = [ctypes.c_int] * 3 + [dp, dp, ip, ip, ctypes.c_int, ip]
+        L.orc_fft.argtypes = [ctypes.c_int, ctypes.c_int, dp]
+        L.orc_expm_potential.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_eigh.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_propagate.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_int64, ctypes.c_int, dp]
+        L.orc_action.argtypes = [pp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_observables.argtypes = [pp, dp, dp]
+        L.orc_overlap.argtypes = [pp, dp, dp, dp]
+        L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
+        for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
+                  "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
+                  "orc_exact"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+class Problem:
+    """Grid, surfaces, masses and V-table of a diabatic model (Eq. diab_mol_ham)."""
+
+    def __init__(self, n, lo, hi, nsurf, inv_mass, vtable, hbar=1.0):
+        n = list(n)
+        self.ndim = len(n)
+        self.n = n
+        self.lo = list(lo)
+        self.hi = list(hi)
+        self.nsurf = int(nsurf)
+        self.inv_mass = list(inv_mass)
+        self.hbar = float(hbar)
+        npts = int(np.prod(n))
+        ne = self.nsurf * (self.nsurf + 1) // 2
+        self.vtable = np.ascontiguousarray(vtable, dtype=np.float64).reshape(ne, npts)
+        self._s = _Problem()
+        self._s.ndim = self.ndim
+        for d in range(3):
+            self._s.n[d] = n[d] if d < self.ndim else 1
+            self._s.lo[d] = self.lo[d] if d < self.ndim else 0.0
+            self._s.hi[d] = self.hi[d] if d < self.ndim else 1.0
+            self._s.inv_mass[d] = self.inv_mass[d] if d < self.ndim else 0.0
+        self._s.nsurf = self.nsurf
+        self._s.hbar = self.hbar
+        self._s.vtable = _dp(self.vtable)
+
+    @property
+    def npts(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def shape(self):
+        return (self.nsurf, *self.n)
+
+    def ptr(self):
+        return ctypes.byref(self._s)
+
+
+def gammas(scheme: int, order: int) -> np.ndarray:
+    out = np.zeros(4096)
+    m = lib().orc_gammas(scheme, order, _dp(out), out.size)
+    if m < 0:
+        raise ValueError("invalid scheme/order")
+    return out[:m].copy()
+
+
+def splitting(split: int, scheme: int, order: int, pruned: bool):
+    a = np.zeros(8192)
+    b = np.zeros(8192)
+    n = lib().orc_splitting(split, scheme, order, int(pruned), _dp(a), _dp(b), a.size)
+    if n < 0:
+        raise ValueError("invalid split/scheme/order")
+    return a[:n].copy(), b[:n].copy()
+
+
+def unique(split: int, scheme: int, order: int):
+    cap = 4096
+    au = np.zeros(cap)
+    bu = np.zeros(cap)
+    ia = np.zeros(cap, dtype=np.int32)
+    ib = np.zeros(cap, dtype=np.int32)
+    counts = np.zeros(4, dtype=np.int32)
+    if lib().orc_unique(split, scheme, order, _dp(au), _dp(bu), _ip(ia), _ip(ib), cap,
+                        _ip(counts)) != 0:
+        raise ValueError("invalid split/scheme/order")
+    n, na, nb, _ = (int(c) for c in counts)
+    return au[:na].copy(), bu[:nb].copy(), ia[:n].copy(), ib[:n].copy()
+
+
+def fft(x: np.ndarray, inverse: bool = False) -> np.ndarray:
+    a = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    lib().orc_fft(a.size, int(inverse), _dp(a.view(np.float64)))
+    return a
+
+
+def expm_potential(V: np.ndarray, tau: float, hbar: float = 1.0) -> np.ndarray:
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    S = V.shape[0]
+    U = np.zeros((S, S), dtype=np.complex128)
+    lib().orc_expm_potential(S, _dp(V), tau, hbar, _dp(U.view(np.float64)))
+    return U
+
+
+def eigh(A: np.ndarray):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    lam = np.zeros(n)
+    R = np.zeros((n, n))
+    lib().orc_eigh(n, _dp(A), _dp(lam), _dp(R))
+    return lam, R
+
+
+def propagate(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: int,
+              dt: float, nsteps: int, pruned: bool = True) -> np.ndarray:
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    rc = lib().orc_propagate(prob.ptr(), split, scheme, order, float(dt), int(nsteps),
+                             int(pruned), _dp(a.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle propagate rejected its arguments")
+    return a
+
+
+def action(prob: Problem, psi: np.ndarray, op: str, tau: float) -> np.ndarray:
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    rc = lib().orc_action(prob.ptr(), 0 if op == "V" else 1, float(tau), _dp(a.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle action rejected its arguments")
+    return a
+
+
+def observables(prob: Problem, psi: np.ndarray) -> dict:
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape)
+    out = np.zeros(4 + prob.nsurf)
+    if lib().orc_observables(prob.ptr(), _dp(a.view(np.float64)), _dp(out)) != 0:
+        raise ValueError("oracle observables rejected its arguments")
+    S = prob.nsurf
+    return {"norm": out[0], "energy": out[1], "pops": out[2:2 + S].copy(),
+            "kinetic": out[2 + S], "potential": out[3 + S]}
+
+
+def overlap(prob: Problem, psi: np.ndarray, phi: np.ndarray) -> complex:
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape)
+    b = np.ascontiguousarray(phi, dtype=np.complex128).reshape(prob.shape)
+    out = np.zeros(2)
+    lib().orc_overlap(prob.ptr(), _dp(a.view(np.float64)), _dp(b.view(np.float64)), _dp(out))
+    return complex(out[0], out[1])
+
+
+def exact(prob: Problem, psi: np.ndarray, t: float) -> np.ndarray:
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    if lib().orc_exact(prob.ptr(), float(t), _dp(a.view(np.float64))) != 0:
+        raise ValueError("grid too large for the dense exact propagator")
+    return a
+
+
+def l2(prob: Problem, psi: np.ndarray) -> float:
+    """L2 norm with the volume element."""
+    dV = float(np.prod([(h - l) / n for n, l, h in zip(prob.n, prob.lo, prob.hi)]))
+    return float(np.sqrt(np.sum(np.abs(psi) ** 2) * dV))

@@ -1,0 +1,283 @@
+"""Pins of the oracle's propagator, observables and brute-force exact evolution.
+
+Independent references used here (none of them calls the oracle's own
+arithmetic):
+  * the dense discrete Hamiltonian H = K (x) 1_S + blockdiag V(x) built with
+    numpy's FFT, exponentiated by scipy.linalg.expm (Eq. exact_evol_op);
+  * the free Gaussian in closed form (V = 0);
+  * for an x-independent coupled potential V0, exp(-i V0 t) times free
+    evolution (T and V commute, so every splitting is exact);
+  * closed-form energies of Gaussian initial states;
+  * invariants the paper states (Sec. "Geometric properties of the exact
+    evolution operator", Appendix A): norm, symplectic form, time
+    reversibility of the symmetric compositions, and global errors
+    O(dt^p) for the orders of Table I.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_1903_04946_amd import synth
+
+
+def problem(orc, m):
+    return orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
+
+
+def dense_h(m):
+    """Dense discrete Hamiltonian, kinetic part via numpy's FFT."""
+    ndim = len(m.n)
+    npts = m.npts
+    Ktot = np.zeros((npts, npts), dtype=complex)
+    for d in range(ndim):
+        n = m.n[d]
+        p = 2 * np.pi * np.fft.fftfreq(n, d=m.dx[d]) * m.hbar
+        T = 0.5 * m.inv_mass[d] * p**2
+        Kd = np.fft.ifft(T[:, None] * np.fft.fft(np.eye(n), axis=0), axis=0)
+        mats = [np.eye(k) for k in m.n]
+        mats[d] = Kd
+        K = mats[0]
+        for M in mats[1:]:
+            K = np.kron(K, M)
+        Ktot += K
+    S = m.nsurf
+    H = np.kron(np.eye(S), Ktot)
+    for i in range(S):
+        for j in range(S):
+            v = m.vtable[synth.packed_index(S, i, j)]
+            H[i * npts:(i + 1) * npts, j * npts:(j + 1) * npts] += np.diag(v)
+    return H
+
+
+def exact_scipy(m, psi, t):
+    H = dense_h(m)
+    return (scipy.linalg.expm(-1j * t * H / m.hbar) @ psi.ravel()).reshape(psi.shape)
+
+
+def l2(m, a):
+    return float(np.sqrt(np.sum(np.abs(a) ** 2) * m.dV))
+
+
+# ------------------------------------------------------------------ brute force
+@pytest.mark.parametrize("n,S", [([16], 2), ([12], 2), ([4, 4, 4], 3), ([6, 4], 2)])
+def test_exact_vs_scipy_expm(orc, n, S):
+    m = synth.random_small(n, S, seed=7)
+    P = problem(orc, m)
+    for t in (0.3, 2.0):
+        ref = exact_scipy(m, m.psi0, t)
+        got = orc.exact(P, m.psi0, t)
+        assert l2(m, got - ref) < 1e-12
+
+
+# ------------------------------------------------------------------ orders
+# (split, scheme, order, model seed, t_f, k range for dt = 2 t_f / 2^(k+1), tolerance).
+# The k ranges sit in the asymptotic window above the FP64 round-off floor
+# (about 1e-12 here); orders 8 and 10 reach that floor within a few halvings,
+# as the paper observes for its own runs (Sec. "One-dimensional model of NaI").
+SLOPE_CASES = [
+    ("VT", 0, 1, 3, 4.0, range(3, 8), 0.35),
+    ("TV", 0, 1, 3, 4.0, range(3, 8), 0.35),
+    ("VTV", 0, 2, 3, 4.0, range(2, 8), 0.35),
+    ("TVT", 0, 2, 3, 4.0, range(2, 8), 0.35),
+    ("VTV", 1, 4, 3, 4.0, range(2, 8), 0.35),
+    ("VTV", 2, 4, 3, 4.0, range(3, 8), 0.35),
+    ("VTV", 1, 6, 3, 4.0, range(2, 7), 0.5),
+    ("TVT", 1, 6, 3, 4.0, range(2, 7), 0.5),
+    ("VTV", 2, 6, 3, 4.0, range(1, 6), 0.75),
+    ("VTV", 1, 8, 5, 2.0, range(4, 8), 0.5),
+    ("VTV", 2, 8, 5, 2.0, range(1, 5), 1.0),
+    ("VTV", 1, 10, 5, 2.0, range(4, 7), 1.0),
+]
+
+
+def fitted_slope(dts, errs, floor=1e-11):
+    dts = np.asarray(dts)
+    errs = np.asarray(errs)
+    sel = errs > floor
+    assert sel.sum() >= 3, (dts, errs)
+    return np.polyfit(np.log(dts[sel]), np.log(errs[sel]), 1)[0]
+
+
+@pytest.mark.parametrize("case", SLOPE_CASES, ids=lambda c: f"{c[0]}-{c[1]}-{c[2]}")
+def test_convergence_order_vs_exact(orc, case):
+    split_name, scheme, order, seed, tf, ks, tol = case
+    split = getattr(orc, split_name)
+    if seed == 3:
+        m = synth.random_small([16], 2, seed=3, lo=-5, hi=5, coupling=0.5)
+    else:
+        m = synth.random_small([12], 2, seed=5, lo=-4, hi=4, coupling=0.3)
+    P = problem(orc, m)
+    ref = exact_scipy(m, m.psi0, tf)
+    dts, errs = [], []
+    for k in ks:
+        nsteps = 2**k if seed != 3 else int(round(tf / (2.0 / 2**k)))
+        dts.append(tf / nsteps)
+        psi = orc.propagate(P, m.psi0, split, scheme, order, tf / nsteps, nsteps)
+        errs.append(l2(m, psi - ref))
+    slope = fitted_slope(dts, errs)
+    assert abs(slope - order) < tol, (slope, errs)
+
+
+def test_convergence_order_3d(orc):
+    m = synth.random_small([4, 4, 4], 3, seed=11, lo=-3, hi=3, coupling=0.4)
+    P = problem(orc, m)
+    tf = 2.0
+    ref = orc.exact(P, m.psi0, tf)
+    for scheme, order, dts in [(0, 2, [0.1, 0.05, 0.025, 0.0125]),
+                               (1, 4, [0.5, 0.25, 0.125, 0.0625])]:
+        errs = []
+        for dt in dts:
+            ns = int(round(tf / dt))
+            errs.append(l2(m, orc.propagate(P, m.psi0, orc.VTV, scheme, order, tf / ns, ns) - ref))
+        assert abs(fitted_slope(dts, errs) - order) < 0.35, errs
+
+
+# ------------------------------------------------------------------ special cases
+def test_free_gaussian_closed_form(orc):
+    n, lo, hi = 256, -20.0, 20.0
+    x = lo + np.arange(n) * (hi - lo) / n
+    sigma, x0, p0, mass, t = 1.0, -1.5, 1.2, 1.7, 2.0
+    psi0 = np.zeros((1, n), complex)
+    psi0[0] = synth.gaussian_1d(x, x0, p0, sigma)
+    P = orc.Problem([n], [lo], [hi], 1, [1 / mass], np.zeros((1, n)))
+    s2 = sigma**2 + 1j * t / mass
+    ref = ((np.pi * sigma**2) ** -0.25 * sigma / np.sqrt(s2) *
+           np.exp(-(x - x0 - p0 * t / mass) ** 2 / (2 * s2) + 1j * p0 * (x - x0)
+                  - 1j * p0**2 * t / (2 * mass)))
+    for scheme, order, dt in [(0, 2, 0.5), (1, 4, 1.0), (2, 6, 2.0)]:
+        ns = int(round(t / dt))
+        got = orc.propagate(P, psi0, orc.VTV, scheme, order, t / ns, ns)
+        assert np.max(np.abs(got[0] - ref)) < 1e-12
+
+
+def test_constant_coupled_potential_is_exact(orc):
+    # V(x) = V0 for all x: T and V commute and every splitting is exact.
+    n, lo, hi = 64, -8.0, 8.0
+    V0 = np.array([[0.3, 0.2, -0.1], [0.2, -0.4, 0.15], [-0.1, 0.15, 0.05]])
+    S = 3
+    vt = np.zeros((6, n))
+    for i in range(S):
+        for j in range(i, S):
+            vt[synth.packed_index(S, i, j)] = V0[i, j]
+    x = lo + np.arange(n) * (hi - lo) / n
+    rng = np.random.default_rng(5)
+    psi0 = np.zeros((S, n), complex)
+    for s in range(S):
+        psi0[s] = synth.gaussian_1d(x, rng.uniform(-1, 1), rng.uniform(-1, 1), 1.0) * rng.uniform(0.2, 1)
+    P = orc.Problem([n], [lo], [hi], S, [0.8], vt)
+    t = 3.0
+    p = 2 * np.pi * np.fft.fftfreq(n, d=(hi - lo) / n)
+    free = np.fft.ifft(np.exp(-1j * t * 0.5 * 0.8 * p**2) * np.fft.fft(psi0, axis=1), axis=1)
+    ref = scipy.linalg.expm(-1j * t * V0) @ free
+    for split, scheme, order, dt in [(orc.VT, 0, 1, 1.0), (orc.VTV, 0, 2, 1.5), (orc.TVT, 1, 4, 3.0),
+                                     (orc.VTV, 2, 6, 1.0)]:
+        ns = int(round(t / dt))
+        got = orc.propagate(P, psi0, split, scheme, order, t / ns, ns)
+        assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_diagonal_potential_decouples(orc):
+    m = synth.random_small([32], 2, seed=9, coupling=0.0)
+    m.psi0[1] = np.roll(m.psi0[0], 5) * 0.5
+    P = problem(orc, m)
+    both = orc.propagate(P, m.psi0, orc.VTV, 1, 4, 0.1, 20)
+    for s in range(2):
+        Ps = orc.Problem(m.n, m.lo, m.hi, 1, m.inv_mass,
+                         m.vtable[synth.packed_index(2, s, s)][None, :])
+        one = orc.propagate(Ps, m.psi0[s:s + 1], orc.VTV, 1, 4, 0.1, 20)
+        assert np.max(np.abs(one[0] - both[s])) < 1e-15
+
+
+def test_zero_steps_identity(orc):
+    m = synth.random_small([16], 2, seed=1)
+    P = problem(orc, m)
+    np.testing.assert_array_equal(orc.propagate(P, m.psi0, orc.VTV, 1, 6, 0.1, 0), m.psi0)
+
+
+def test_pruned_equals_unpruned(orc):
+    m = synth.two_surface_1d(n=256)
+    P = problem(orc, m)
+    for scheme, order in [(1, 4), (2, 4), (1, 6), (2, 6)]:
+        a = orc.propagate(P, m.psi0, orc.VTV, scheme, order, 0.05, 20, pruned=True)
+        b = orc.propagate(P, m.psi0, orc.VTV, scheme, order, 0.05, 20, pruned=False)
+        assert l2(m, a - b) < 1e-13
+
+
+def test_lvc_ground_surface_stays_empty(orc):
+    m = synth.lvc_3d(n=16)
+    P = problem(orc, m)
+    psi = orc.propagate(P, m.psi0, orc.VTV, 1, 4, 10.0, 3)
+    assert np.all(psi[0] == 0)
+    assert abs(orc.observables(P, psi)["norm"] - 1) < 1e-13
+
+
+# ------------------------------------------------------------------ observables
+def test_initial_energy_closed_form_1d(orc):
+    # Gaussian of width 1/sqrt(2) at x0 = -2 on V11 = (x+1)^2/2:
+    # <T> = 1/(4 sigma^2) = 1/2, <V> = ((x0+1)^2 + sigma^2/2)/2 = 5/8.
+    m = synth.two_surface_1d()
+    ob = orc.observables(problem(orc, m), m.psi0)
+    assert abs(ob["norm"] - 1) < 1e-14
+    assert abs(ob["kinetic"] - 0.5) < 1e-13
+    assert abs(ob["potential"] - 0.625) < 1e-13
+    assert abs(ob["energy"] - 1.125) < 1e-13
+    np.testing.assert_allclose(ob["pops"], [1.0, 0.0], atol=1e-14)
+
+
+def test_initial_energy_closed_form_lvc(orc):
+    m = synth.lvc_3d(n=32)
+    ob = orc.observables(problem(orc, m), m.psi0)
+    om, E, _ = synth.lvc_parameters(1903)
+    ref = (E[2] + om.sum() / 2) / synth.EV_PER_HARTREE
+    assert abs(ob["energy"] - ref) < 1e-12
+    np.testing.assert_allclose(ob["pops"], [0, 0, 1], atol=1e-14)
+
+
+def test_overlap_matches_numpy(orc):
+    m = synth.random_small([8, 8], 2, seed=4)
+    P = problem(orc, m)
+    phi = synth.random_state(m.psi0.shape, 6, m.dV)
+    ref = np.vdot(m.psi0.ravel(), phi.ravel()) * m.dV
+    assert abs(orc.overlap(P, m.psi0, phi) - ref) < 1e-14
+
+
+# ------------------------------------------------------------------ invariants
+def test_geometric_invariants_1d(orc):
+    """Norm, symplectic form and time reversibility (Fig. 8 analogue)."""
+    m = synth.two_surface_1d(n=512)
+    P = problem(orc, m)
+    x = m.axes()[0]
+    phi = np.zeros_like(m.psi0)
+    phi[0] = synth.gaussian_1d(x, -1.0, 1.0, m.meta["sigma"])
+    phi = synth.normalise(phi, m.dV)
+    w0 = -2 * orc.overlap(P, m.psi0, phi).imag
+    for split, scheme, order in [(orc.VTV, 0, 2), (orc.TVT, 0, 2), (orc.VTV, 1, 4), (orc.VTV, 2, 6)]:
+        psi = orc.propagate(P, m.psi0, split, scheme, order, 0.02, 100)
+        ph = orc.propagate(P, phi, split, scheme, order, 0.02, 100)
+        assert abs(orc.observables(P, psi)["norm"] - 1) < 1e-12
+        assert abs(-2 * orc.overlap(P, psi, ph).imag - w0) < 1e-12
+        back = orc.propagate(P, psi, split, scheme, order, -0.02, 100)
+        assert l2(m, back - m.psi0) < 1e-12
+    # the first-order splitting is not time-reversible (Table I)
+    psi = orc.propagate(P, m.psi0, orc.VT, 0, 1, 0.02, 100)
+    assert abs(orc.observables(P, psi)["norm"] - 1) < 1e-12
+    back = orc.propagate(P, psi, orc.VT, 0, 1, -0.02, 100)
+    assert l2(m, back - m.psi0) > 1e-4
+
+
+@pytest.mark.parametrize("scheme,order", [(0, 2), (2, 4), (2, 6)])
+def test_energy_error_follows_order(orc, scheme, order):
+    """Energy is not conserved exactly; its error shrinks as dt^p (Fig. 9)."""
+    m = synth.random_small([32], 2, seed=21, lo=-6, hi=6, coupling=0.5)
+    P = problem(orc, m)
+    e0 = orc.observables(P, m.psi0)["energy"]
+    tf = 2.0
+    dts = {2: [0.1 / 2**k for k in range(6)], 4: [0.5 / 2**k for k in range(6)],
+           6: [2.0 / 2**k for k in range(5)]}[order]
+    errs = []
+    for dt in dts:
+        ns = int(round(tf / dt))
+        psi = orc.propagate(P, m.psi0, orc.VTV, scheme, order, tf / ns, ns)
+        errs.append(abs(orc.observables(P, psi)["energy"] - e0))
+    assert errs[0] > 1e-10  # not conserved
+    assert abs(fitted_slope(dts, errs, floor=1e-12) - order) < 0.5, errs
