@@ -1,0 +1,185 @@
+/*
+ * soprop.h -- C ABI of libsoprop, a gfx950 (MI355X) implementation of the
+ * composed split-operator propagator for a separable diabatic Hamiltonian
+ * H = T(p) + V(q) (Roulet, Choi, Vanicek, arXiv:1903.04946).
+ *
+ * One time step is the pruned splitting sequence
+ *     U(dt) = U_B(b_N dt) U_A(a_N dt) ... U_B(b_1 dt) U_A(a_1 dt)
+ * (Sec. "Compositions of split-operator algorithms") of a recursive
+ * symmetric composition -- triple jump or Suzuki's fractal -- of the
+ * second-order VTV or TVT algorithm (Eqs. so_VTV, so_TVT, second_order_so;
+ * Sec. "Symmetric composition schemes"), after pruning zero coefficients and
+ * merging neighbouring A actions (Eq. merging_splitting_coeff_b_zero), with
+ * one stored evolution-operator table per unique coefficient and integer
+ * index arrays into them (Eq. range_index_unq, Table II).  Each kinetic action
+ * is forward FFT -> phase exp(-i tau T(p)/hbar) -> inverse FFT, each potential
+ * action the S x S unitary exp(-i tau V(q)/hbar) at every grid point
+ * (Sec. "Dynamic Fourier method", Eq. diab_mol_ham), obtained from a Jacobi
+ * eigen-decomposition of V(q) (Sec. "Molecular Hamiltonian in the diabatic
+ * basis").
+ *
+ * Conventions
+ *   - Units: any consistent set; hbar is a plan parameter (1 in atomic units).
+ *   - Grid: ndim in {1, 3}; periodic box [lo_d, hi_d), n_d points,
+ *     dx_d = (hi_d - lo_d)/n_d.  Momenta p = hbar * 2 pi k'/(n_d dx_d) with
+ *     k' = k for k < n_d/2 and k - n_d otherwise.
+ *   - Wavefunction psi: caller-owned DEVICE memory, C-contiguous
+ *     [nsurf][n_0]..[n_{ndim-1}] (last axis fastest), interleaved complex
+ *     (complex128 for SOP_C128 plans, complex64 for SOP_C64 plans).
+ *   - V-table: caller-owned HOST memory, double, the packed upper triangle of
+ *     the real symmetric S x S potential per grid point in the order
+ *     V00, V01, .., V0,S-1, V11, V12, .., VS-1,S-1; array
+ *     [nsurf*(nsurf+1)/2][npts], points flattened like psi.  The library
+ *     copies it; the caller may free it after sop_plan_create returns.
+ *   - Kinetic energy T(p) = sum_d inv_mass[d] p_d^2 / 2.
+ *
+ * Streams and synchronisation
+ *   All device work is enqueued on the HIP stream given at plan creation
+ *   (NULL = the default stream).  sop_propagate is asynchronous.
+ *   sop_plan_create, sop_observables and sop_overlap synchronise the stream
+ *   before returning.
+ *
+ * Errors
+ *   Every call returns a sop_status.  Arguments are validated before any
+ *   device work: on SOP_ERR_INVALID or SOP_ERR_UNSUPPORTED nothing is
+ *   touched.  On SOP_ERR_HIP the HIP error text is available from
+ *   sop_last_error() and psi is undefined.  Out-parameters are written only
+ *   on SOP_OK.  A plan is not thread-safe; distinct plans are.
+ */
+#ifndef SOPROP_H
+#define SOPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOP_ABI_VERSION 1
+
+typedef enum {
+  SOP_OK = 0,
+  SOP_ERR_INVALID = 1,     /* malformed argument (null pointer, bad size, ...) */
+  SOP_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. a grid length)  */
+  SOP_ERR_NOMEM = 3,       /* device allocation failed                        */
+  SOP_ERR_HIP = 4,         /* a HIP runtime call failed                       */
+  SOP_ERR_STATE = 5        /* call not allowed in the plan's current state    */
+} sop_status;
+
+/* Elementary splitting (Eqs. so_VT, so_TV, so_VTV, so_TVT).  A is the
+ * operator applied first: VTV and TV apply V first, TVT and VT apply T
+ * first.  VT/TV are first order and take no composition (order 1). */
+typedef enum { SOP_SPLIT_VTV = 0, SOP_SPLIT_TVT = 1, SOP_SPLIT_VT = 2, SOP_SPLIT_TV = 3 } sop_split;
+
+/* Composition scheme (Sec. "Symmetric composition schemes"): Strang (the
+ * bare second-order method, order 2), recursive triple jump (M = 3^n Strang
+ * stages for order 2(n+1)) or Suzuki's fractal (M = 5^n). */
+typedef enum { SOP_COMP_STRANG = 0, SOP_COMP_TRIPLE_JUMP = 1, SOP_COMP_SUZUKI = 2 } sop_comp;
+
+typedef enum { SOP_C128 = 0, SOP_C64 = 1 } sop_dtype;
+
+typedef struct {
+  int ndim;        /* 1 or 3 */
+  int n[3];        /* points per axis; supported lengths listed by sop_supported_length */
+  double lo[3];
+  double hi[3];
+} sop_grid;
+
+typedef struct {
+  sop_grid grid;
+  int nsurf;              /* S, 1..3 for ndim = 3, 1..4 for ndim = 1 */
+  const double* inv_mass; /* [ndim] host, 1/m_d (Eq. diab_mol_ham, diagonal mass matrix) */
+  const double* vtable;   /* host, packed upper triangle, see above */
+  sop_split split;
+  sop_comp comp;
+  int order;              /* 1 for VT/TV; 2 (Strang) or 4, 6, 8, 10 */
+  double dt;              /* time step, nonzero, finite */
+  double hbar;            /* > 0 */
+  sop_dtype dtype;
+} sop_plan_desc;
+
+/* Sizes of a plan (Table II quantities for its scheme and order). */
+typedef struct {
+  int M;          /* Strang stages per step = number of B actions N_B       */
+  int n_a;        /* A actions per step after pruning (M+1; 1 for VT/TV)    */
+  int n_b;        /* B actions per step                                     */
+  int n_a_unq;    /* unique A coefficients                                  */
+  int n_b_unq;    /* unique B coefficients                                  */
+  int n_v_tables; /* stored potential tables  (= n_a_unq if A = V)          */
+  int n_t_tables; /* stored kinetic factor sets                             */
+  int64_t npts;
+  size_t table_bytes;   /* device bytes of stored evolution operators      */
+  size_t scratch_bytes; /* device bytes of observables scratch             */
+} sop_plan_info;
+
+typedef struct sop_plan sop_plan;
+
+/* ABI version (SOP_ABI_VERSION of the built library). */
+int sop_abi_version(void);
+
+/* Static text for a status code. */
+const char* sop_status_string(sop_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* sop_last_error(void);
+
+/* 1 if a grid length n is supported on a 1D (ndim = 1) or 3D axis. */
+int sop_supported_length(int ndim, int n);
+
+/* Composition coefficients and the pruned, deduplicated sequence, computed
+ * on the host only (no device needed).  Sec. "Symmetric composition schemes",
+ * Sec. "Pruning splitting coefficients", Eq. range_index_unq.
+ *   a, b        : [cap] out, the pruned sequence (a_1..a_N, b_1..b_N; the
+ *                 trailing b_N = 0 of a composed method is included)
+ *   a_unq, b_unq: [cap] out, the unique nonzero values (first occurrence)
+ *   ia, ib      : [cap] out, 0-based indices into a_unq/b_unq; ib = -1 where b = 0
+ *   counts      : [4] out = {N, n_a_unq, n_b_unq, M}
+ * Any array pointer may be NULL to skip it.  SOP_ERR_INVALID if cap < N. */
+sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int cap, double* a,
+                               double* b, double* a_unq, double* b_unq, int* ia, int* ib,
+                               int* counts);
+
+/* Builds a plan: validates, computes the sequence on the host, uploads the
+ * V-table and forms the unique potential tables exp(-i c dt V/hbar) on the
+ * device (FP64 formation, rounded once to complex64 for SOP_C64 plans), plus
+ * per-axis kinetic factors and FFT twiddles.  hip_stream: a hipStream_t or
+ * NULL.  Synchronises the stream.  *out receives the plan. */
+sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out);
+
+/* Frees the plan's device memory.  NULL is accepted. */
+sop_status sop_plan_destroy(sop_plan* plan);
+
+sop_status sop_plan_info_get(const sop_plan* plan, sop_plan_info* out);
+
+/* Rebinds the plan to another stream (NULL = default). */
+sop_status sop_plan_set_stream(sop_plan* plan, void* hip_stream);
+
+/* psi <- U(direction * dt)^nsteps psi, in place, on the plan's stream.
+ * direction = -1 applies the same sequence with every table conjugated,
+ * i.e. U(-dt) (time reversal; Sec. "Geometric properties of the exact
+ * evolution operator").  nsteps = 0 is a no-op.  Asynchronous. */
+sop_status sop_propagate(sop_plan* plan, void* psi_dev, int64_t nsteps, int direction);
+
+/* Observables of psi in FP64 (Sec. "Geometric properties of the exact
+ * evolution operator"): out[0] = <psi|psi>, out[1] = <psi|H|psi>,
+ * out[2+s] = population of surface s (s < nsurf), out[2+S] = <T>,
+ * out[3+S] = <V>.  Inner products carry the volume element.  <T> is taken
+ * in the momentum representation from an FFT of a scratch copy; psi is not
+ * modified.  out must hold 4 + nsurf doubles (host).  Synchronises. */
+sop_status sop_observables(sop_plan* plan, const void* psi_dev, double* out);
+
+/* <psi|phi> with the volume element; out[0] = Re, out[1] = Im (host).
+ * The symplectic two-form is -2 hbar Im<psi|phi>.  Synchronises. */
+sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev, double* out);
+
+/* Applies one action to psi (testing aid; asynchronous): op = 0 potential
+ * exp(-i tau V/hbar) with tau = coef * dt, op = 1 kinetic exp(-i tau T/hbar).
+ * The table for coef is formed on the fly into the plan's scratch. */
+sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOPROP_H */

@@ -626,32 +626,34 @@ int orc_observables(const orc_problem* prob, const double* psi_in, double* out) 
   if (!make_grid(prob, g) || !prob->vtable) return -1;
   const int S = g.S;
   const cd* psi = reinterpret_cast<const cd*>(psi_in);
+  // Sums over up to ~1e7 grid points accumulate in long double so that the
+  // reduction itself stays far below the 1e-12 invariant errors of interest.
   std::vector<double> pop(S, 0.0);
-  double ev = 0.0;
   for (int s = 0; s < S; ++s) {
-    double acc = 0;
-    for (int64_t x = 0; x < g.npts; ++x) acc += std::norm(psi[s * g.npts + x]);
-    pop[s] = acc * g.dV;
+    ld acc = 0;
+    for (int64_t x = 0; x < g.npts; ++x) acc += (ld)std::norm(psi[s * g.npts + x]);
+    pop[s] = (double)(acc * (ld)g.dV);
   }
+  ld evl = 0;
   for (int64_t x = 0; x < g.npts; ++x) {
     for (int i = 0; i < S; ++i)
       for (int j = 0; j < S; ++j) {
         double v = prob->vtable[(int64_t)packed_index(S, i, j) * g.npts + x];
-        ev += (std::conj(psi[i * g.npts + x]) * v * psi[j * g.npts + x]).real();
+        evl += (ld)(std::conj(psi[i * g.npts + x]) * v * psi[j * g.npts + x]).real();
       }
   }
-  ev *= g.dV;
+  const double ev = (double)(evl * (ld)g.dV);
   std::vector<cd> tmp(psi, psi + (size_t)S * g.npts);
   fft_state(g, tmp.data(), false);
-  double et = 0.0;
+  ld etl = 0;
   for (int64_t k = 0; k < g.npts; ++k) {
     double t = kinetic_energy_at(g, k);
-    for (int s = 0; s < S; ++s) et += t * std::norm(tmp[s * g.npts + k]);
+    for (int s = 0; s < S; ++s) etl += (ld)(t * std::norm(tmp[s * g.npts + k]));
   }
-  et *= g.dV / (double)g.npts;
-  double norm = 0;
-  for (int s = 0; s < S; ++s) norm += pop[s];
-  out[0] = norm;
+  const double et = (double)(etl * (ld)g.dV / (ld)g.npts);
+  ld norm = 0;
+  for (int s = 0; s < S; ++s) norm += (ld)pop[s];
+  out[0] = (double)norm;
   out[1] = et + ev;
   for (int s = 0; s < S; ++s) out[2 + s] = pop[s];
   out[2 + S] = et;
@@ -666,11 +668,14 @@ int orc_overlap(const orc_problem* prob, const double* psi_in, const double* phi
   if (!make_grid(prob, g)) return -1;
   const cd* psi = reinterpret_cast<const cd*>(psi_in);
   const cd* phi = reinterpret_cast<const cd*>(phi_in);
-  cd acc(0, 0);
-  for (int64_t i = 0; i < (int64_t)g.S * g.npts; ++i) acc += std::conj(psi[i]) * phi[i];
-  acc *= g.dV;
-  out[0] = acc.real();
-  out[1] = acc.imag();
+  ld re = 0, im = 0;
+  for (int64_t i = 0; i < (int64_t)g.S * g.npts; ++i) {
+    cd z = std::conj(psi[i]) * phi[i];
+    re += (ld)z.real();
+    im += (ld)z.imag();
+  }
+  out[0] = (double)(re * (ld)g.dV);
+  out[1] = (double)(im * (ld)g.dV);
   return 0;
 }
 

@@ -1,0 +1,290 @@
+// fft_core.hpp -- register/LDS Stockham FFT building blocks for gfx950.
+//
+// A pencil of length N is held by N/E threads, E complex values each.  A
+// stage of radix R with sub-transform length L (product of the earlier
+// radices) lets thread t own the butterflies j = t + (N/E) b, b < E/R; the
+// inputs of butterfly j are the elements j + m N/R (m < R), its twiddles are
+// exp(-+2 pi i k m/(L R)) with k = j mod L, and its outputs land at
+// (j - k) R + k + m L (Stockham auto-sort: natural order in and out, no bit
+// reversal).  Between stages the values go through LDS; after the last
+// stage thread t owns exactly the elements of a radix-R_last first stage, so
+// a forward transform (radices R_1..R_k) followed by an inverse one with the
+// radices reversed (R_k..R_1) needs no exchange at the turn, and pointwise
+// work (the kinetic phase, the potential matvec) happens in registers.
+//
+// The transforms are the unnormalised DFTs of the dynamic Fourier method
+// (Sec. "Dynamic Fourier method"): forward exp(-2 pi i jk/N), inverse
+// exp(+2 pi i jk/N); the 1/N of the inverse is folded into the kinetic
+// factors by the planner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sop {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+  if (INV) return {-a.im, a.re};
+  return {a.im, -a.re};
+}
+
+// ----------------------------------------------------------------- radix DFTs
+template <typename T>
+struct K {
+  static constexpr T r2 = (T)0.70710678118654752440084436210484903928;   // cos(pi/4)
+  static constexpr T c8 = (T)0.92387953251128675612818318939678828682;   // cos(pi/8)
+  static constexpr T s8 = (T)0.38268343236508977172845998403039886676;   // sin(pi/8)
+  static constexpr T s3 = (T)0.86602540378443864676372317075293618347;   // sin(pi/3)
+};
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+  // y0 = x0 + x1 + x2; y1,2 = x0 - (x1+x2)/2 -+ i sin(pi/3) (x1 - x2) (forward)
+  cx<T> s = cadd(v[1], v[2]);
+  cx<T> d = csub(v[1], v[2]);
+  cx<T> h = {v[0].re - (T)0.5 * s.re, v[0].im - (T)0.5 * s.im};
+  cx<T> e = mul_mi<INV>(cx<T>{d.re * K<T>::s3, d.im * K<T>::s3});
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(h, e);
+  v[2] = csub(h, e);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  cx<T> c = cadd(v[1], v[3]), d = mul_mi<INV>(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+// x * exp(-+ i pi/4)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> w8_1(cx<T> a) {
+  const T r = K<T>::r2;
+  if (INV) return {(a.re - a.im) * r, (a.re + a.im) * r};
+  return {(a.re + a.im) * r, (a.im - a.re) * r};
+}
+// x * exp(-+ 3 i pi/4)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> w8_3(cx<T> a) {
+  const T r = K<T>::r2;
+  if (INV) return {-(a.re + a.im) * r, (a.re - a.im) * r};
+  return {(a.im - a.re) * r, -(a.re + a.im) * r};
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  o[1] = w8_1<INV>(o[1]);
+  o[2] = mul_mi<INV>(o[2]);
+  o[3] = w8_3<INV>(o[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  cx<T> e[8], o[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e[k] = v[2 * k];
+    o[k] = v[2 * k + 1];
+  }
+  dft8<INV>(e);
+  dft8<INV>(o);
+  const T c = K<T>::c8, s = K<T>::s8;
+  const T sg = INV ? (T)1 : (T)-1;  // sign of the imaginary part of the twiddle
+  // o[k] *= exp(sg * i * 2 pi k / 16), k = 1..7
+  o[1] = cmul(o[1], cx<T>{c, sg * s});
+  o[2] = w8_1<INV>(o[2]);
+  o[3] = cmul(o[3], cx<T>{s, sg * c});
+  o[4] = mul_mi<INV>(o[4]);
+  o[5] = cmul(o[5], cx<T>{-s, sg * c});
+  o[6] = w8_3<INV>(o[6]);
+  o[7] = cmul(o[7], cx<T>{-c, sg * s});
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 8] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else if constexpr (R == 16) dft16<INV>(v);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ----------------------------------------------------------------- schedules
+template <int... Rs>
+struct RList {};
+
+template <int R, int... Rs>
+struct RHead {
+  static constexpr int value = R;
+};
+
+// A pencil schedule: length N, E elements per thread, forward radices Fwd and
+// inverse radices Inv = reverse(Fwd).
+template <int N_, int E_, class Fwd_, class Inv_, int RF_, int RL_>
+struct Sched {
+  static constexpr int N = N_;
+  static constexpr int E = E_;
+  static constexpr int TPC = N_ / E_;  // threads per pencil
+  static constexpr int RF = RF_;       // first forward radix (= last inverse radix)
+  static constexpr int RL = RL_;       // last forward radix (= first inverse radix)
+  using Fwd = Fwd_;
+  using Inv = Inv_;
+};
+
+// Element index owned by thread t in register slot `slot` for a radix-R stage.
+template <int N, int E, int R>
+__device__ __forceinline__ int own_idx(int t, int slot) {
+  const int b = slot / R, m = slot % R;
+  return t + (N / E) * b + m * (N / R);
+}
+
+// ----------------------------------------------------------------- LDS layouts
+// Pencil-fastest layout: offset = base + p * pstride + e * estride
+struct LayStrided {
+  int base, pstride, estride;
+  __device__ __forceinline__ int off(int p, int e) const { return base + p * pstride + e * estride; }
+};
+// Element-fastest layout with one padding slot per 16 elements:
+// offset = base + p * pstride + e + e/16
+struct LayPadded {
+  int base, pstride;
+  __device__ __forceinline__ int off(int p, int e) const { return base + p * pstride + e + (e >> 4); }
+};
+
+// ----------------------------------------------------------------- stages
+template <typename T, int N, int E, int R, int L, bool INV>
+__device__ __forceinline__ void stage(cx<T> (&v)[E], int t, const cx<T>* __restrict__ tw) {
+  constexpr int TPC = N / E;
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    if constexpr (L > 1) {
+      const int j = t + TPC * b;
+      const int k = j % L;
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        cx<T> w = tw[(k * m) * (N / (L * R))];
+        if (INV) w.im = -w.im;
+        v[b * R + m] = cmul(v[b * R + m], w);
+      }
+    }
+    dft<R, INV>(&v[b * R]);
+  }
+}
+
+// Writes the outputs of a (R, L) stage to LDS and reads the inputs of the
+// next stage (radix R2).  All P pencils of the thread go through together.
+template <typename T, int N, int E, int R, int L, int R2, int P, class Lay>
+__device__ __forceinline__ void exchange(cx<T> (*v)[E], cx<T>* lds, const Lay& lay, int t) {
+  constexpr int TPC = N / E;
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    const int j = t + TPC * b;
+    const int k = j % L;
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lay.off(p, base + m * L)] = v[p][b * R + m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < E / R2; ++b) {
+    const int j = t + TPC * b;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int m = 0; m < R2; ++m) v[p][b * R2 + m] = lds[lay.off(p, j + m * (N / R2))];
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int E, bool INV, int L, int P, class Lay, int R, int... Rest>
+__device__ __forceinline__ void run_stages(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
+                                           const cx<T>* __restrict__ tw, int t, RList<R, Rest...>) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) stage<T, N, E, R, L, INV>(v[p], t, tw);
+  if constexpr (sizeof...(Rest) > 0) {
+    constexpr int R2 = RHead<Rest...>::value;
+    exchange<T, N, E, R, L, R2, P>(v, lds, lay, t);
+    run_stages<T, N, E, INV, L * R, P, Lay>(v, lds, lay, tw, t, RList<Rest...>{});
+  }
+}
+
+// Forward transform of P pencils v[0..P-1]: input in radix-RF ownership,
+// output in radix-RL ownership.
+template <class SC, int P, typename T, class Lay>
+__device__ __forceinline__ void fft_forward(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                            const cx<T>* __restrict__ tw, int t) {
+  run_stages<T, SC::N, SC::E, false, 1, P, Lay>(v, lds, lay, tw, t, typename SC::Fwd{});
+}
+// Inverse transform: input in radix-RL ownership, output in radix-RF ownership.
+template <class SC, int P, typename T, class Lay>
+__device__ __forceinline__ void fft_inverse(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                            const cx<T>* __restrict__ tw, int t) {
+  run_stages<T, SC::N, SC::E, true, 1, P, Lay>(v, lds, lay, tw, t, typename SC::Inv{});
+}
+
+// ----------------------------------------------------------------- potential
+// w = U v for the complex-symmetric U given by its packed upper triangle
+// (S(S+1)/2 entries, row-major); conj = 1 applies conj(U) = U(-tau).
+template <typename T, int S>
+__device__ __forceinline__ void apply_u(cx<T> (&w)[S], const cx<T> (&u)[S * (S + 1) / 2]) {
+  cx<T> in[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) in[s] = w[s];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    cx<T> acc = {(T)0, (T)0};
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      const int e = a * S - (a * (a - 1)) / 2 + (b - a);
+      acc = cadd(acc, cmul(u[e], in[j]));
+    }
+    w[i] = acc;
+  }
+}
+
+}  // namespace sop

@@ -1,0 +1,60 @@
+// internal.hpp -- host-side interface between the planner / C ABI and the
+// HIP kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/soprop.h"
+
+namespace sop {
+
+// Program of one time step: an alternating list of actions.  Entry =
+// (op << 16) | table index, op 0 = potential, 1 = kinetic.
+enum { OP_V = 0, OP_T = 1 };
+inline int prog_entry(int op, int idx) { return (op << 16) | idx; }
+inline int prog_op(int e) { return e >> 16; }
+inline int prog_idx(int e) { return e & 0xffff; }
+
+// Device-side view of a plan that the launchers need.
+struct DevView {
+  int ndim = 1;
+  int n[3] = {1, 1, 1};  // axis lengths, axis 0 slowest
+  int S = 1;
+  int64_t npts = 1;
+  bool f64 = true;
+  hipStream_t stream = nullptr;
+  const void* vexp = nullptr;  // [n_vtab][S(S+1)/2][npts] complex
+  const void* kin = nullptr;   // 1D: [n_ttab][n0]; 3D: [n_ttab][3][kin_stride]
+  int kin_stride = 0;          // complex entries per axis block (3D)
+  const void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis twiddles exp(-2 pi i k/n)
+  const int* prog = nullptr;   // device copy of the step program
+  int nact = 0;
+  std::vector<int> hprog;      // host copy of the step program
+};
+
+// kernels_1d.hip
+bool k1d_supported(int n, int S);
+hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
+hipError_t k1d_fft_forward(const DevView& d, void* psi);
+
+// kernels_3d.hip
+bool k3d_supported(int n, int S);
+hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
+hipError_t k3d_fft_forward(const DevView& d, void* psi);
+
+// kernels_aux.hip
+hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
+                     void* out);
+hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
+                      const double* vraw_dev, const double* inv_mass, const double* dx,
+                      double hbar, double* partials_dev, double* out_dev);
+hipError_t overlap_reduce(const DevView& d, const void* psi, const void* phi,
+                          double* partials_dev, double* out_dev);
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+}  // namespace sop

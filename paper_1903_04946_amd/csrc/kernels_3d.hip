@@ -1,0 +1,324 @@
+// kernels_3d.hip -- three-dimensional cubic grids n^3: the composed time step
+// as a sequence of pencil passes over psi[s][z][y][x] (x fastest).
+//
+// A substep (one potential action followed by one kinetic action, Sec.
+// "Dynamic Fourier method") is four passes over the state:
+//   z-pass : [inverse FFT along z] -> potential unitary(ies) -> [forward FFT z]
+//            (all S surfaces of a tile of x-columns, so the S x S matvec of
+//            Sec. "Molecular Hamiltonian in the diabatic basis" runs in
+//            registers);
+//   y-pass : forward FFT along y;
+//   x-pass : forward FFT along x -> kinetic phase -> inverse FFT along x;
+//   y-pass : inverse FFT along y.
+// Between passes the z axis stays in the momentum representation, so the
+// potential's own pass carries the z transforms.  The last potential action
+// of a step and the first of the next share one z-pass (two matvecs in
+// registers; the arithmetic is the same as two separate passes).
+// The kinetic factor is separable, exp(-i tau T(p)/hbar) / (n_y n_x) =
+// f_z(k_z) f_y(k_y) f_x(k_x); the planner stores the three per-axis factors
+// of each unique coefficient.  The 1/n_z of the z round trip is applied by
+// the z-pass after its inverse transform, because consecutive kinetic
+// actions (TVT at a step boundary) share one z round trip.
+#include <vector>
+
+#include "fft_core.hpp"
+#include "internal.hpp"
+
+namespace sop {
+namespace {
+
+using Z32 = Sched<32, 8, RList<8, 4>, RList<4, 8>, 8, 4>;
+using Z48 = Sched<48, 12, RList<4, 4, 3>, RList<3, 4, 4>, 4, 3>;
+using Z64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
+using Z128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
+using Z256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
+
+// Columns per tile for the strided (y, z) passes: at least a full wave per
+// block and 128-byte contiguous segments in FP64.
+template <class SC>
+constexpr int cols() {
+  return SC::TPC >= 8 ? 8 : 64 / SC::TPC;
+}
+
+// ---------------------------------------------------------------- z-pass
+template <typename T, class SC, int S, int C, bool PRE_INV, bool POST_FWD>
+__global__ void __launch_bounds__(C * SC::TPC)
+    k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
+              int conj, const cx<T>* __restrict__ tw) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
+  const int lane = threadIdx.x;
+  const int col = lane % C, t = lane / C;
+  const int x = blockIdx.x * C + col, y = blockIdx.y;
+  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
+  const int64_t off0 = (int64_t)y * N + x;
+  const LayStrided lay{col, C, S * C};
+  cx<T> v[S][E];
+  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[s][q] = psi[s * npts + own_idx<N, E, RIN>(t, q) * plane + off0];
+  if constexpr (PRE_INV) {
+    fft_inverse<SC, S>(v, lds, lay, tw, t);
+    // normalisation of the z round trip (exact for power-of-two N)
+    constexpr T inv_n = (T)1 / (T)N;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[s][q] = cx<T>{v[s][q].re * inv_n, v[s][q].im * inv_n};
+  }
+  const T csign = conj ? (T)-1 : (T)1;
+  for (int a = 0; a < nv; ++a) {
+    const cx<T>* U = vexp + (size_t)(a == 0 ? iv0 : iv1) * NE * npts + off0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int64_t zo = (int64_t)own_idx<N, E, SC::RF>(t, q) * plane;
+      cx<T> u[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        u[e] = U[e * npts + zo];
+        u[e].im *= csign;
+      }
+      cx<T> w[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) w[s] = v[s][q];
+      apply_u<T, S>(w, u);
+#pragma unroll
+      for (int s = 0; s < S; ++s) v[s][q] = w[s];
+    }
+  }
+  if constexpr (POST_FWD) fft_forward<SC, S>(v, lds, lay, tw, t);
+  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int q = 0; q < E; ++q) psi[s * npts + own_idx<N, E, ROUT>(t, q) * plane + off0] = v[s][q];
+}
+
+// ---------------------------------------------------------------- y-pass
+template <typename T, class SC, int C, bool INV>
+__global__ void __launch_bounds__(C * SC::TPC)
+    k3d_ypass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int N = SC::N, E = SC::E;
+  const int lane = threadIdx.x;
+  const int col = lane % C, t = lane / C;
+  const int x = blockIdx.x * C + col, z = blockIdx.y, s = blockIdx.z;
+  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
+  cx<T>* base = psi + s * npts + z * plane + x;
+  const LayStrided lay{col, 0, C};
+  cx<T> v[1][E];
+  constexpr int RIN = INV ? SC::RL : SC::RF;
+  constexpr int ROUT = INV ? SC::RF : SC::RL;
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = base[own_idx<N, E, RIN>(t, q) * N];
+  if constexpr (INV)
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  else
+    fft_forward<SC, 1>(v, lds, lay, tw, t);
+#pragma unroll
+  for (int q = 0; q < E; ++q) base[own_idx<N, E, ROUT>(t, q) * N] = v[0][q];
+}
+
+// ---------------------------------------------------------------- x-pass
+enum { XP_PHASE = 0, XP_FWD = 1, XP_INV = 2 };
+
+template <typename T, class SC, int ROWS, int MODE>
+__global__ void __launch_bounds__(ROWS * SC::TPC)
+    k3d_xpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
+              const cx<T>* __restrict__ kin, int conj) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
+  const int lane = threadIdx.x;
+  const int t = lane % TPC, row = lane / TPC;
+  const int y = blockIdx.x * ROWS + row, z = blockIdx.y, s = blockIdx.z;
+  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
+  cx<T>* base = psi + s * npts + z * plane + (int64_t)y * N;
+  const LayPadded lay{row * (N + N / 16), 0};
+  cx<T> v[1][E];
+  constexpr int RIN = MODE == XP_INV ? SC::RL : SC::RF;
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = base[own_idx<N, E, RIN>(t, q)];
+  if constexpr (MODE == XP_INV) {
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  } else {
+    fft_forward<SC, 1>(v, lds, lay, tw, t);
+  }
+  if constexpr (MODE == XP_PHASE) {
+    const T csign = conj ? (T)-1 : (T)1;
+    cx<T> fzy = cmul(kin[z], kin[N + y]);
+    fzy.im *= csign;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(t, q)];
+      fx.im *= csign;
+      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
+    }
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  }
+  constexpr int ROUT = MODE == XP_FWD ? SC::RL : SC::RF;
+#pragma unroll
+  for (int q = 0; q < E; ++q) base[own_idx<N, E, ROUT>(t, q)] = v[0][q];
+}
+
+constexpr int kRows = 8;
+
+// ---------------------------------------------------------------- launchers
+template <typename K>
+hipError_t set_lds(K k, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <typename T, class SC, int S>
+struct Passes {
+  static constexpr int N = SC::N;
+  static constexpr int C = cols<SC>();
+
+  template <bool PI, bool PF>
+  static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int conj) {
+    auto k = k3d_zpass<T, SC, S, C, PI, PF>;
+    const size_t lds = (size_t)S * C * N * sizeof(cx<T>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(N / C, N), dim3(C * SC::TPC), lds, d.stream, psi,
+                       (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0]);
+    return hipGetLastError();
+  }
+  static hipError_t zpass(const DevView& d, cx<T>* psi, bool pi, bool pf, int nv, int iv0,
+                          int iv1, int conj) {
+    if (pi && pf) return z<true, true>(d, psi, nv, iv0, iv1, conj);
+    if (pi) return z<true, false>(d, psi, nv, iv0, iv1, conj);
+    if (pf) return z<false, true>(d, psi, nv, iv0, iv1, conj);
+    return z<false, false>(d, psi, nv, iv0, iv1, conj);
+  }
+  template <bool INV>
+  static hipError_t ypass(const DevView& d, cx<T>* psi) {
+    auto k = k3d_ypass<T, SC, C, INV>;
+    const size_t lds = (size_t)C * N * sizeof(cx<T>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(N / C, N, d.S), dim3(C * SC::TPC), lds, d.stream, psi,
+                       (const cx<T>*)d.tw[1]);
+    return hipGetLastError();
+  }
+  template <int MODE>
+  static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj) {
+    auto k = k3d_xpass<T, SC, kRows, MODE>;
+    const size_t lds = (size_t)kRows * (N + N / 16) * sizeof(cx<T>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
+    hipLaunchKernelGGL(k, dim3(N / kRows, N, d.S), dim3(kRows * SC::TPC), lds, d.stream, psi,
+                       (const cx<T>*)d.tw[2], kin, conj);
+    return hipGetLastError();
+  }
+
+  // Walks the action program for nsteps steps and emits the passes.
+  static hipError_t propagate(const DevView& d, void* vpsi, int64_t nsteps, int conj) {
+    cx<T>* psi = (cx<T>*)vpsi;
+    bool zk = false;        // z axis currently in the momentum representation
+    bool zopen = false;     // a z-pass is being assembled
+    bool zpre = false;
+    int zv[2] = {0, 0}, znv = 0;
+    hipError_t e = hipSuccess;
+    auto flush = [&](bool post_fwd) -> hipError_t {
+      hipError_t r = zpass(d, psi, zpre, post_fwd, znv, zv[0], zv[1], conj);
+      zopen = false;
+      znv = 0;
+      zk = post_fwd;
+      return r;
+    };
+    for (int64_t step = 0; step < nsteps; ++step) {
+      for (int a = 0; a < d.nact; ++a) {
+        const int code = d.hprog[a];
+        const int idx = prog_idx(code);
+        if (prog_op(code) == OP_V) {
+          if (zopen && znv == 2) {
+            if ((e = flush(false)) != hipSuccess) return e;
+          }
+          if (!zopen) {
+            zopen = true;
+            zpre = zk;
+            znv = 0;
+            zk = false;
+          }
+          zv[znv++] = idx;
+        } else {
+          if (zopen) {
+            if ((e = flush(true)) != hipSuccess) return e;
+          } else if (!zk) {
+            if ((e = zpass(d, psi, false, true, 0, 0, 0, conj)) != hipSuccess) return e;
+            zk = true;
+          }
+          if ((e = ypass<false>(d, psi)) != hipSuccess) return e;
+          if ((e = xpass<XP_PHASE>(d, psi, idx, conj)) != hipSuccess) return e;
+          if ((e = ypass<true>(d, psi)) != hipSuccess) return e;
+        }
+      }
+    }
+    if (zopen) return flush(false);
+    if (zk) return zpass(d, psi, true, false, 0, 0, 0, conj);
+    return hipSuccess;
+  }
+
+  static hipError_t fft_forward(const DevView& d, void* vpsi) {
+    cx<T>* psi = (cx<T>*)vpsi;
+    hipError_t e = zpass(d, psi, false, true, 0, 0, 0, 0);
+    if (e != hipSuccess) return e;
+    if ((e = ypass<false>(d, psi)) != hipSuccess) return e;
+    return xpass<XP_FWD>(d, psi, 0, 0);
+  }
+};
+
+template <class F>
+hipError_t dispatch(int n, int S, bool f64, F&& f) {
+#define SOP_3D_CASE(NN)                                                      \
+  case NN:                                                                   \
+    if (f64) {                                                               \
+      if (S == 1) return f.template operator()<double, Z##NN, 1>();          \
+      if (S == 2) return f.template operator()<double, Z##NN, 2>();          \
+      if (S == 3) return f.template operator()<double, Z##NN, 3>();          \
+    } else {                                                                 \
+      if (S == 1) return f.template operator()<float, Z##NN, 1>();           \
+      if (S == 2) return f.template operator()<float, Z##NN, 2>();           \
+      if (S == 3) return f.template operator()<float, Z##NN, 3>();           \
+    }                                                                        \
+    return hipErrorInvalidValue;
+  switch (n) {
+    SOP_3D_CASE(32)
+    SOP_3D_CASE(48)
+    SOP_3D_CASE(64)
+    SOP_3D_CASE(128)
+    SOP_3D_CASE(256)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SOP_3D_CASE
+}
+
+}  // namespace
+
+bool k3d_supported(int n, int S) {
+  if (S < 1 || S > 3) return false;
+  return n == 32 || n == 48 || n == 64 || n == 128 || n == 256;
+}
+
+hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) {
+  return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
+    return Passes<T, SC, S>::propagate(d, psi, nsteps, conj);
+  });
+}
+
+hipError_t k3d_fft_forward(const DevView& d, void* psi) {
+  return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
+    return Passes<T, SC, S>::fft_forward(d, psi);
+  });
+}
+
+}  // namespace sop

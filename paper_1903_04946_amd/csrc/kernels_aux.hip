@@ -1,0 +1,329 @@
+// kernels_aux.hip -- evolution-operator table formation and FP64 reductions.
+//
+// Potential tables (Sec. "Pruning splitting coefficients": the unique
+// evolution operators are computed once at initialisation; Sec. "Molecular
+// Hamiltonian in the diabatic basis": the exponential of the S x S potential
+// matrix from its Jacobi diagonalisation).  Per grid point the real
+// symmetric V(q) is diagonalised by cyclic two-sided Jacobi rotations in
+// FP64; for every unique coefficient c the complex-symmetric
+// exp(-i tau V/hbar) = R diag(exp(-i lambda tau/hbar)) R^T, tau = c dt, is
+// formed in FP64 and rounded once to the plan precision; its packed upper
+// triangle is stored structure-of-arrays, [unique][entry][point].
+//
+// Reductions: norm, surface populations and <V> from psi, <T> from its
+// forward transform, and <psi|phi>; every sum is FP64 with a fixed block
+// count and a fixed-order tree, so results are bitwise reproducible.
+#include "fft_core.hpp"
+#include "internal.hpp"
+
+namespace sop {
+namespace {
+
+// One sweep set of cyclic Jacobi rotations on a real symmetric S x S matrix.
+// On return A is diagonal (eigenvalues on the diagonal) and R holds the
+// eigenvectors in its columns.
+template <int S>
+__device__ void jacobi_sym(double (&A)[S][S], double (&R)[S][S]) {
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) R[i][j] = (i == j) ? 1.0 : 0.0;
+  if constexpr (S == 1) return;
+  for (int sweep = 0; sweep < 24; ++sweep) {
+    bool rotated = false;
+#pragma unroll
+    for (int p = 0; p < S - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < S; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double scale = fabs(A[p][p]) + fabs(A[q][q]);
+        if (fabs(apq) <= 1e-18 * scale) {  // negligible next to the diagonal
+          A[p][q] = 0.0;
+          A[q][p] = 0.0;
+          continue;
+        }
+        rotated = true;
+        // tan(2 theta) = 2 a_pq / (a_qq - a_pp), |theta| <= pi/4
+        const double th = 0.5 * atan((2.0 * apq) / (A[q][q] - A[p][p]));
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        // A <- A J (columns p, q), J = [[c, s], [-s, c]] on (p, q)
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          const double arp = A[r][p], arq = A[r][q];
+          A[r][p] = cs * arp - sn * arq;
+          A[r][q] = sn * arp + cs * arq;
+          const double rrp = R[r][p], rrq = R[r][q];
+          R[r][p] = cs * rrp - sn * rrq;
+          R[r][q] = sn * rrp + cs * rrq;
+        }
+        // A <- J^T A (rows p, q)
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          const double apr = A[p][r], aqr = A[q][r];
+          A[p][r] = cs * apr - sn * aqr;
+          A[q][r] = sn * apr + cs * aqr;
+        }
+        A[p][q] = 0.0;
+        A[q][p] = 0.0;
+      }
+    }
+    if (!rotated) break;
+  }
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(256)
+    k_form_vexp(const double* __restrict__ vraw, int64_t npts, const double* __restrict__ taus,
+                int ntau, cx<T>* __restrict__ out) {
+  constexpr int NE = S * (S + 1) / 2;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    double A[S][S], R[S][S];
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = i; j < S; ++j) {
+        const double vij = vraw[(int64_t)e * npts + x];
+        A[i][j] = vij;
+        A[j][i] = vij;
+        ++e;
+      }
+    jacobi_sym<S>(A, R);
+    for (int u = 0; u < ntau; ++u) {
+      double ere[S], eim[S];
+#pragma unroll
+      for (int l = 0; l < S; ++l) sincos(-A[l][l] * taus[u], &eim[l], &ere[l]);
+      int ee = 0;
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = i; j < S; ++j) {
+          double re = 0.0, im = 0.0;
+#pragma unroll
+          for (int l = 0; l < S; ++l) {
+            const double rr = R[i][l] * R[j][l];
+            re += rr * ere[l];
+            im += rr * eim[l];
+          }
+          out[((int64_t)u * NE + ee) * npts + x] = cx<T>{(T)re, (T)im};
+          ++ee;
+        }
+    }
+  }
+}
+
+// Block-level fixed-order sum of NV values per thread; thread 0 writes the
+// block's NV sums to out.
+template <int NV>
+__device__ void block_sum(double (&acc)[NV], double* out) {
+  __shared__ double red[kReduceThreads][NV];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) red[tid][v] = acc[v];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) red[tid][v] += red[tid + w][v];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = red[0][v];
+  }
+}
+
+// Per block: sum_x |psi_s(x)|^2 for each s, and sum_x Re(psi(x)^dag V(x) psi(x)).
+template <typename T, int S>
+__global__ void __launch_bounds__(kReduceThreads)
+    k_obs_points(const cx<T>* __restrict__ psi, const double* __restrict__ vraw, int64_t npts,
+                 double* __restrict__ partials) {
+  double acc[S + 1];
+#pragma unroll
+  for (int v = 0; v <= S; ++v) acc[v] = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * kReduceThreads) {
+    double re[S], im[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const cx<T> p = psi[s * npts + x];
+      re[s] = (double)p.re;
+      im[s] = (double)p.im;
+      acc[s] += re[s] * re[s] + im[s] * im[s];
+    }
+    int e = 0;
+    double ev = 0.0;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = i; j < S; ++j) {
+        const double vij = vraw[(int64_t)e * npts + x];
+        // Re(conj(psi_i) psi_j), counted twice off the diagonal
+        const double rr = re[i] * re[j] + im[i] * im[j];
+        ev += (i == j ? 1.0 : 2.0) * vij * rr;
+        ++e;
+      }
+    acc[S] += ev;
+  }
+  block_sum<S + 1>(acc, partials + (size_t)blockIdx.x * (S + 1));
+}
+
+// Per block: sum_k T(k) sum_s |psi_hat_s(k)|^2 with T(k) = sum_d inv_mass_d
+// (hbar kappa_d)^2 / 2, kappa_d = 2 pi k'_d / (n_d dx_d).
+template <typename T>
+__global__ void __launch_bounds__(kReduceThreads)
+    k_obs_kinetic(const cx<T>* __restrict__ ph, int S, int ndim, int n0, int n1, int n2,
+                  double c0, double c1, double c2, double* __restrict__ partials) {
+  const int64_t npts = (int64_t)n0 * n1 * n2;
+  double acc[1] = {0.0};
+  for (int64_t x = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * kReduceThreads) {
+    const int k2 = (int)(x % n2);
+    const int k1 = (int)((x / n2) % n1);
+    const int k0 = (int)(x / ((int64_t)n1 * n2));
+    auto sq = [](int k, int n) {
+      const double kk = (k < n / 2) ? (double)k : (double)(k - n);
+      return kk * kk;
+    };
+    // c_d = inv_mass_d * (hbar * 2 pi / (n_d dx_d))^2 / 2
+    double t = c0 * sq(k0, n0);
+    if (ndim > 1) t += c1 * sq(k1, n1) + c2 * sq(k2, n2);
+    double m = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const cx<T> p = ph[s * npts + x];
+      m += (double)p.re * (double)p.re + (double)p.im * (double)p.im;
+    }
+    acc[0] += t * m;
+  }
+  block_sum<1>(acc, partials + blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kReduceThreads)
+    k_overlap(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, int64_t n,
+              double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kReduceThreads) {
+    const cx<T> p = a[i], q = b[i];
+    // conj(p) q
+    acc[0] += (double)p.re * (double)q.re + (double)p.im * (double)q.im;
+    acc[1] += (double)p.re * (double)q.im - (double)p.im * (double)q.re;
+  }
+  block_sum<2>(acc, partials + (size_t)blockIdx.x * 2);
+}
+
+// Sums nblocks rows of nv partials in a fixed order into out[nv].
+__global__ void __launch_bounds__(kReduceThreads)
+    k_final(const double* __restrict__ partials, int nblocks, int nv, double* __restrict__ out) {
+  __shared__ double red[kReduceThreads];
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kReduceThreads) acc += partials[(size_t)b * nv + v];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+    __syncthreads();
+  }
+}
+
+template <int S, typename T>
+hipError_t form_impl(const DevView& d, const double* vraw, const double* taus, int ntau,
+                     void* out) {
+  int blocks = (int)((d.npts + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_form_vexp<T, S>), dim3(blocks), dim3(256), 0, d.stream, vraw, d.npts,
+                     taus, ntau, (cx<T>*)out);
+  return hipGetLastError();
+}
+
+template <int S, typename T>
+hipError_t obs_points_impl(const DevView& d, const void* psi, const double* vraw,
+                           double* partials) {
+  hipLaunchKernelGGL((k_obs_points<T, S>), dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                     d.stream, (const cx<T>*)psi, vraw, d.npts, partials);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
+                     void* out) {
+  switch (d.S) {
+    case 1: return d.f64 ? form_impl<1, double>(d, vraw_dev, taus, ntau, out)
+                         : form_impl<1, float>(d, vraw_dev, taus, ntau, out);
+    case 2: return d.f64 ? form_impl<2, double>(d, vraw_dev, taus, ntau, out)
+                         : form_impl<2, float>(d, vraw_dev, taus, ntau, out);
+    case 3: return d.f64 ? form_impl<3, double>(d, vraw_dev, taus, ntau, out)
+                         : form_impl<3, float>(d, vraw_dev, taus, ntau, out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// partials layout: [kReduceBlocks][S+1] for the pointwise sums, then
+// [kReduceBlocks] for the kinetic sum.  out_dev receives S + 2 raw sums:
+// sum |psi_s|^2 (S values), sum psi^dag V psi, sum T |psi_hat|^2.
+hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
+                      const double* vraw_dev, const double* inv_mass, const double* dx,
+                      double hbar, double* partials, double* out_dev) {
+  hipError_t e;
+  switch (d.S) {
+    case 1: e = d.f64 ? obs_points_impl<1, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<1, float>(d, psi, vraw_dev, partials); break;
+    case 2: e = d.f64 ? obs_points_impl<2, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<2, float>(d, psi, vraw_dev, partials); break;
+    case 3: e = d.f64 ? obs_points_impl<3, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<3, float>(d, psi, vraw_dev, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int nv = d.S + 1;
+  double* kpart = partials + (size_t)kReduceBlocks * nv;
+  double c[3] = {0, 0, 0};
+  const double twopi = 6.283185307179586476925286766559;
+  for (int a = 0; a < d.ndim; ++a) {
+    const double kap = hbar * twopi / ((double)d.n[a] * dx[a]);
+    c[a] = 0.5 * inv_mass[a] * kap * kap;
+  }
+  if (d.f64)
+    hipLaunchKernelGGL(k_obs_kinetic<double>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                       d.stream, (const cx<double>*)psi_hat, d.S, d.ndim, d.n[0], d.n[1], d.n[2],
+                       c[0], c[1], c[2], kpart);
+  else
+    hipLaunchKernelGGL(k_obs_kinetic<float>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                       d.stream, (const cx<float>*)psi_hat, d.S, d.ndim, d.n[0], d.n[1], d.n[2],
+                       c[0], c[1], c[2], kpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials,
+                     kReduceBlocks, nv, out_dev);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, kpart, kReduceBlocks,
+                     1, out_dev + nv);
+  return hipGetLastError();
+}
+
+hipError_t overlap_reduce(const DevView& d, const void* psi, const void* phi, double* partials,
+                          double* out_dev) {
+  const int64_t n = d.npts * d.S;
+  if (d.f64)
+    hipLaunchKernelGGL(k_overlap<double>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, d.stream,
+                       (const cx<double>*)psi, (const cx<double>*)phi, n, partials);
+  else
+    hipLaunchKernelGGL(k_overlap<float>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, d.stream,
+                       (const cx<float>*)psi, (const cx<float>*)phi, n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials, kReduceBlocks,
+                     2, out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace sop

@@ -1,0 +1,553 @@
+// plan.cpp -- host planner and the C ABI of libsoprop (see include/soprop.h).
+//
+// The planner turns a scheme (splitting, composition, order) into the pruned
+// action sequence with unique coefficients (Sec. "Symmetric composition
+// schemes", Sec. "Pruning splitting coefficients", Table II), uploads the
+// V-table, forms the unique potential tables on the device, computes the
+// per-axis kinetic factors and FFT twiddles in extended precision, and
+// drives the kernels.  It shares no code with the CPU oracle.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/soprop.h"
+#include "internal.hpp"
+
+using sop::DevView;
+
+namespace {
+
+thread_local std::string g_err;
+
+sop_status fail(sop_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPTRY(expr)                                                                 \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) {                                                          \
+      return fail(SOP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+    }                                                                                \
+  } while (0)
+
+typedef long double ld;
+const ld kTwoPi = 6.283185307179586476925286766559005768394L;
+
+// ------------------------------------------------------------------ schemes
+// Outer coefficients of one recursion level raising the order p -> p+2:
+// triple jump (c, 1-2c, c), c = 1/(2 - 2^(1/(p+1))); Suzuki's fractal
+// (c, c, 1-4c, c, c), c = 1/(4 - 4^(1/(p+1))).
+std::vector<ld> level_coefficients(sop_comp comp, int p) {
+  if (comp == SOP_COMP_TRIPLE_JUMP) {
+    const ld c = 1.0L / (2.0L - std::pow(2.0L, 1.0L / (ld)(p + 1)));
+    return {c, 1.0L - 2.0L * c, c};
+  }
+  const ld c = 1.0L / (4.0L - std::pow(4.0L, 1.0L / (ld)(p + 1)));
+  return {c, c, 1.0L - 4.0L * c, c, c};
+}
+
+// Composition coefficients gamma_0..gamma_{M-1}.  Stage i of the flattened
+// recursion is the product over levels of the level's coefficient picked by
+// the base-3 (or base-5) digit of i; the least significant digit belongs to
+// the innermost level (order 2 -> 4), since every outer stage scales a whole
+// inner sequence.
+bool composition(sop_comp comp, int order, std::vector<ld>& g) {
+  g.clear();
+  if (comp == SOP_COMP_STRANG) {
+    if (order != 2) return false;
+    g.push_back(1.0L);
+    return true;
+  }
+  if (comp != SOP_COMP_TRIPLE_JUMP && comp != SOP_COMP_SUZUKI) return false;
+  if (order < 2 || order > 10 || (order & 1)) return false;
+  const int levels = order / 2 - 1;
+  const int base = comp == SOP_COMP_TRIPLE_JUMP ? 3 : 5;
+  std::vector<std::vector<ld>> lc;
+  for (int l = 0; l < levels; ++l) lc.push_back(level_coefficients(comp, 2 * l + 2));
+  int M = 1;
+  for (int l = 0; l < levels; ++l) M *= base;
+  g.resize(M);
+  for (int i = 0; i < M; ++i) {
+    ld prod = 1.0L;
+    int r = i;
+    for (int l = 0; l < levels; ++l) {
+      prod *= lc[l][r % base];
+      r /= base;
+    }
+    g[i] = prod;
+  }
+  return true;
+}
+
+struct Sequence {
+  int M = 0;                   // number of B actions
+  std::vector<double> a, b;    // pruned sequence, a has M+1 entries (1 for VT/TV)
+  std::vector<double> au, bu;  // unique values
+  std::vector<int> ia, ib;     // indices (ib has M entries)
+  bool a_is_v = true;
+};
+
+// Unique values of a palindromic list, searching only its first half and
+// mirroring the indices (symmetry, Eq. symmetric_splitting_coefficients).
+void unique_palindrome(const std::vector<double>& v, std::vector<double>& unq,
+                       std::vector<int>& idx) {
+  const int n = (int)v.size();
+  unq.clear();
+  idx.assign(n, -1);
+  for (int j = 0; j < (n + 1) / 2; ++j) {
+    int hit = -1;
+    for (int u = 0; u < (int)unq.size() && hit < 0; ++u) {
+      const double tol = 1e-13 * std::fmax(std::fabs(v[j]), std::fabs(unq[u]));
+      if (std::fabs(v[j] - unq[u]) <= tol) hit = u;
+    }
+    if (hit < 0) {
+      unq.push_back(v[j]);
+      hit = (int)unq.size() - 1;
+    }
+    idx[j] = hit;
+    idx[n - 1 - j] = hit;
+  }
+}
+
+sop_status build_sequence(sop_split split, sop_comp comp, int order, Sequence& s) {
+  s = Sequence();
+  if (split == SOP_SPLIT_VT || split == SOP_SPLIT_TV) {
+    if (order != 1 || comp != SOP_COMP_STRANG)
+      return fail(SOP_ERR_INVALID, "first-order splittings take comp = STRANG and order = 1");
+    s.M = 1;
+    s.a = {1.0};
+    s.b = {1.0};
+    s.au = {1.0};
+    s.bu = {1.0};
+    s.ia = {0};
+    s.ib = {0};
+    s.a_is_v = (split == SOP_SPLIT_TV);  // TV applies V first
+    return SOP_OK;
+  }
+  if (split != SOP_SPLIT_VTV && split != SOP_SPLIT_TVT)
+    return fail(SOP_ERR_INVALID, "unknown splitting");
+  std::vector<ld> g;
+  if (!composition(comp, order, g))
+    return fail(SOP_ERR_INVALID, "invalid composition/order (Strang: 2; TJ/SF: 2..10 even)");
+  const int M = (int)g.size();
+  s.M = M;
+  // Pruned sequence (Eq. merging_splitting_coeff_b_zero applied to every
+  // Strang stage A(g/2) B(g) A(g/2)): a_1 = g_1/2, a_j = (g_{j-1} + g_j)/2,
+  // a_{M+1} = g_M/2 and b_j = g_j.
+  s.a.resize(M + 1);
+  s.b.resize(M);
+  s.a[0] = (double)(g[0] / 2);
+  for (int j = 1; j < M; ++j) s.a[j] = (double)((g[j - 1] + g[j]) / 2);
+  s.a[M] = (double)(g[M - 1] / 2);
+  for (int j = 0; j < M; ++j) s.b[j] = (double)g[j];
+  unique_palindrome(s.a, s.au, s.ia);
+  unique_palindrome(s.b, s.bu, s.ib);
+  s.a_is_v = (split == SOP_SPLIT_VTV);
+  return SOP_OK;
+}
+
+bool supported_length(int ndim, int n) {
+  if (ndim == 1) return sop::k1d_supported(n, 1);
+  if (ndim == 3) return sop::k3d_supported(n, 1);
+  return false;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+struct sop_plan {
+  int ndim = 1;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, dx[3] = {1, 1, 1};
+  double inv_mass[3] = {0, 0, 0};
+  int S = 1;
+  int64_t npts = 1;
+  double dt = 0, hbar = 1, dV = 1;
+  sop_dtype dtype = SOP_C128;
+  size_t csize = 16;  // bytes per complex element
+  Sequence seq;
+  std::vector<double> vtaus;  // c dt / hbar of the potential tables
+  std::vector<double> ttaus;  // c dt of the kinetic factor sets
+  DevView dv;
+  double* d_vraw = nullptr;
+  void* d_vexp = nullptr;
+  void* d_kin = nullptr;
+  void* d_tw = nullptr;
+  int* d_prog = nullptr;
+  int* d_prog1 = nullptr;  // single-action programs {V(0), T(0)}
+  double* d_taus = nullptr;
+  void* d_scratch = nullptr;
+  void* d_atab = nullptr;  // table for sop_apply_action
+  void* d_akin = nullptr;
+  double* d_part = nullptr;
+  double* d_out = nullptr;
+  size_t table_bytes = 0;
+};
+
+namespace {
+
+void free_plan(sop_plan* p) {
+  if (!p) return;
+  void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
+                  p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+// Kinetic factors of one coefficient set: [ntau][ndim or 3][n] complex,
+// f_d(k) = exp(-i tau hbar kappa_k^2 inv_mass_d / 2) / n_d.  On 3D grids
+// the z axis carries no 1/n_z: the z transforms are not paired with each
+// kinetic action (two adjacent kinetic actions share one z round trip), so
+// the z-pass applies 1/n_z after each inverse z transform instead.
+std::vector<ld> kinetic_factors(const sop_plan* p, const std::vector<double>& taus) {
+  const int nax = p->ndim == 1 ? 1 : 3;
+  const int nn = p->n[0];
+  std::vector<ld> out((size_t)taus.size() * nax * nn * 2);
+  for (size_t u = 0; u < taus.size(); ++u)
+    for (int a = 0; a < nax; ++a)
+      for (int k = 0; k < nn; ++k) {
+        const int kk = (k < nn / 2) ? k : k - nn;
+        const ld kap = kTwoPi * (ld)kk / ((ld)p->n[a] * (ld)p->dx[a]);
+        const ld ph = -(ld)taus[u] * (ld)p->hbar * kap * kap * (ld)p->inv_mass[a] / 2.0L;
+        const size_t o = (((size_t)u * nax + a) * nn + k) * 2;
+        const ld scale = (nax == 3 && a == 0) ? 1.0L : 1.0L / (ld)p->n[a];
+        out[o] = std::cos(ph) * scale;
+        out[o + 1] = std::sin(ph) * scale;
+      }
+  return out;
+}
+
+// Rounds interleaved extended-precision values to the plan precision.
+std::vector<char> pack(const std::vector<ld>& v, bool f64) {
+  std::vector<char> out(v.size() * (f64 ? 8 : 4));
+  if (f64) {
+    double* d = reinterpret_cast<double*>(out.data());
+    for (size_t i = 0; i < v.size(); ++i) d[i] = (double)v[i];
+  } else {
+    float* f = reinterpret_cast<float*>(out.data());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)(double)v[i];
+  }
+  return out;
+}
+
+sop_status validate(const sop_plan_desc* d) {
+  if (!d) return fail(SOP_ERR_INVALID, "desc is NULL");
+  const int nd = d->grid.ndim;
+  if (nd != 1 && nd != 3) return fail(SOP_ERR_UNSUPPORTED, "ndim must be 1 or 3");
+  for (int a = 0; a < nd; ++a) {
+    if (d->grid.n[a] < 1) return fail(SOP_ERR_INVALID, "grid size must be positive");
+    if (!(d->grid.hi[a] > d->grid.lo[a]) || !std::isfinite(d->grid.hi[a] - d->grid.lo[a]))
+      return fail(SOP_ERR_INVALID, "grid requires lo < hi");
+    if (!supported_length(nd, d->grid.n[a]))
+      return fail(SOP_ERR_UNSUPPORTED, "unsupported grid length " + std::to_string(d->grid.n[a]));
+  }
+  if (nd == 3 && (d->grid.n[1] != d->grid.n[0] || d->grid.n[2] != d->grid.n[0]))
+    return fail(SOP_ERR_UNSUPPORTED, "3D grids must be cubic");
+  if (d->nsurf < 1 || (nd == 1 && d->nsurf > 2) || (nd == 3 && d->nsurf > 3))
+    return fail(SOP_ERR_UNSUPPORTED, "nsurf must be 1..2 (1D) or 1..3 (3D)");
+  if (!d->inv_mass || !d->vtable) return fail(SOP_ERR_INVALID, "inv_mass and vtable are required");
+  for (int a = 0; a < nd; ++a)
+    if (!std::isfinite(d->inv_mass[a]) || d->inv_mass[a] < 0)
+      return fail(SOP_ERR_INVALID, "inv_mass must be finite and >= 0");
+  if (!(d->dt != 0) || !std::isfinite(d->dt)) return fail(SOP_ERR_INVALID, "dt must be finite and nonzero");
+  if (!(d->hbar > 0) || !std::isfinite(d->hbar)) return fail(SOP_ERR_INVALID, "hbar must be > 0");
+  if (d->dtype != SOP_C128 && d->dtype != SOP_C64) return fail(SOP_ERR_INVALID, "bad dtype");
+  return SOP_OK;
+}
+
+sop_status ensure_scratch(sop_plan* p) {
+  if (!p->d_scratch) HIPTRY(hipMalloc(&p->d_scratch, (size_t)p->S * p->npts * p->csize));
+  return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sop_abi_version(void) { return SOP_ABI_VERSION; }
+
+const char* sop_status_string(sop_status s) {
+  switch (s) {
+    case SOP_OK: return "ok";
+    case SOP_ERR_INVALID: return "invalid argument";
+    case SOP_ERR_UNSUPPORTED: return "unsupported";
+    case SOP_ERR_NOMEM: return "out of device memory";
+    case SOP_ERR_HIP: return "HIP runtime error";
+    case SOP_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* sop_last_error(void) { return g_err.c_str(); }
+
+int sop_supported_length(int ndim, int n) { return supported_length(ndim, n) ? 1 : 0; }
+
+sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int cap, double* a,
+                               double* b, double* a_unq, double* b_unq, int* ia, int* ib,
+                               int* counts) {
+  Sequence s;
+  sop_status st = build_sequence(split, comp, order, s);
+  if (st != SOP_OK) return st;
+  const int N = (int)s.a.size();
+  if (cap < N) return fail(SOP_ERR_INVALID, "capacity smaller than the sequence length");
+  for (int j = 0; j < N; ++j) {
+    if (a) a[j] = s.a[j];
+    if (b) b[j] = j < (int)s.b.size() ? s.b[j] : 0.0;
+    if (ia) ia[j] = s.ia[j];
+    if (ib) ib[j] = j < (int)s.ib.size() ? s.ib[j] : -1;
+  }
+  for (size_t u = 0; u < s.au.size(); ++u)
+    if (a_unq) a_unq[u] = s.au[u];
+  for (size_t u = 0; u < s.bu.size(); ++u)
+    if (b_unq) b_unq[u] = s.bu[u];
+  if (counts) {
+    counts[0] = N;
+    counts[1] = (int)s.au.size();
+    counts[2] = (int)s.bu.size();
+    counts[3] = s.M;
+  }
+  return SOP_OK;
+}
+
+sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out) {
+  if (!out) return fail(SOP_ERR_INVALID, "out is NULL");
+  sop_status st = validate(desc);
+  if (st != SOP_OK) return st;
+  sop_plan* p = new (std::nothrow) sop_plan();
+  if (!p) return fail(SOP_ERR_NOMEM, "host allocation failed");
+  struct Guard {
+    sop_plan* p;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) free_plan(p);
+    }
+  } guard{p};
+
+  st = build_sequence(desc->split, desc->comp, desc->order, p->seq);
+  if (st != SOP_OK) return st;
+  p->ndim = desc->grid.ndim;
+  p->S = desc->nsurf;
+  p->npts = 1;
+  p->dV = 1;
+  for (int a = 0; a < p->ndim; ++a) {
+    p->n[a] = desc->grid.n[a];
+    p->lo[a] = desc->grid.lo[a];
+    p->hi[a] = desc->grid.hi[a];
+    p->dx[a] = (p->hi[a] - p->lo[a]) / p->n[a];
+    p->inv_mass[a] = desc->inv_mass[a];
+    p->npts *= p->n[a];
+    p->dV *= p->dx[a];
+  }
+  p->dt = desc->dt;
+  p->hbar = desc->hbar;
+  p->dtype = desc->dtype;
+  const bool f64 = desc->dtype == SOP_C128;
+  p->csize = f64 ? 16 : 8;
+  const int S = p->S, NE = S * (S + 1) / 2;
+  hipStream_t stream = (hipStream_t)hip_stream;
+
+  // coefficient sets: potential and kinetic
+  const Sequence& q = p->seq;
+  const std::vector<double>& vc = q.a_is_v ? q.au : q.bu;
+  const std::vector<double>& tc = q.a_is_v ? q.bu : q.au;
+  for (double c : vc) p->vtaus.push_back((double)((ld)c * (ld)p->dt / (ld)p->hbar));
+  for (double c : tc) p->ttaus.push_back((double)((ld)c * (ld)p->dt));
+
+  // step program
+  std::vector<int> prog;
+  const int nA = (int)q.a.size(), nB = (int)q.b.size();
+  const int opA = q.a_is_v ? sop::OP_V : sop::OP_T, opB = q.a_is_v ? sop::OP_T : sop::OP_V;
+  for (int j = 0; j < nA; ++j) {
+    prog.push_back(sop::prog_entry(opA, q.ia[j]));
+    if (j < nB) prog.push_back(sop::prog_entry(opB, q.ib[j]));
+  }
+
+  // device buffers
+  const size_t vbytes = (size_t)NE * p->npts * sizeof(double);
+  const size_t tbytes = vc.size() * NE * p->npts * p->csize;
+  const int nax = p->ndim == 1 ? 1 : 3;
+  const size_t kbytes = tc.size() * nax * p->n[0] * p->csize;
+  const size_t wbytes = (size_t)nax * p->n[0] * p->csize;
+  if (hipMalloc(&p->d_vraw, vbytes) != hipSuccess || hipMalloc(&p->d_vexp, tbytes) != hipSuccess ||
+      hipMalloc(&p->d_kin, kbytes) != hipSuccess || hipMalloc(&p->d_tw, wbytes) != hipSuccess ||
+      hipMalloc((void**)&p->d_prog, prog.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&p->d_prog1, 2 * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&p->d_taus, (vc.size() + 1) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->d_part, (size_t)sop::kReduceBlocks * (S + 2) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->d_out, 8 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SOP_ERR_NOMEM, "device allocation failed for the plan tables");
+  }
+  p->table_bytes = tbytes + kbytes;
+
+  // twiddles exp(-2 pi i k/n), one block per axis
+  std::vector<ld> tw((size_t)nax * p->n[0] * 2);
+  for (int a = 0; a < nax; ++a)
+    for (int k = 0; k < p->n[a]; ++k) {
+      const ld ang = -kTwoPi * (ld)k / (ld)p->n[a];
+      tw[((size_t)a * p->n[0] + k) * 2] = std::cos(ang);
+      tw[((size_t)a * p->n[0] + k) * 2 + 1] = std::sin(ang);
+    }
+  std::vector<char> twp = pack(tw, f64), kinp = pack(kinetic_factors(p, p->ttaus), f64);
+  const int prog1[2] = {sop::prog_entry(sop::OP_V, 0), sop::prog_entry(sop::OP_T, 0)};
+  HIPTRY(hipMemcpyAsync(p->d_vraw, desc->vtable, vbytes, hipMemcpyHostToDevice, stream));
+  HIPTRY(hipMemcpyAsync(p->d_tw, twp.data(), wbytes, hipMemcpyHostToDevice, stream));
+  HIPTRY(hipMemcpyAsync(p->d_kin, kinp.data(), kbytes, hipMemcpyHostToDevice, stream));
+  HIPTRY(hipMemcpyAsync(p->d_prog, prog.data(), prog.size() * sizeof(int), hipMemcpyHostToDevice,
+                        stream));
+  HIPTRY(hipMemcpyAsync(p->d_prog1, prog1, sizeof(prog1), hipMemcpyHostToDevice, stream));
+  HIPTRY(hipMemcpyAsync(p->d_taus, p->vtaus.data(), p->vtaus.size() * sizeof(double),
+                        hipMemcpyHostToDevice, stream));
+
+  DevView& d = p->dv;
+  d.ndim = p->ndim;
+  for (int a = 0; a < 3; ++a) d.n[a] = a < p->ndim ? p->n[a] : 1;
+  d.S = S;
+  d.npts = p->npts;
+  d.f64 = f64;
+  d.stream = stream;
+  d.vexp = p->d_vexp;
+  d.kin = p->d_kin;
+  d.kin_stride = p->n[0];
+  for (int a = 0; a < 3; ++a)
+    d.tw[a] = (const char*)p->d_tw + (size_t)(a < nax ? a : 0) * p->n[0] * p->csize;
+  d.prog = p->d_prog;
+  d.nact = (int)prog.size();
+  d.hprog = prog;
+
+  HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->d_vexp));
+  HIPTRY(hipStreamSynchronize(stream));
+  guard.keep = true;
+  *out = p;
+  return SOP_OK;
+}
+
+sop_status sop_plan_destroy(sop_plan* plan) {
+  if (plan) {
+    (void)hipStreamSynchronize(plan->dv.stream);
+    free_plan(plan);
+  }
+  return SOP_OK;
+}
+
+sop_status sop_plan_info_get(const sop_plan* p, sop_plan_info* out) {
+  if (!p || !out) return fail(SOP_ERR_INVALID, "NULL argument");
+  sop_plan_info i;
+  std::memset(&i, 0, sizeof(i));
+  i.M = p->seq.M;
+  i.n_a = (int)p->seq.a.size();
+  i.n_b = (int)p->seq.b.size();
+  i.n_a_unq = (int)p->seq.au.size();
+  i.n_b_unq = (int)p->seq.bu.size();
+  i.n_v_tables = (int)p->vtaus.size();
+  i.n_t_tables = (int)p->ttaus.size();
+  i.npts = p->npts;
+  i.table_bytes = p->table_bytes;
+  i.scratch_bytes = (size_t)p->S * p->npts * p->csize;
+  *out = i;
+  return SOP_OK;
+}
+
+sop_status sop_plan_set_stream(sop_plan* p, void* hip_stream) {
+  if (!p) return fail(SOP_ERR_INVALID, "plan is NULL");
+  p->dv.stream = (hipStream_t)hip_stream;
+  return SOP_OK;
+}
+
+sop_status sop_propagate(sop_plan* p, void* psi, int64_t nsteps, int direction) {
+  if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
+  if (direction != 1 && direction != -1) return fail(SOP_ERR_INVALID, "direction must be +1 or -1");
+  if (nsteps == 0) return SOP_OK;
+  const int conj = direction < 0 ? 1 : 0;
+  if (p->ndim == 1)
+    HIPTRY(sop::k1d_propagate(p->dv, psi, nsteps, conj));
+  else
+    HIPTRY(sop::k3d_propagate(p->dv, psi, nsteps, conj));
+  return SOP_OK;
+}
+
+sop_status sop_observables(sop_plan* p, const void* psi, double* out) {
+  if (!p || !psi || !out) return fail(SOP_ERR_INVALID, "NULL argument");
+  sop_status st = ensure_scratch(p);
+  if (st != SOP_OK) return st;
+  const size_t bytes = (size_t)p->S * p->npts * p->csize;
+  HIPTRY(hipMemcpyAsync(p->d_scratch, psi, bytes, hipMemcpyDeviceToDevice, p->dv.stream));
+  if (p->ndim == 1)
+    HIPTRY(sop::k1d_fft_forward(p->dv, p->d_scratch));
+  else
+    HIPTRY(sop::k3d_fft_forward(p->dv, p->d_scratch));
+  HIPTRY(sop::obs_reduce(p->dv, psi, p->d_scratch, p->d_vraw, p->inv_mass, p->dx, p->hbar,
+                         p->d_part, p->d_out));
+  double raw[8];
+  HIPTRY(hipMemcpyAsync(raw, p->d_out, (p->S + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                        p->dv.stream));
+  HIPTRY(hipStreamSynchronize(p->dv.stream));
+  const int S = p->S;
+  double norm = 0;
+  for (int s = 0; s < S; ++s) norm += raw[s] * p->dV;
+  const double ev = raw[S] * p->dV;
+  const double et = raw[S + 1] * p->dV / (double)p->npts;
+  out[0] = norm;
+  out[1] = et + ev;
+  for (int s = 0; s < S; ++s) out[2 + s] = raw[s] * p->dV;
+  out[2 + S] = et;
+  out[3 + S] = ev;
+  return SOP_OK;
+}
+
+sop_status sop_overlap(sop_plan* p, const void* psi, const void* phi, double* out) {
+  if (!p || !psi || !phi || !out) return fail(SOP_ERR_INVALID, "NULL argument");
+  HIPTRY(sop::overlap_reduce(p->dv, psi, phi, p->d_part, p->d_out));
+  double raw[2];
+  HIPTRY(hipMemcpyAsync(raw, p->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, p->dv.stream));
+  HIPTRY(hipStreamSynchronize(p->dv.stream));
+  out[0] = raw[0] * p->dV;
+  out[1] = raw[1] * p->dV;
+  return SOP_OK;
+}
+
+sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
+  if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (op != 0 && op != 1) return fail(SOP_ERR_INVALID, "op must be 0 (V) or 1 (T)");
+  if (!std::isfinite(coef)) return fail(SOP_ERR_INVALID, "coef must be finite");
+  DevView d = p->dv;
+  if (op == 0) {
+    const int NE = p->S * (p->S + 1) / 2;
+    if (!p->d_atab) HIPTRY(hipMalloc(&p->d_atab, (size_t)NE * p->npts * p->csize));
+    const double tau = (double)((ld)coef * (ld)p->dt / (ld)p->hbar);
+    HIPTRY(hipMemcpyAsync(p->d_taus + p->vtaus.size(), &tau, sizeof(double),
+                          hipMemcpyHostToDevice, d.stream));
+    HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->d_atab));
+    d.vexp = p->d_atab;
+    d.prog = p->d_prog1;
+    d.hprog = {sop::prog_entry(sop::OP_V, 0)};
+  } else {
+    const int nax = p->ndim == 1 ? 1 : 3;
+    const size_t kb = (size_t)nax * p->n[0] * p->csize;
+    if (!p->d_akin) HIPTRY(hipMalloc(&p->d_akin, kb));
+    std::vector<char> kp = pack(kinetic_factors(p, {(double)((ld)coef * (ld)p->dt)}), d.f64);
+    HIPTRY(hipMemcpyAsync(p->d_akin, kp.data(), kb, hipMemcpyHostToDevice, d.stream));
+    d.kin = p->d_akin;
+    d.prog = p->d_prog1 + 1;
+    d.hprog = {sop::prog_entry(sop::OP_T, 0)};
+  }
+  d.nact = 1;
+  if (p->ndim == 1)
+    HIPTRY(sop::k1d_propagate(d, psi, 1, 0));
+  else
+    HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
+  // the host staging buffers above must outlive the copies
+  HIPTRY(hipStreamSynchronize(d.stream));
+  return SOP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libsoprop (include/soprop.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch supplies device memory (the caller's psi tensors) and the
+stream.  If the library is missing or cannot be loaded, every entry point
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsoprop.so")
+
+SPLITS = {"VTV": 0, "TVT": 1, "VT": 2, "TV": 3}
+COMPS = {"strang": 0, "triple_jump": 1, "tj": 1, "suzuki": 2, "sf": 2}
+C128, C64 = 0, 1
+
+
+class SopError(RuntimeError):
+    pass
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("nsurf", ctypes.c_int),
+                ("inv_mass", ctypes.POINTER(ctypes.c_double)),
+                ("vtable", ctypes.POINTER(ctypes.c_double)),
+                ("split", ctypes.c_int), ("comp", ctypes.c_int), ("order", ctypes.c_int),
+                ("dt", ctypes.c_double), ("hbar", ctypes.c_double), ("dtype", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("n_a", ctypes.c_int), ("n_b", ctypes.c_int),
+                ("n_a_unq", ctypes.c_int), ("n_b_unq", ctypes.c_int),
+                ("n_v_tables", ctypes.c_int), ("n_t_tables", ctypes.c_int),
+                ("npts", ctypes.c_int64), ("table_bytes", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
+           "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
+           "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
+           "sop_apply_action"]
+
+_lib = None
+
+
+def lib():
+    """Loads libsoprop.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SopError(f"{LIB_PATH} is not built; run python -m paper_1903_04946_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    dp, ip, vp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
+    L.sop_abi_version.restype = ctypes.c_int
+    L.sop_status_string.restype = ctypes.c_char_p
+    L.sop_status_string.argtypes = [ctypes.c_int]
+    L.sop_last_error.restype = ctypes.c_char_p
+    L.sop_supported_length.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.sop_scheme_sequence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      dp, dp, dp, dp, ip, ip, ip]
+    L.sop_plan_create.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(vp)]
+    L.sop_plan_destroy.argtypes = [vp]
+    L.sop_plan_info_get.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.sop_plan_set_stream.argtypes = [vp, vp]
+    L.sop_propagate.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int]
+    L.sop_observables.argtypes = [vp, vp, dp]
+    L.sop_overlap.argtypes = [vp, vp, vp, dp]
+    L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
+    for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
+              "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
+              "sop_apply_action"):
+        getattr(L, f).restype = ctypes.c_int
+    L.sop_supported_length.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        L = lib()
+        raise SopError(f"{what}: {L.sop_status_string(rc).decode()} "
+                       f"({L.sop_last_error().decode()})")
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def scheme_sequence(split: str, comp: str, order: int):
+    """Pruned sequence and unique coefficients from the library's planner."""
+    cap = 4096
+    a, b, au, bu = (np.zeros(cap) for _ in range(4))
+    ia = np.zeros(cap, np.int32)
+    ib = np.zeros(cap, np.int32)
+    counts = np.zeros(4, np.int32)
+    _check(lib().sop_scheme_sequence(SPLITS[split], COMPS[comp], order, cap, _dp(a), _dp(b),
+                                     _dp(au), _dp(bu), _ip(ia), _ip(ib), _ip(counts)),
+           "sop_scheme_sequence")
+    N, na, nb, M = (int(c) for c in counts)
+    return {"a": a[:N].copy(), "b": b[:N].copy(), "a_unq": au[:na].copy(),
+            "b_unq": bu[:nb].copy(), "ia": ia[:N].copy(), "ib": ib[:N].copy(), "M": M}
+
+
+@dataclass
+class PlanInfo:
+    M: int
+    n_a: int
+    n_b: int
+    n_a_unq: int
+    n_b_unq: int
+    n_v_tables: int
+    n_t_tables: int
+    npts: int
+    table_bytes: int
+    scratch_bytes: int
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A propagation plan (sop_plan_create).
+
+    n, lo, hi: per-axis grid (1D or cubic 3D); nsurf; inv_mass per axis;
+    vtable: float64 [S(S+1)/2][npts] packed upper triangle of V(q);
+    split: 'VTV' | 'TVT' | 'VT' | 'TV'; comp: 'strang' | 'triple_jump' |
+    'suzuki'; order; dt; dtype: torch.complex128 or torch.complex64.
+    """
+
+    def __init__(self, n, lo, hi, nsurf, inv_mass, vtable, split="VTV", comp="strang",
+                 order=2, dt=0.01, hbar=1.0, dtype=None, stream=None):
+        import torch
+        if dtype is None:
+            dtype = torch.complex128
+        if dtype not in (torch.complex128, torch.complex64):
+            raise ValueError("dtype must be complex128 or complex64")
+        L = lib()
+        self.dtype = dtype
+        self.n = list(n)
+        self.nsurf = int(nsurf)
+        self.shape = (self.nsurf, *self.n)
+        g = _Grid()
+        g.ndim = len(self.n)
+        for d in range(3):
+            g.n[d] = self.n[d] if d < g.ndim else 1
+            g.lo[d] = lo[d] if d < g.ndim else 0.0
+            g.hi[d] = hi[d] if d < g.ndim else 1.0
+        self._inv_mass = np.ascontiguousarray(inv_mass, dtype=np.float64)
+        ne = self.nsurf * (self.nsurf + 1) // 2
+        self._vt = np.ascontiguousarray(vtable, dtype=np.float64).reshape(ne, -1)
+        if self._vt.shape[1] != int(np.prod(self.n)):
+            raise ValueError("vtable size does not match the grid")
+        d = _Desc()
+        d.grid = g
+        d.nsurf = self.nsurf
+        d.inv_mass = _dp(self._inv_mass)
+        d.vtable = _dp(self._vt)
+        d.split = SPLITS[split]
+        d.comp = COMPS[comp]
+        d.order = int(order)
+        d.dt = float(dt)
+        d.hbar = float(hbar)
+        d.dtype = C128 if dtype == torch.complex128 else C64
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(L.sop_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)),
+               "sop_plan_create")
+        self._h = h
+
+    @classmethod
+    def from_model(cls, model, **kw):
+        return cls(model.n, model.lo, model.hi, model.nsurf, model.inv_mass, model.vtable,
+                   hbar=model.hbar, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sop_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> PlanInfo:
+        i = _Info()
+        _check(lib().sop_plan_info_get(self._h, ctypes.byref(i)), "sop_plan_info_get")
+        return PlanInfo(i.M, i.n_a, i.n_b, i.n_a_unq, i.n_b_unq, i.n_v_tables, i.n_t_tables,
+                        i.npts, i.table_bytes, i.scratch_bytes)
+
+    def _check_psi(self, psi):
+        import torch
+        if not isinstance(psi, torch.Tensor) or not psi.is_cuda:
+            raise TypeError("psi must be a CUDA (HIP) tensor")
+        if psi.dtype != self.dtype:
+            raise TypeError(f"psi dtype {psi.dtype} != plan dtype {self.dtype}")
+        if tuple(psi.shape) != self.shape or not psi.is_contiguous():
+            raise ValueError(f"psi must be a contiguous tensor of shape {self.shape}")
+
+    def set_stream(self, stream=None):
+        self._stream = stream
+        _check(lib().sop_plan_set_stream(self._h, _stream_handle(stream)), "sop_plan_set_stream")
+
+    def propagate(self, psi, nsteps: int, direction: int = 1):
+        """psi <- U(direction dt)^nsteps psi in place (asynchronous)."""
+        self._check_psi(psi)
+        _check(lib().sop_propagate(self._h, ctypes.c_void_p(psi.data_ptr()), int(nsteps),
+                                   int(direction)), "sop_propagate")
+        return psi
+
+    def apply_action(self, psi, op: str, coef: float):
+        self._check_psi(psi)
+        _check(lib().sop_apply_action(self._h, ctypes.c_void_p(psi.data_ptr()),
+                                      0 if op == "V" else 1, float(coef)), "sop_apply_action")
+        return psi
+
+    def observables(self, psi) -> dict:
+        self._check_psi(psi)
+        out = np.zeros(4 + self.nsurf)
+        _check(lib().sop_observables(self._h, ctypes.c_void_p(psi.data_ptr()), _dp(out)),
+               "sop_observables")
+        S = self.nsurf
+        return {"norm": out[0], "energy": out[1], "pops": out[2:2 + S].copy(),
+                "kinetic": out[2 + S], "potential": out[3 + S]}
+
+    def overlap(self, psi, phi) -> complex:
+        self._check_psi(psi)
+        self._check_psi(phi)
+        out = np.zeros(2)
+        _check(lib().sop_overlap(self._h, ctypes.c_void_p(psi.data_ptr()),
+                                 ctypes.c_void_p(phi.data_ptr()), _dp(out)), "sop_overlap")
+        return complex(out[0], out[1])

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* the library loads and exports every function include/soprop.h declares;
+* the planner's pruned sequence and unique coefficients agree with Table II
+  (tests/golden/table2_counts.txt) and with the oracle's own, independently
+  written composition code;
+* descriptor validation rejects malformed plans before any device work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1903_04946_amd import soprop
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "soprop.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sop_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(soprop.LIB_PATH):
+        import paper_1903_04946_amd.build as b
+        b.build()
+    return soprop.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(soprop.EXPORTS)
+    assert L.sop_abi_version() == 1
+
+
+def test_supported_lengths(L):
+    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        assert L.sop_supported_length(1, n) == 1
+    for n in (32, 48, 64, 128, 256):
+        assert L.sop_supported_length(3, n) == 1
+    for n in (0, 100, 96, 16384):
+        assert L.sop_supported_length(1, n) == 0
+    assert L.sop_supported_length(2, 64) == 0
+
+
+SCHEME = {"strang": ("strang", 0), "tj": ("triple_jump", 1), "sf": ("suzuki", 2)}
+
+
+def golden_rows():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "table2_counts.txt")):
+        if line.strip() and not line.startswith("#"):
+            s, o, bef, aft, na, nb = line.split()
+            rows.append((s, int(o), int(bef), int(aft), int(na), int(nb)))
+    return rows
+
+
+@pytest.mark.parametrize("row", golden_rows(), ids=lambda r: f"{r[0]}{r[1]}")
+def test_planner_table2_and_oracle(L, orc, row):
+    s, order, before, after, na, nb = row
+    comp, oc = SCHEME[s]
+    q = soprop.scheme_sequence("VTV", comp, order)
+    M = q["M"]
+    assert len(q["a"]) == M + 1
+    assert len(q["a"]) + M == after
+    assert 3 * M == before
+    assert (len(q["a_unq"]), len(q["b_unq"])) == (na, nb)
+    np.testing.assert_array_equal(q["a_unq"][q["ia"]], q["a"])
+    np.testing.assert_array_equal(q["b_unq"][q["ib"][:M]], q["b"][:M])
+    # the oracle's independent composition code
+    au, bu, ia, ib = orc.unique(orc.VTV, oc, order)
+    ap, bp = orc.splitting(orc.VTV, oc, order, True)
+    np.testing.assert_allclose(q["a"], ap, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(q["b"][:M], bp[:M], rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(q["ia"], ia)
+    np.testing.assert_array_equal(q["ib"][:M], ib[:M])
+    np.testing.assert_allclose(q["a_unq"], au, rtol=1e-15)
+    np.testing.assert_allclose(q["b_unq"], bu, rtol=1e-15)
+
+
+def test_first_order_and_tvt_sequences(L):
+    for sp in ("VT", "TV"):
+        q = soprop.scheme_sequence(sp, "strang", 1)
+        assert list(q["a"]) == [1.0] and q["M"] == 1
+    q = soprop.scheme_sequence("TVT", "suzuki", 4)
+    assert (len(q["a_unq"]), len(q["b_unq"])) == (3, 2)
+
+
+def _desc(**kw):
+    g = soprop._Grid()
+    g.ndim = kw.get("ndim", 1)
+    for d in range(3):
+        g.n[d] = kw.get("n", 64)
+        g.lo[d] = -1.0
+        g.hi[d] = kw.get("hi", 1.0)
+    d = soprop._Desc()
+    d.grid = g
+    d.nsurf = kw.get("nsurf", 2)
+    im = np.ones(3)
+    vt = np.zeros(3 * 64**3)
+    d.inv_mass = soprop._dp(im)
+    d.vtable = soprop._dp(vt) if kw.get("vt", True) else ctypes.POINTER(ctypes.c_double)()
+    d.split = kw.get("split", 0)
+    d.comp = kw.get("comp", 0)
+    d.order = kw.get("order", 2)
+    d.dt = kw.get("dt", 0.1)
+    d.hbar = kw.get("hbar", 1.0)
+    d.dtype = kw.get("dtype", 0)
+    return d, (im, vt)
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"ndim": 2}, 2), ({"n": 100}, 2), ({"nsurf": 3}, 2), ({"nsurf": 0}, 2),
+    ({"dt": 0.0}, 1), ({"dt": float("nan")}, 1), ({"hbar": 0.0}, 1), ({"hi": -2.0}, 1),
+    ({"order": 3, "comp": 1}, 1), ({"order": 4, "comp": 0}, 1), ({"split": 2, "order": 2}, 1),
+    ({"vt": False}, 1), ({"dtype": 7}, 1), ({"order": 12, "comp": 1}, 1),
+])
+def test_validation_before_device_work(L, kw, code):
+    d, keep = _desc(**kw)
+    h = ctypes.c_void_p()
+    rc = L.sop_plan_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == code, L.sop_last_error()
+    assert h.value is None
+    assert L.sop_last_error().decode() != ""
+
+
+def test_null_arguments(L):
+    assert L.sop_propagate(None, None, 1, 1) == 1
+    assert L.sop_observables(None, None, None) == 1
+    assert L.sop_plan_destroy(None) == 0
