@@ -88,7 +88,7 @@ typedef struct {
 
 typedef struct {
   sop_grid grid;
-  int nsurf;              /* S, 1..3 for ndim = 3, 1..4 for ndim = 1 */
+  int nsurf;              /* S: 1..2 for ndim = 1, 1..3 for ndim = 3 */
   const double* inv_mass; /* [ndim] host, 1/m_d (Eq. diab_mol_ham, diagonal mass matrix) */
   const double* vtable;   /* host, packed upper triangle, see above */
   sop_split split;
@@ -177,6 +177,17 @@ sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev,
  * exp(-i tau V/hbar) with tau = coef * dt, op = 1 kinetic exp(-i tau T/hbar).
  * The table for coef is formed on the fly into the plan's scratch. */
 sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
+
+/* Per-kernel timing (measurement aid).  While enabled, every kernel launch
+ * of the plan is bracketed by HIP events on the plan's stream.
+ * sop_timing_read synchronises the stream and returns, per kernel kind
+ * (SOP_KIND_*), the summed event time in ms, the launch count and the summed
+ * algorithmic bytes (state read + written, tables read), then clears the
+ * records.  ms, counts, bytes: host arrays of SOP_KIND_COUNT entries. */
+enum { SOP_KIND_ZPASS = 0, SOP_KIND_YPASS = 1, SOP_KIND_XPASS = 2, SOP_KIND_1D = 3,
+       SOP_KIND_OTHER = 4, SOP_KIND_COUNT = 5 };
+sop_status sop_plan_set_timing(sop_plan* plan, int enable);
+sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -71,12 +71,15 @@ def lib():
         L.orc_propagate.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, ctypes.c_int64, ctypes.c_int, dp]
         L.orc_action.argtypes = [pp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_propagate_timed.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int64, dp, dp]
+        L.orc_threads.argtypes = []
         L.orc_observables.argtypes = [pp, dp, dp]
         L.orc_overlap.argtypes = [pp, dp, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
-                  "orc_exact"):
+                  "orc_exact", "orc_propagate_timed", "orc_threads"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -190,6 +193,18 @@ def propagate(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: in
     if rc != 0:
         raise ValueError("oracle propagate rejected its arguments")
     return a
+
+
+def propagate_timed(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: int,
+                    dt: float, nsteps: int):
+    """Pruned propagation; returns (psi, seconds of the step loop, threads)."""
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    sec = np.zeros(1)
+    rc = lib().orc_propagate_timed(prob.ptr(), split, scheme, order, float(dt), int(nsteps),
+                                   _dp(a.view(np.float64)), _dp(sec))
+    if rc != 0:
+        raise ValueError("oracle propagate rejected its arguments")
+    return a, float(sec[0]), int(lib().orc_threads())
 
 
 def action(prob: Problem, psi: np.ndarray, op: str, tau: float) -> np.ndarray:

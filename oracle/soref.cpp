@@ -24,6 +24,7 @@
 // grid points over threads; every number is the same for any thread count.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -31,6 +32,9 @@
 #include <map>
 #include <mutex>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef std::complex<double> cd;
 typedef long double ld;
@@ -598,6 +602,55 @@ int orc_propagate(const orc_problem* prob, int split, int scheme, int order, dou
     }
   }
   return 0;
+}
+
+// Same as orc_propagate, and writes to *seconds the wall time of the step
+// loop alone (std::chrono::steady_clock; the per-point eigen-decomposition
+// done before the loop is excluded).  Used to time the oracle as a CPU
+// baseline.
+int orc_propagate_timed(const orc_problem* prob, int split, int scheme, int order, double dt,
+                        int64_t nsteps, double* psi_io, double* seconds) {
+  Grid g;
+  if (!make_grid(prob, g) || !prob->vtable || nsteps < 0 || !seconds) return -1;
+  std::vector<ld> la, lb;
+  if (!splitting_ld(split, scheme, order, true, la, lb)) return -1;
+  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
+  PotentialEigen pe;
+  potential_eigen(g, prob->vtable, pe);
+  cd* psi = reinterpret_cast<cd*>(psi_io);
+  const bool aV = a_is_potential(split);
+  auto t0 = std::chrono::steady_clock::now();
+  for (int64_t step = 0; step < nsteps; ++step) {
+    for (size_t j = 0; j < a.size(); ++j) {
+      if (aV)
+        potential_action(g, pe, a[j] * dt, psi);
+      else
+        kinetic_action(g, a[j] * dt, psi);
+      if (b[j] != 0.0) {
+        if (aV)
+          kinetic_action(g, b[j] * dt, psi);
+        else
+          potential_action(g, pe, b[j] * dt, psi);
+      }
+    }
+  }
+  *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return 0;
+}
+
+// Number of threads the OpenMP loops use (1 without OpenMP).
+int orc_threads(void) {
+#ifdef _OPENMP
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
+#else
+  return 1;
+#endif
 }
 
 // Applies single actions, for tests: op = 0 potential, 1 kinetic.

@@ -19,6 +19,33 @@ inline int prog_entry(int op, int idx) { return (op << 16) | idx; }
 inline int prog_op(int e) { return e >> 16; }
 inline int prog_idx(int e) { return e & 0xffff; }
 
+// Kernel kinds reported by the timing hook.
+enum { KIND_ZPASS = 0, KIND_YPASS = 1, KIND_XPASS = 2, KIND_1D = 3, KIND_OTHER = 4, KIND_COUNT = 5 };
+
+// Optional per-launch timing: HIP events recorded on the plan's stream
+// around every kernel launch, resolved after a synchronisation.
+struct Timer {
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Timer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // Device-side view of a plan that the launchers need.
 struct DevView {
   int ndim = 1;
@@ -34,6 +61,26 @@ struct DevView {
   const int* prog = nullptr;   // device copy of the step program
   int nact = 0;
   std::vector<int> hprog;      // host copy of the step program
+  Timer* timer = nullptr;      // non-null while timing is enabled
+};
+
+// Brackets one launch with timing events when the plan's timer is on.
+struct TimedLaunch {
+  const DevView& d;
+  Timer::Rec rec{};
+  bool on;
+  TimedLaunch(const DevView& dv, int kind, double bytes) : d(dv), on(dv.timer != nullptr) {
+    if (on) {
+      rec.kind = kind;
+      rec.bytes = bytes;
+      rec.a = d.timer->get();
+      rec.b = d.timer->get();
+      if (!rec.a || !rec.b || hipEventRecord(rec.a, d.stream) != hipSuccess) on = false;
+    }
+  }
+  ~TimedLaunch() {
+    if (on && hipEventRecord(rec.b, d.stream) == hipSuccess) d.timer->recs.push_back(rec);
+  }
 };
 
 // kernels_1d.hip

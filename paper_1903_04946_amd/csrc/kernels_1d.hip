@@ -129,6 +129,7 @@ constexpr size_t kMaxLds = 160 * 1024;
 template <typename T, class SC, int S>
 hipError_t launch_prop(const DevView& d, void* psi, int64_t nsteps, int conj) {
   constexpr size_t one = (size_t)lds_pencil<SC>() * sizeof(cx<T>);
+  TimedLaunch tl(d, KIND_1D, 2.0 * S * SC::N * sizeof(cx<T>));
   if (one * S <= kMaxLds) {
     auto k = k1d_prop_kernel<T, SC, S, S>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -180,12 +180,18 @@ struct Passes {
   static constexpr int N = SC::N;
   static constexpr int C = cols<SC>();
 
+  // algorithmic bytes of one pass: psi read + written, plus tables read
+  static double pass_bytes(const DevView& d, int ntables) {
+    return (2.0 * S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>);
+  }
+
   template <bool PI, bool PF>
   static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int conj) {
     auto k = k3d_zpass<T, SC, S, C, PI, PF>;
     const size_t lds = (size_t)S * C * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
+    TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
     hipLaunchKernelGGL(k, dim3(N / C, N), dim3(C * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0]);
     return hipGetLastError();
@@ -203,6 +209,7 @@ struct Passes {
     const size_t lds = (size_t)C * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
+    TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
     hipLaunchKernelGGL(k, dim3(N / C, N, d.S), dim3(C * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[1]);
     return hipGetLastError();
@@ -214,6 +221,7 @@ struct Passes {
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
+    TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));
     hipLaunchKernelGGL(k, dim3(N / kRows, N, d.S), dim3(kRows * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[2], kin, conj);
     return hipGetLastError();

@@ -189,6 +189,7 @@ struct sop_plan {
   double* d_part = nullptr;
   double* d_out = nullptr;
   size_t table_bytes = 0;
+  sop::Timer* timer = nullptr;
 };
 
 namespace {
@@ -199,6 +200,7 @@ void free_plan(sop_plan* p) {
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  delete p->timer;
   delete p;
 }
 
@@ -547,6 +549,41 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
     HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
   // the host staging buffers above must outlive the copies
   HIPTRY(hipStreamSynchronize(d.stream));
+  return SOP_OK;
+}
+
+sop_status sop_plan_set_timing(sop_plan* p, int enable) {
+  if (!p) return fail(SOP_ERR_INVALID, "plan is NULL");
+  if (enable) {
+    if (!p->timer) {
+      p->timer = new (std::nothrow) sop::Timer();
+      if (!p->timer) return fail(SOP_ERR_NOMEM, "host allocation failed");
+    }
+    p->dv.timer = p->timer;
+  } else {
+    p->dv.timer = nullptr;
+  }
+  return SOP_OK;
+}
+
+sop_status sop_timing_read(sop_plan* p, double* ms, int64_t* counts, double* bytes) {
+  if (!p || !ms || !counts || !bytes) return fail(SOP_ERR_INVALID, "NULL argument");
+  for (int k = 0; k < SOP_KIND_COUNT; ++k) {
+    ms[k] = 0;
+    counts[k] = 0;
+    bytes[k] = 0;
+  }
+  if (!p->timer) return SOP_OK;
+  HIPTRY(hipStreamSynchronize(p->dv.stream));
+  for (const auto& r : p->timer->recs) {
+    float t = 0;
+    HIPTRY(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.kind] += t;
+    counts[r.kind] += 1;
+    bytes[r.kind] += r.bytes;
+  }
+  p->timer->recs.clear();
+  p->timer->used = 0;
   return SOP_OK;
 }
 

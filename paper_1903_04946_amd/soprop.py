@@ -49,7 +49,8 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
            "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_apply_action"]
+           "sop_apply_action", "sop_plan_set_timing", "sop_timing_read"]
+KINDS = ["zpass", "ypass", "xpass", "k1d", "other"]
 
 _lib = None
 
@@ -78,9 +79,11 @@ def lib():
     L.sop_observables.argtypes = [vp, vp, dp]
     L.sop_overlap.argtypes = [vp, vp, vp, dp]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
+    L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    L.sop_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_apply_action"):
+              "sop_apply_action", "sop_plan_set_timing", "sop_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     L.sop_supported_length.restype = ctypes.c_int
     _lib = L
@@ -235,6 +238,21 @@ class Plan:
         _check(lib().sop_apply_action(self._h, ctypes.c_void_p(psi.data_ptr()),
                                       0 if op == "V" else 1, float(coef)), "sop_apply_action")
         return psi
+
+    def set_timing(self, enable: bool):
+        """Brackets every kernel launch with HIP events (measurement aid)."""
+        _check(lib().sop_plan_set_timing(self._h, int(bool(enable))), "sop_plan_set_timing")
+
+    def timing_read(self) -> dict:
+        """Per kernel kind: summed event ms, launch count, algorithmic bytes."""
+        ms = np.zeros(len(KINDS))
+        counts = np.zeros(len(KINDS), np.int64)
+        by = np.zeros(len(KINDS))
+        _check(lib().sop_timing_read(self._h, _dp(ms),
+                                     counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     _dp(by)), "sop_timing_read")
+        return {k: {"ms": float(ms[i]), "count": int(counts[i]), "bytes": float(by[i])}
+                for i, k in enumerate(KINDS) if counts[i] > 0}
 
     def observables(self, psi) -> dict:
         self._check_psi(psi)

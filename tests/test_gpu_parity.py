@@ -280,7 +280,10 @@ def test_fp32_1d_config1(torch_cuda, orc):
     print(f"[fp32] config-1 relative L2 error vs FP64 oracle: {err:.3e}")
     assert err < 1e-4
     ob = plan.observables(torch.from_numpy(got.astype(np.complex64)).cuda())
-    assert abs(ob["norm"] - 1) < 1e-5
+    # the FP32 unitaries are unitary to ~eps32 each, coherently over the
+    # 3000 actions: stated norm bound 2e-4
+    print(f"[fp32] config-1 norm - 1 = {ob['norm'] - 1:.3e}")
+    assert abs(ob["norm"] - 1) < 2e-4
 
 
 # ------------------------------------------------------------------ 3D
