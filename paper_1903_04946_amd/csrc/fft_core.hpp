@@ -173,6 +173,39 @@ struct Sched {
   using Inv = Inv_;
 };
 
+// Global accesses through buffer resources: the descriptor (base, extent)
+// lives in SGPRs and every access takes one 32-bit VGPR offset, so all loads
+// and stores of a thread share a handful of offset registers.  Accesses
+// outside the extent read zero and drop writes instead of faulting.  The
+// fourth descriptor word 0x00020000 is the raw 32-bit data format of the
+// gfx9 family.
+typedef unsigned int sop_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int sop_u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const cx<T>* p, uint32_t nelem) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(p), (short)0,
+                                           (int)(nelem * (uint32_t)sizeof(cx<T>)), 0x00020000);
+}
+__device__ __forceinline__ cx<double> bld(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<double>*) {
+  sop_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(idx * 16u), 0, 0);
+  return __builtin_bit_cast(cx<double>, v);
+}
+__device__ __forceinline__ cx<float> bld(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<float>*) {
+  sop_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(idx * 8u), 0, 0);
+  return __builtin_bit_cast(cx<float>, v);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ld(__amdgpu_buffer_rsrc_t r, uint32_t idx) {
+  return bld(r, idx, (cx<T>*)nullptr);
+}
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<double> v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(sop_u32x4, v), r, (int)(idx * 16u), 0, 0);
+}
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<float> v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sop_u32x2, v), r, (int)(idx * 8u), 0, 0);
+}
+
 // Element index owned by thread t in register slot `slot` for a radix-R stage.
 template <int N, int E, int R>
 __device__ __forceinline__ int own_idx(int t, int slot) {

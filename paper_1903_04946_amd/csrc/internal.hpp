@@ -90,12 +90,16 @@ hipError_t k1d_fft_forward(const DevView& d, void* psi);
 
 // kernels_3d.hip
 bool k3d_supported(int n, int S);
+// Columns per z-pass tile; 3D potential tables are stored tile-contiguous
+// ([tile (y, x/C)][z][entry][x % C]) with this C.
+int k3d_table_tile(int n, bool f64);
 hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
 hipError_t k3d_fft_forward(const DevView& d, void* psi);
 
 // kernels_aux.hip
+// tile = 0: [u][entry][point] (1D); tile = C: the z-pass tile layout (3D).
 hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
-                     void* out);
+                     int tile, void* out);
 hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
                       const double* vraw_dev, const double* inv_mass, const double* dx,
                       double hbar, double* partials_dev, double* out_dev);

@@ -33,14 +33,40 @@ using Z64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
 using Z128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
 using Z256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
 
-// Columns per tile for the strided (y, z) passes: at least a full wave per
-// block and 128-byte contiguous segments in FP64.
+// Schedules of the single-pencil y and x passes: sixteen values per thread
+// where that saves an LDS exchange.
 template <class SC>
+struct XYSched {
+  using type = SC;
+};
+template <>
+struct XYSched<Z128> {
+  using type = Sched<128, 16, RList<16, 8>, RList<8, 16>, 16, 8>;
+};
+template <>
+struct XYSched<Z256> {
+  using type = Sched<256, 16, RList<16, 16>, RList<16, 16>, 16, 16>;
+};
+
+// Columns per tile of the y-pass: at least a full wave per block and
+// 128-byte contiguous row segments.
+template <class SC, typename T>
 constexpr int cols() {
-  return SC::TPC >= 8 ? 8 : 64 / SC::TPC;
+  constexpr int seg = 128 / (int)sizeof(cx<T>);
+  return SC::TPC * seg >= 64 ? seg : 64 / SC::TPC;
+}
+// Columns per tile of the z-pass (16 in both precisions: 256-byte FP64 and
+// 128-byte FP32 segments of psi; the potential table is stored
+// tile-contiguous, see below).
+template <class SC, typename T>
+constexpr int zcols() {
+  return 16;
 }
 
 // ---------------------------------------------------------------- z-pass
+// Potential tables are stored per z-pass tile: for table u, tile
+// (y, x / C) holds [z][entry][x % C] contiguously, N * NE * C complex, so a
+// tile reads its table as one contiguous stream.
 template <typename T, class SC, int S, int C, bool PRE_INV, bool POST_FWD>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
@@ -51,17 +77,23 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
   const int x = blockIdx.x * C + col, y = blockIdx.y;
-  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
-  const int64_t off0 = (int64_t)y * N + x;
-  const LayStrided lay{col, C, S * C};
+  constexpr uint32_t plane = (uint32_t)N * N;
+  constexpr int64_t npts = (int64_t)plane * N;
+  constexpr uint32_t tile = (uint32_t)N * NE * C;
+  const uint32_t off0 = (uint32_t)y * N + x;
+  const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
+  const LayStrided lay{col, 0, C};  // one surface at a time through LDS
   cx<T> v[S][E];
   constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
 #pragma unroll
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < S; ++s) {
+    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = psi[s * npts + own_idx<N, E, RIN>(t, q) * plane + off0];
+    for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
+  }
   if constexpr (PRE_INV) {
-    fft_inverse<SC, S>(v, lds, lay, tw, t);
+#pragma unroll
+    for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
     // normalisation of the z round trip (exact for power-of-two N)
     constexpr T inv_n = (T)1 / (T)N;
 #pragma unroll
@@ -70,15 +102,15 @@ __global__ void __launch_bounds__(C * SC::TPC)
       for (int q = 0; q < E; ++q) v[s][q] = cx<T>{v[s][q].re * inv_n, v[s][q].im * inv_n};
   }
   const T csign = conj ? (T)-1 : (T)1;
-  for (int a = 0; a < nv; ++a) {
-    const cx<T>* U = vexp + (size_t)(a == 0 ? iv0 : iv1) * NE * npts + off0;
+  auto vact = [&](int iv) {
+    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int64_t zo = (int64_t)own_idx<N, E, SC::RF>(t, q) * plane;
+      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * C) + col;
       cx<T> u[NE];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        u[e] = U[e * npts + zo];
+        u[e] = ld<T>(ru, pt + e * C);
         u[e].im *= csign;
       }
       cx<T> w[S];
@@ -88,13 +120,20 @@ __global__ void __launch_bounds__(C * SC::TPC)
 #pragma unroll
       for (int s = 0; s < S; ++s) v[s][q] = w[s];
     }
+  };
+  if (nv >= 1) vact(iv0);
+  if (nv >= 2) vact(iv1);
+  if constexpr (POST_FWD) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
   }
-  if constexpr (POST_FWD) fft_forward<SC, S>(v, lds, lay, tw, t);
   constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
 #pragma unroll
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < S; ++s) {
+    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
 #pragma unroll
-    for (int q = 0; q < E; ++q) psi[s * npts + own_idx<N, E, ROUT>(t, q) * plane + off0] = v[s][q];
+    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
+  }
 }
 
 // ---------------------------------------------------------------- y-pass
@@ -108,19 +147,19 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const int col = lane % C, t = lane / C;
   const int x = blockIdx.x * C + col, z = blockIdx.y, s = blockIdx.z;
   constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
-  cx<T>* base = psi + s * npts + z * plane + x;
+  const auto base = rsrc(psi + s * npts + z * plane, (uint32_t)plane);
   const LayStrided lay{col, 0, C};
   cx<T> v[1][E];
   constexpr int RIN = INV ? SC::RL : SC::RF;
   constexpr int ROUT = INV ? SC::RF : SC::RL;
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = base[own_idx<N, E, RIN>(t, q) * N];
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) * N + x);
   if constexpr (INV)
     fft_inverse<SC, 1>(v, lds, lay, tw, t);
   else
     fft_forward<SC, 1>(v, lds, lay, tw, t);
 #pragma unroll
-  for (int q = 0; q < E; ++q) base[own_idx<N, E, ROUT>(t, q) * N] = v[0][q];
+  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) * N + x, v[0][q]);
 }
 
 // ---------------------------------------------------------------- x-pass
@@ -137,12 +176,13 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
   const int t = lane % TPC, row = lane / TPC;
   const int y = blockIdx.x * ROWS + row, z = blockIdx.y, s = blockIdx.z;
   constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
-  cx<T>* base = psi + s * npts + z * plane + (int64_t)y * N;
+  const auto base = rsrc(psi + s * npts + z * plane, (uint32_t)plane);
+  const uint32_t yo = (uint32_t)y * N;
   const LayPadded lay{row * (N + N / 16), 0};
   cx<T> v[1][E];
   constexpr int RIN = MODE == XP_INV ? SC::RL : SC::RF;
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = base[own_idx<N, E, RIN>(t, q)];
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) + yo);
   if constexpr (MODE == XP_INV) {
     fft_inverse<SC, 1>(v, lds, lay, tw, t);
   } else {
@@ -162,10 +202,8 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
   }
   constexpr int ROUT = MODE == XP_FWD ? SC::RL : SC::RF;
 #pragma unroll
-  for (int q = 0; q < E; ++q) base[own_idx<N, E, ROUT>(t, q)] = v[0][q];
+  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) + yo, v[0][q]);
 }
-
-constexpr int kRows = 8;
 
 // ---------------------------------------------------------------- launchers
 template <typename K>
@@ -178,7 +216,17 @@ hipError_t set_lds(K k, size_t bytes) {
 template <typename T, class SC, int S>
 struct Passes {
   static constexpr int N = SC::N;
-  static constexpr int C = cols<SC>();
+  using XS = typename XYSched<SC>::type;
+  static constexpr int C = cols<XS, T>();
+  static constexpr int CZ = zcols<SC, T>();
+  // rows per x-pass block: about 128 threads, and a divisor of N
+  static constexpr int rows() {
+    int r = XS::TPC >= 16 ? 8 : 128 / XS::TPC;
+    while (N % r != 0) r /= 2;
+    return r;
+  }
+  static constexpr int ROWS = rows();
+  static_assert(N % C == 0 && N % CZ == 0 && N % ROWS == 0, "tiles must cover the grid");
 
   // algorithmic bytes of one pass: psi read + written, plus tables read
   static double pass_bytes(const DevView& d, int ntables) {
@@ -187,12 +235,12 @@ struct Passes {
 
   template <bool PI, bool PF>
   static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int conj) {
-    auto k = k3d_zpass<T, SC, S, C, PI, PF>;
-    const size_t lds = (size_t)S * C * N * sizeof(cx<T>);
+    auto k = k3d_zpass<T, SC, S, CZ, PI, PF>;
+    const size_t lds = (size_t)CZ * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
-    hipLaunchKernelGGL(k, dim3(N / C, N), dim3(C * SC::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / CZ, N), dim3(CZ * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0]);
     return hipGetLastError();
   }
@@ -205,24 +253,24 @@ struct Passes {
   }
   template <bool INV>
   static hipError_t ypass(const DevView& d, cx<T>* psi) {
-    auto k = k3d_ypass<T, SC, C, INV>;
+    auto k = k3d_ypass<T, XS, C, INV>;
     const size_t lds = (size_t)C * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
-    hipLaunchKernelGGL(k, dim3(N / C, N, d.S), dim3(C * SC::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / C, N, d.S), dim3(C * XS::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[1]);
     return hipGetLastError();
   }
   template <int MODE>
   static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj) {
-    auto k = k3d_xpass<T, SC, kRows, MODE>;
-    const size_t lds = (size_t)kRows * (N + N / 16) * sizeof(cx<T>);
+    auto k = k3d_xpass<T, XS, ROWS, MODE>;
+    const size_t lds = (size_t)ROWS * (N + N / 16) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
     TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));
-    hipLaunchKernelGGL(k, dim3(N / kRows, N, d.S), dim3(kRows * SC::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S), dim3(ROWS * XS::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[2], kin, conj);
     return hipGetLastError();
   }
@@ -311,6 +359,11 @@ hipError_t dispatch(int n, int S, bool f64, F&& f) {
 }
 
 }  // namespace
+
+int k3d_table_tile(int n, bool f64) {
+  (void)n;
+  return f64 ? zcols<Z128, double>() : zcols<Z128, float>();
+}
 
 bool k3d_supported(int n, int S) {
   if (S < 1 || S > 3) return false;

@@ -8,7 +8,8 @@
 // FP64; for every unique coefficient c the complex-symmetric
 // exp(-i tau V/hbar) = R diag(exp(-i lambda tau/hbar)) R^T, tau = c dt, is
 // formed in FP64 and rounded once to the plan precision; its packed upper
-// triangle is stored structure-of-arrays, [unique][entry][point].
+// triangle is stored structure-of-arrays, [unique][entry][point] for 1D
+// grids, or tile-contiguous for the 3D z-pass ([unique][tile][z][entry][col]).
 //
 // Reductions: norm, surface populations and <V> from psi, <T> from its
 // forward transform, and <psi|phi>; every sum is FP64 with a fixed block
@@ -73,10 +74,21 @@ __device__ void jacobi_sym(double (&A)[S][S], double (&R)[S][S]) {
   }
 }
 
+// Destination index of (table u, entry e, point x): structure of arrays for
+// 1D (tile = 0) or the z-pass tile layout for a cubic 3D grid of side n.
+__device__ __forceinline__ int64_t table_index(int64_t npts, int NE, int tile, int n, int u, int e,
+                                               int64_t x) {
+  if (tile == 0) return ((int64_t)u * NE + e) * npts + x;
+  const int64_t plane = (int64_t)n * n;
+  const int64_t z = x / plane, y = (x / n) % n, xx = x % n;
+  const int64_t tl = y * (n / tile) + xx / tile;
+  return (int64_t)u * NE * npts + tl * ((int64_t)n * NE * tile) + (z * NE + e) * tile + xx % tile;
+}
+
 template <typename T, int S>
 __global__ void __launch_bounds__(256)
     k_form_vexp(const double* __restrict__ vraw, int64_t npts, const double* __restrict__ taus,
-                int ntau, cx<T>* __restrict__ out) {
+                int ntau, int tile, int n, cx<T>* __restrict__ out) {
   constexpr int NE = S * (S + 1) / 2;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
        x += (int64_t)gridDim.x * blockDim.x) {
@@ -108,7 +120,7 @@ __global__ void __launch_bounds__(256)
             re += rr * ere[l];
             im += rr * eim[l];
           }
-          out[((int64_t)u * NE + ee) * npts + x] = cx<T>{(T)re, (T)im};
+          out[table_index(npts, NE, tile, n, u, ee, x)] = cx<T>{(T)re, (T)im};
           ++ee;
         }
     }
@@ -236,12 +248,12 @@ __global__ void __launch_bounds__(kReduceThreads)
 }
 
 template <int S, typename T>
-hipError_t form_impl(const DevView& d, const double* vraw, const double* taus, int ntau,
+hipError_t form_impl(const DevView& d, const double* vraw, const double* taus, int ntau, int tile,
                      void* out) {
   int blocks = (int)((d.npts + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((k_form_vexp<T, S>), dim3(blocks), dim3(256), 0, d.stream, vraw, d.npts,
-                     taus, ntau, (cx<T>*)out);
+                     taus, ntau, tile, d.n[0], (cx<T>*)out);
   return hipGetLastError();
 }
 
@@ -256,14 +268,14 @@ hipError_t obs_points_impl(const DevView& d, const void* psi, const double* vraw
 }  // namespace
 
 hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
-                     void* out) {
+                     int tile, void* out) {
   switch (d.S) {
-    case 1: return d.f64 ? form_impl<1, double>(d, vraw_dev, taus, ntau, out)
-                         : form_impl<1, float>(d, vraw_dev, taus, ntau, out);
-    case 2: return d.f64 ? form_impl<2, double>(d, vraw_dev, taus, ntau, out)
-                         : form_impl<2, float>(d, vraw_dev, taus, ntau, out);
-    case 3: return d.f64 ? form_impl<3, double>(d, vraw_dev, taus, ntau, out)
-                         : form_impl<3, float>(d, vraw_dev, taus, ntau, out);
+    case 1: return d.f64 ? form_impl<1, double>(d, vraw_dev, taus, ntau, tile, out)
+                         : form_impl<1, float>(d, vraw_dev, taus, ntau, tile, out);
+    case 2: return d.f64 ? form_impl<2, double>(d, vraw_dev, taus, ntau, tile, out)
+                         : form_impl<2, float>(d, vraw_dev, taus, ntau, tile, out);
+    case 3: return d.f64 ? form_impl<3, double>(d, vraw_dev, taus, ntau, tile, out)
+                         : form_impl<3, float>(d, vraw_dev, taus, ntau, tile, out);
     default: return hipErrorInvalidValue;
   }
 }

@@ -189,6 +189,7 @@ struct sop_plan {
   double* d_part = nullptr;
   double* d_out = nullptr;
   size_t table_bytes = 0;
+  int tile = 0;  // potential-table layout (0 = [u][entry][point])
   sop::Timer* timer = nullptr;
 };
 
@@ -425,7 +426,8 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   d.nact = (int)prog.size();
   d.hprog = prog;
 
-  HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->d_vexp));
+  p->tile = p->ndim == 3 ? sop::k3d_table_tile(p->n[0], f64) : 0;
+  HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
   HIPTRY(hipStreamSynchronize(stream));
   guard.keep = true;
   *out = p;
@@ -528,7 +530,7 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
     const double tau = (double)((ld)coef * (ld)p->dt / (ld)p->hbar);
     HIPTRY(hipMemcpyAsync(p->d_taus + p->vtaus.size(), &tau, sizeof(double),
                           hipMemcpyHostToDevice, d.stream));
-    HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->d_atab));
+    HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->tile, p->d_atab));
     d.vexp = p->d_atab;
     d.prog = p->d_prog1;
     d.hprog = {sop::prog_entry(sop::OP_V, 0)};
