@@ -74,12 +74,17 @@ def lib():
         L.orc_propagate_timed.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_threads.argtypes = []
+        L.orc_expm_frechet.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double,
+                                       dp, dp]
+        L.orc_gradient.argtypes = [pp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp, dp]
         L.orc_observables.argtypes = [pp, dp, dp]
         L.orc_overlap.argtypes = [pp, dp, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
-                  "orc_exact", "orc_propagate_timed", "orc_threads"):
+                  "orc_exact", "orc_propagate_timed", "orc_threads", "orc_expm_frechet",
+                  "orc_gradient"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +210,34 @@ def propagate_timed(prob: Problem, psi: np.ndarray, split: int, scheme: int, ord
     if rc != 0:
         raise ValueError("oracle propagate rejected its arguments")
     return a, float(sec[0]), int(lib().orc_threads())
+
+
+def expm_frechet(V: np.ndarray, D: np.ndarray, tau: float, hbar: float = 1.0):
+    """(exp(-i tau V/hbar), its Frechet derivative in direction D)."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    S = V.shape[0]
+    U = np.zeros((S, S), np.complex128)
+    L = np.zeros((S, S), np.complex128)
+    lib().orc_expm_frechet(S, _dp(V), _dp(D), tau, hbar, _dp(U.view(np.float64)),
+                           _dp(L.view(np.float64)))
+    return U, L
+
+
+def gradient(prob: Problem, dvtables: np.ndarray, psi0: np.ndarray, split: int, scheme: int,
+             order: int, dt: float, nsteps: int, weights):
+    """(populations at the end, sum_s w_s dP_s/dtheta_k) by tangent propagation."""
+    dv = np.ascontiguousarray(dvtables, dtype=np.float64)
+    npar = dv.shape[0]
+    a = np.ascontiguousarray(psi0, dtype=np.complex128).reshape(prob.shape)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    pops = np.zeros(prob.nsurf)
+    grad = np.zeros(max(npar, 1))
+    rc = lib().orc_gradient(prob.ptr(), npar, _dp(dv), split, scheme, order, float(dt),
+                            int(nsteps), _dp(a.view(np.float64)), _dp(w), _dp(pops), _dp(grad))
+    if rc != 0:
+        raise ValueError("oracle gradient rejected its arguments")
+    return pops, grad[:npar]
 
 
 def action(prob: Problem, psi: np.ndarray, op: str, tau: float) -> np.ndarray:

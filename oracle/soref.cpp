@@ -796,3 +796,175 @@ int orc_exact(const orc_problem* prob, double t, double* psi_io) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- gradients
+// Derivatives of surface populations with respect to parameters theta_k of
+// a potential linear in them, V(theta) = V + sum_k theta_k D_k, by forward
+// (tangent) propagation of d psi / d theta_k alongside psi.  Kinetic actions
+// do not depend on theta; a potential action psi <- U psi with
+// U = exp(-i tau V / hbar) gives d psi <- U d psi + L_k psi, where L_k is the
+// Frechet derivative of the exponential in direction D_k, read off the
+// upper-right block of exp([[A, E], [0, A]]) with A = -i tau V / hbar,
+// E = -i tau D_k / hbar.  That block exponential is evaluated in long double
+// by scaling and squaring of its Taylor series.
+
+typedef std::complex<ld> cl;
+
+// exp(M) for an n x n complex matrix (row-major), scaling and squaring.
+static void expm_taylor(int n, const std::vector<cl>& M, std::vector<cl>& out) {
+  ld norm = 0;
+  for (int i = 0; i < n; ++i) {
+    ld row = 0;
+    for (int j = 0; j < n; ++j) row += std::abs(M[(size_t)i * n + j]);
+    norm = std::max(norm, row);
+  }
+  int sq = 0;
+  while (norm > 0.25L) {
+    norm /= 2;
+    ++sq;
+  }
+  const ld scale = std::ldexp(1.0L, -sq);
+  std::vector<cl> A(M), term((size_t)n * n), next((size_t)n * n);
+  for (auto& a : A) a *= scale;
+  out.assign((size_t)n * n, cl(0, 0));
+  for (int i = 0; i < n; ++i) out[(size_t)i * n + i] = 1;
+  term = out;  // identity
+  for (int k = 1; k <= 30; ++k) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        cl acc(0, 0);
+        for (int l = 0; l < n; ++l) acc += term[(size_t)i * n + l] * A[(size_t)l * n + j];
+        next[(size_t)i * n + j] = acc / (ld)k;
+      }
+    term.swap(next);
+    for (size_t q = 0; q < out.size(); ++q) out[q] += term[q];
+  }
+  for (int r = 0; r < sq; ++r) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        cl acc(0, 0);
+        for (int l = 0; l < n; ++l) acc += out[(size_t)i * n + l] * out[(size_t)l * n + j];
+        next[(size_t)i * n + j] = acc;
+      }
+    out.swap(next);
+  }
+}
+
+// U = exp(-i tau V/hbar) and L = its Frechet derivative in direction D, both
+// S x S complex (double), from the 2S x 2S block exponential.
+static void expm_frechet_point(int S, const double* V, const double* D, double tau, double hbar,
+                               cd* U, cd* L) {
+  const int n = 2 * S;
+  std::vector<cl> M((size_t)n * n, cl(0, 0)), E;
+  const cl f(0, -(ld)tau / (ld)hbar);
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j) {
+      M[(size_t)i * n + j] = f * (ld)V[i * S + j];
+      M[(size_t)(i + S) * n + (j + S)] = f * (ld)V[i * S + j];
+      M[(size_t)i * n + (j + S)] = f * (ld)D[i * S + j];
+    }
+  expm_taylor(n, M, E);
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j) {
+      if (U) U[i * S + j] = cd((double)E[(size_t)i * n + j].real(), (double)E[(size_t)i * n + j].imag());
+      if (L)
+        L[i * S + j] = cd((double)E[(size_t)i * n + j + S].real(), (double)E[(size_t)i * n + j + S].imag());
+    }
+}
+
+static void unpack_matrix(int S, const double* table, int64_t npts, int64_t x, double* M) {
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j) M[i * S + j] = table[(int64_t)packed_index(S, i, j) * npts + x];
+}
+
+extern "C" {
+
+// Frechet derivative of exp(-i tau V / hbar) in direction D (real symmetric
+// S x S, row-major); U and L receive S x S complex (interleaved).
+int orc_expm_frechet(int S, const double* V, const double* D, double tau, double hbar, double* U,
+                     double* L) {
+  if (S < 1 || S > 16) return -1;
+  expm_frechet_point(S, V, D, tau, hbar, reinterpret_cast<cd*>(U), reinterpret_cast<cd*>(L));
+  return 0;
+}
+
+// Populations P_s(T) of psi propagated nsteps steps (pruned sequence) and
+// grad[k] = sum_s weights[s] dP_s/dtheta_k, by tangent propagation.
+// dvtables: [nparams][S(S+1)/2][npts] packed like the V-table.
+// pops: [S] out; grad: [nparams] out.  Returns 0 or -1.
+int orc_gradient(const orc_problem* prob, int nparams, const double* dvtables, int split,
+                 int scheme, int order, double dt, int64_t nsteps, const double* psi0,
+                 const double* weights, double* pops, double* grad) {
+  Grid g;
+  if (!make_grid(prob, g) || !prob->vtable || nparams < 0 || nsteps < 0) return -1;
+  std::vector<ld> la, lb;
+  if (!splitting_ld(split, scheme, order, true, la, lb)) return -1;
+  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
+  const int S = g.S;
+  const int64_t n = (int64_t)S * g.npts;
+  std::vector<cd> psi(reinterpret_cast<const cd*>(psi0), reinterpret_cast<const cd*>(psi0) + n);
+  std::vector<std::vector<cd>> dpsi(nparams, std::vector<cd>(n, cd(0, 0)));
+  const bool aV = a_is_potential(split);
+
+  auto potential = [&](double tau) {
+#pragma omp parallel
+    {
+      std::vector<double> V((size_t)S * S), D((size_t)S * S);
+      std::vector<cd> U((size_t)S * S), L((size_t)S * S), v(S), w(S);
+#pragma omp for schedule(static)
+      for (int64_t x = 0; x < g.npts; ++x) {
+        unpack_matrix(S, prob->vtable, g.npts, x, V.data());
+        for (int s = 0; s < S; ++s) v[s] = psi[s * g.npts + x];
+        for (int k = 0; k < nparams; ++k) {
+          unpack_matrix(S, dvtables + (int64_t)k * (S * (S + 1) / 2) * g.npts, g.npts, x, D.data());
+          expm_frechet_point(S, V.data(), D.data(), tau, g.hbar, U.data(), L.data());
+          for (int i = 0; i < S; ++i) {
+            cd acc(0, 0);
+            for (int j = 0; j < S; ++j)
+              acc += U[i * S + j] * dpsi[k][j * g.npts + x] + L[i * S + j] * v[j];
+            w[i] = acc;
+          }
+          for (int s = 0; s < S; ++s) dpsi[k][s * g.npts + x] = w[s];
+        }
+        if (nparams == 0) {
+          std::vector<double> Z((size_t)S * S, 0.0);
+          expm_frechet_point(S, V.data(), Z.data(), tau, g.hbar, U.data(), nullptr);
+        }
+        for (int i = 0; i < S; ++i) {
+          cd acc(0, 0);
+          for (int j = 0; j < S; ++j) acc += U[i * S + j] * v[j];
+          psi[i * g.npts + x] = acc;
+        }
+      }
+    }
+  };
+  auto kinetic = [&](double tau) {
+    kinetic_action(g, tau, psi.data());
+    for (int k = 0; k < nparams; ++k) kinetic_action(g, tau, dpsi[k].data());
+  };
+  for (int64_t step = 0; step < nsteps; ++step) {
+    for (size_t j = 0; j < a.size(); ++j) {
+      if (aV) potential(a[j] * dt); else kinetic(a[j] * dt);
+      if (b[j] != 0.0) {
+        if (aV) kinetic(b[j] * dt); else potential(b[j] * dt);
+      }
+    }
+  }
+  for (int s = 0; s < S; ++s) {
+    ld acc = 0;
+    for (int64_t x = 0; x < g.npts; ++x) acc += (ld)std::norm(psi[s * g.npts + x]);
+    pops[s] = (double)(acc * (ld)g.dV);
+  }
+  for (int k = 0; k < nparams; ++k) {
+    ld acc = 0;
+    for (int s = 0; s < S; ++s)
+      for (int64_t x = 0; x < g.npts; ++x) {
+        const cd z = std::conj(psi[s * g.npts + x]) * dpsi[k][s * g.npts + x];
+        acc += (ld)weights[s] * 2.0L * (ld)z.real();
+      }
+    grad[k] = (double)(acc * (ld)g.dV);
+  }
+  return 0;
+}
+
+}  // extern "C"
