@@ -97,6 +97,12 @@ typedef struct {
   double dt;              /* time step, nonzero, finite */
   double hbar;            /* > 0 */
   sop_dtype dtype;
+  /* Optional parameters theta_k of a potential linear in them,
+   * V(theta) = vtable + sum_k theta_k dvtables[k] (vtable is V at theta = 0),
+   * for sop_plan_set_params and the adjoint.  nparams = 0 and dvtables = NULL
+   * when unused; at most 8.  dvtables: host, [nparams][S(S+1)/2][npts]. */
+  int nparams;
+  const double* dvtables;
 } sop_plan_desc;
 
 /* Sizes of a plan (Table II quantities for its scheme and order). */
@@ -177,6 +183,42 @@ sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev,
  * exp(-i tau V/hbar) with tau = coef * dt, op = 1 kinetic exp(-i tau T/hbar).
  * The table for coef is formed on the fly into the plan's scratch. */
 sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
+
+/* Sets the parameters: V <- vtable + sum_k theta[k] dvtables[k], and forms the
+ * potential tables again on the device (theta: host, [nparams]).
+ * Synchronises.  SOP_ERR_STATE if the plan has no parameters. */
+sop_status sop_plan_set_params(sop_plan* plan, const double* theta);
+
+/* Adjoint (reverse-mode) derivatives of the final surface populations
+ * P_s(T) = ||psi_s(T)||^2 dV with respect to the plan's parameters, for
+ * FP64 plans on 3D grids of 32, 64, 128 or 256 points per axis.
+ *
+ * The gradient of L = sum_s w_s P_s is 2 dV sum_j Re <lambda_j| dU_j/dtheta_k
+ * |psi_{j-1}> over the potential actions j, with lambda_j = (U_N..U_{j+1})^dag
+ * W psi_T (Sec. "Geometric properties of the exact evolution operator": the
+ * propagator is unitary, so U^dag = U^{-1} = U(-dt), conjugated tables).
+ * The backward sweep applies U_j^dag to lambda and to psi together, so psi
+ * is recomputed by time reversibility (symmetric compositions are exactly
+ * reversible, Appendix A) instead of stored; every K steps the stored
+ * forward state replaces the recomputed one (checkpoints).  dU_j/dtheta_k
+ * is the Frechet derivative of exp(-i tau V) in direction dvtables[k], in
+ * the divided-difference (Daleckii-Krein) form in V's eigenbasis.
+ *
+ * Workspace: caller-owned device memory of sop_adjoint_workspace_bytes
+ * bytes; it holds psi(T) (its first S*npts complex values), lambda, the
+ * gradient accumulator and ceil(nsteps/K) checkpoints. */
+sop_status sop_adjoint_workspace_bytes(const sop_plan* plan, int64_t nsteps, int K,
+                                       size_t* bytes);
+/* Forward sweep from psi0_dev (not modified): propagates nsteps steps in the
+ * workspace, storing checkpoints, and writes P_s(T) to pops_out[S] (host).
+ * Synchronises. */
+sop_status sop_adjoint_forward(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int K,
+                               void* workspace_dev, double* pops_out);
+/* Backward sweep after sop_adjoint_forward with the same nsteps and K:
+ * grad_out[k] = sum_s weights[s] dP_s/dtheta_k (host arrays [S], [nparams]).
+ * Synchronises.  The workspace's psi is consumed. */
+sop_status sop_adjoint_backward(sop_plan* plan, int64_t nsteps, int K, const double* weights,
+                                void* workspace_dev, double* grad_out);
 
 /* Per-kernel timing (measurement aid).  While enabled, every kernel launch
  * of the plan is bracketed by HIP events on the plan's stream.

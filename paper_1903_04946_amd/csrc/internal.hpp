@@ -88,8 +88,19 @@ bool k1d_supported(int n, int S);
 hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
 hipError_t k1d_fft_forward(const DevView& d, void* psi);
 
+// Device buffers of an adjoint sweep (FP64 only).
+struct AdjointView {
+  void* stacked = nullptr;      // [2S][npts] complex: psi then lambda
+  const void* eig = nullptr;    // R and lam per point, z-pass tile layout, S(S+1)/2 pairs
+  double* qacc = nullptr;       // [S(S+1)/2][npts] packed gradient accumulator
+  const double* taus = nullptr; // c dt / hbar of each potential table
+  const void* checkpoints = nullptr;  // [ncp][S][npts] complex, psi at steps 0, K, 2K, ...
+};
+
 // kernels_3d.hip
 bool k3d_supported(int n, int S);
+bool k3d_adjoint_supported(int n, int S, bool f64);
+hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps, int K);
 // Columns per z-pass tile; 3D potential tables are stored tile-contiguous
 // ([tile (y, x/C)][z][entry][x % C]) with this C.
 int k3d_table_tile(int n, bool f64);
@@ -105,6 +116,17 @@ hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
                       double hbar, double* partials_dev, double* out_dev);
 hipError_t overlap_reduce(const DevView& d, const void* psi, const void* phi,
                           double* partials_dev, double* out_dev);
+hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* out);
+hipError_t set_vparams(const DevView& d, double* vraw, const double* vbase, const double* dv,
+                       const double* delta_dev, int nparams);
+hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const double* w_dev,
+                        double* qacc);
+hipError_t grad_reduce(const DevView& d, const double* qacc, const double* dv, int nparams,
+                       double* partials, double* out_dev);
+// out_dev[0..S) = sum |psi_s|^2, out_dev[S] = sum psi^dag V psi (raw sums)
+hipError_t pops_reduce(const DevView& d, const void* psi, const double* vraw_dev,
+                       double* partials, double* out_dev);
+constexpr int kMaxParams = 8;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 

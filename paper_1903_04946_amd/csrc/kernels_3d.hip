@@ -19,6 +19,7 @@
 // of each unique coefficient.  The 1/n_z of the z round trip is applied by
 // the z-pass after its inverse transform, because consecutive kinetic
 // actions (TVT at a step boundary) share one z round trip.
+#include <type_traits>
 #include <vector>
 
 #include "fft_core.hpp"
@@ -32,6 +33,27 @@ using Z48 = Sched<48, 12, RList<4, 4, 3>, RList<3, 4, 4>, 4, 3>;
 using Z64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
 using Z128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
 using Z256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
+
+// Schedules of the adjoint z-pass (2S pencils per thread): four values per
+// thread and pencil.
+template <class SC>
+struct AdjSched;
+template <>
+struct AdjSched<Z32> {
+  using type = Sched<32, 4, RList<4, 4, 2>, RList<2, 4, 4>, 4, 2>;
+};
+template <>
+struct AdjSched<Z64> {
+  using type = Sched<64, 4, RList<4, 4, 4>, RList<4, 4, 4>, 4, 4>;
+};
+template <>
+struct AdjSched<Z128> {
+  using type = Sched<128, 4, RList<4, 4, 4, 2>, RList<2, 4, 4, 4>, 4, 2>;
+};
+template <>
+struct AdjSched<Z256> {
+  using type = Sched<256, 4, RList<4, 4, 4, 4>, RList<4, 4, 4, 4>, 4, 4>;
+};
 
 // Schedules of the single-pencil y and x passes: sixteen values per thread
 // where that saves an LDS exchange.
@@ -131,6 +153,153 @@ __global__ void __launch_bounds__(C * SC::TPC)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
+#pragma unroll
+    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
+  }
+}
+
+// ---------------------------------------------------------------- adjoint z-pass
+// Backward sweep of the adjoint method over the stacked state [psi; lambda]
+// (2S pencils, FP64).  For each potential action j, walked in reverse, the
+// kernel holds psi_j (the state after the action) and lambda_j (the adjoint
+// after it) and computes
+//   psi_{j-1} = U_j^dag psi_j,   lambda_{j-1} = U_j^dag lambda_j,
+//   Q(x) += R Re(M) R^T,  M_ab = conj(alpha_a) F_ab beta_b,
+// with alpha = R^T lambda_j, beta = R^T psi_{j-1}, V(x) = R diag(lam) R^T and
+// the divided differences of f(v) = exp(-i tau v):
+//   F_ab = (f(lam_a) - f(lam_b)) / (lam_a - lam_b)
+//        = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2),
+// so that d P / d theta_k = 2 dV sum_x sum_ij Q_ij(x) D_k,ij(x) (Daleckii-
+// Krein form of the Frechet derivative of exp(-i tau V(theta))).  Q is kept
+// packed (Q_ii; Q_ij + Q_ji for i < j) in qacc[entry][point].
+template <class SC, int S, int C, bool PRE_INV, bool POST_FWD>
+__global__ void __launch_bounds__(C * SC::TPC)
+    k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ vexp,
+                  const cx<double>* __restrict__ eig, double* __restrict__ qacc,
+                  const double* __restrict__ taus, int nv, int iv0, int iv1,
+                  const cx<double>* __restrict__ tw) {
+  extern __shared__ char smem_raw[];
+  cx<double>* lds = reinterpret_cast<cx<double>*>(smem_raw);
+  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2, P = 2 * S;
+  const int lane = threadIdx.x;
+  const int col = lane % C, t = lane / C;
+  const int x = blockIdx.x * C + col, y = blockIdx.y;
+  constexpr uint32_t plane = (uint32_t)N * N;
+  constexpr int64_t npts = (int64_t)plane * N;
+  constexpr uint32_t tile = (uint32_t)N * NE * C;
+  const uint32_t off0 = (uint32_t)y * N + x;
+  const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
+  const LayStrided lay{col, 0, C};
+  cx<double> v[P][E];
+  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const auto rs = rsrc(stk + s * npts, (uint32_t)npts);
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[s][q] = ld<double>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
+  }
+  if constexpr (PRE_INV) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
+    constexpr double inv_n = 1.0 / (double)N;
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[s][q] = cx<double>{v[s][q].re * inv_n, v[s][q].im * inv_n};
+  }
+  auto vact = [&](int iv) {
+    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
+    const auto rg = rsrc(eig + tbase, tile);
+    const double tau = taus[iv];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * C) + col;
+      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * plane + off0;
+      cx<double> u[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        u[e] = ld<double>(ru, tp + e * C);
+        u[e].im = -u[e].im;  // U^dag = conj(U) for complex-symmetric U
+      }
+      double ev[2 * NE];  // R (row-major S x S) then lam (S)
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const cx<double> w = ld<double>(rg, tp + e * C);
+        ev[2 * e] = w.re;
+        ev[2 * e + 1] = w.im;
+      }
+      cx<double> ps[S], la[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        ps[s] = v[s][q];
+        la[s] = v[S + s][q];
+      }
+      apply_u<double, S>(ps, u);  // psi_{j-1}
+      // alpha = R^T lambda_j, beta = R^T psi_{j-1}
+      cx<double> al[S], be[S];
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        al[a] = cx<double>{0.0, 0.0};
+        be[a] = cx<double>{0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double r = ev[i * S + a];
+          al[a] = cx<double>{al[a].re + r * la[i].re, al[a].im + r * la[i].im};
+          be[a] = cx<double>{be[a].re + r * ps[i].re, be[a].im + r * ps[i].im};
+        }
+      }
+      const double* lam = ev + S * S;
+      double rm[S][S];  // Re(M)
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+          // F_ab = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2)
+          const double h = 0.5 * tau * (lam[a] - lam[b]);
+          const double sc = (fabs(h) < 1e-8) ? 1.0 - h * h / 6.0 : sin(h) / h;
+          double sn, cs;
+          sincos(-0.5 * tau * (lam[a] + lam[b]), &sn, &cs);
+          // -i tau (cs + i sn) sc = tau sc (sn - i cs)
+          const cx<double> F = {tau * sc * sn, -tau * sc * cs};
+          const cx<double> fb = cmul(F, be[b]);
+          rm[a][b] = al[a].re * fb.re + al[a].im * fb.im;  // Re(conj(alpha_a) F_ab beta_b)
+        }
+      // Q = R Re(M) R^T, accumulated packed
+      int e = 0;
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = i; j < S; ++j) {
+          double qij = 0.0, qji = 0.0;
+#pragma unroll
+          for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b < S; ++b) {
+              qij += ev[i * S + a] * rm[a][b] * ev[j * S + b];
+              qji += ev[j * S + a] * rm[a][b] * ev[i * S + b];
+            }
+          double* qp = qacc + (size_t)e * npts + pt;
+          *qp += (i == j) ? qij : qij + qji;
+          ++e;
+        }
+      apply_u<double, S>(la, u);  // lambda_{j-1}
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        v[s][q] = ps[s];
+        v[S + s][q] = la[s];
+      }
+    }
+  };
+  if (nv >= 1) vact(iv0);
+  if (nv >= 2) vact(iv1);
+  if constexpr (POST_FWD) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
+  }
+  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const auto rs = rsrc(stk + s * npts, (uint32_t)npts);
 #pragma unroll
     for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
   }
@@ -330,6 +499,100 @@ struct Passes {
     if ((e = ypass<false>(d, psi)) != hipSuccess) return e;
     return xpass<XP_FWD>(d, psi, 0, 0);
   }
+
+  // ------------------------------------------------------------ adjoint
+  template <bool PI, bool PF>
+  static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1) {
+    using SA = typename AdjSched<SC>::type;
+    auto k = k3d_zpass_adj<SA, S, CZ, PI, PF>;
+    const size_t lds = (size_t)CZ * N * sizeof(cx<double>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    // psi, lambda read + written; per action a table, the eigen table and the
+    // gradient accumulator (read + written)
+    const double bytes = (4.0 * S + nv * (2.0 * S * (S + 1) / 2.0 + S * (S + 1))) *
+                         (double)d.npts * sizeof(cx<double>) / 1.0;
+    TimedLaunch tl(d, KIND_OTHER, bytes);
+    hipLaunchKernelGGL(k, dim3(N / CZ, N), dim3(CZ * SA::TPC), lds, d.stream,
+                       (cx<double>*)a.stacked, (const cx<double>*)d.vexp,
+                       (const cx<double>*)a.eig, a.qacc, a.taus, nv, iv0, iv1,
+                       (const cx<double>*)d.tw[0]);
+    return hipGetLastError();
+  }
+  static hipError_t zadj(const DevView& d, const AdjointView& a, bool pi, bool pf, int nv,
+                         int iv0, int iv1) {
+    if (pi && pf) return za<true, true>(d, a, nv, iv0, iv1);
+    if (pi) return za<true, false>(d, a, nv, iv0, iv1);
+    if (pf) return za<false, true>(d, a, nv, iv0, iv1);
+    return za<false, false>(d, a, nv, iv0, iv1);
+  }
+
+  // Backward sweep: steps nsteps..1, each step's actions in reverse order
+  // with conjugated tables on [psi; lambda]; psi is replaced by the stored
+  // checkpoint at every step index that is a multiple of K.
+  static hipError_t adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps,
+                                     int K) {
+    if constexpr (!std::is_same<T, double>::value) {
+      return hipErrorInvalidValue;
+    } else {
+      DevView d2 = d;  // the stacked state for the y and x passes
+      d2.S = 2 * S;
+      cx<T>* stk = (cx<T>*)a.stacked;
+      bool zk = false, zopen = false, zpre = false;
+      int zv[2] = {0, 0}, znv = 0;
+      hipError_t e = hipSuccess;
+      auto flush = [&](bool post_fwd) -> hipError_t {
+        hipError_t r = zadj(d, a, zpre, post_fwd, znv, zv[0], zv[1]);
+        zopen = false;
+        znv = 0;
+        zk = post_fwd;
+        return r;
+      };
+      for (int64_t n = nsteps; n >= 1; --n) {
+        for (int i = d.nact - 1; i >= 0; --i) {
+          const int code = d.hprog[i];
+          const int idx = prog_idx(code);
+          if (prog_op(code) == OP_V) {
+            if (zopen && znv == 2) {
+              if ((e = flush(false)) != hipSuccess) return e;
+            }
+            if (!zopen) {
+              zopen = true;
+              zpre = zk;
+              znv = 0;
+              zk = false;
+            }
+            zv[znv++] = idx;
+          } else {
+            if (zopen) {
+              if ((e = flush(true)) != hipSuccess) return e;
+            } else if (!zk) {
+              if ((e = zadj(d, a, false, true, 0, 0, 0)) != hipSuccess) return e;
+              zk = true;
+            }
+            if ((e = ypass<false>(d2, stk)) != hipSuccess) return e;
+            if ((e = xpass<XP_PHASE>(d2, stk, idx, 1)) != hipSuccess) return e;
+            if ((e = ypass<true>(d2, stk)) != hipSuccess) return e;
+          }
+        }
+        if ((n - 1) % K == 0) {
+          if (zopen) {
+            if ((e = flush(false)) != hipSuccess) return e;
+          } else if (zk) {
+            if ((e = zadj(d, a, true, false, 0, 0, 0)) != hipSuccess) return e;
+            zk = false;
+          }
+          const size_t bytes = (size_t)S * d.npts * sizeof(cx<T>);
+          e = hipMemcpyAsync(a.stacked, (const char*)a.checkpoints + (size_t)((n - 1) / K) * bytes,
+                             bytes, hipMemcpyDeviceToDevice, d.stream);
+          if (e != hipSuccess) return e;
+        }
+      }
+      if (zopen) return flush(false);
+      if (zk) return zadj(d, a, true, false, 0, 0, 0);
+      return hipSuccess;
+    }
+  }
 };
 
 template <class F>
@@ -374,6 +637,37 @@ hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) 
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
     return Passes<T, SC, S>::propagate(d, psi, nsteps, conj);
   });
+}
+
+bool k3d_adjoint_supported(int n, int S, bool f64) {
+  return f64 && S >= 1 && S <= 3 && (n == 32 || n == 64 || n == 128 || n == 256);
+}
+
+hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps, int K) {
+  if (!k3d_adjoint_supported(d.n[0], d.S, d.f64)) return hipErrorInvalidValue;
+  switch (d.n[0]) {
+    case 32:
+    case 64:
+    case 128:
+    case 256:
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  auto run = [&]<class SC>() -> hipError_t {
+    switch (d.S) {
+      case 1: return Passes<double, SC, 1>::adjoint_backward(d, a, nsteps, K);
+      case 2: return Passes<double, SC, 2>::adjoint_backward(d, a, nsteps, K);
+      case 3: return Passes<double, SC, 3>::adjoint_backward(d, a, nsteps, K);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (d.n[0]) {
+    case 32: return run.template operator()<Z32>();
+    case 64: return run.template operator()<Z64>();
+    case 128: return run.template operator()<Z128>();
+    default: return run.template operator()<Z256>();
+  }
 }
 
 hipError_t k3d_fft_forward(const DevView& d, void* psi) {

@@ -247,6 +247,90 @@ __global__ void __launch_bounds__(kReduceThreads)
   }
 }
 
+// Eigen-decomposition table for the adjoint: per point R (row-major S x S)
+// then the eigenvalues, as S(S+1)/2 pairs of doubles in the z-pass tile
+// layout (the pair of entry e is stored where a table stores its entry e).
+template <int S>
+__global__ void __launch_bounds__(256)
+    k_form_eig(const double* __restrict__ vraw, int64_t npts, int tile, int n,
+               cx<double>* __restrict__ out) {
+  constexpr int NE = S * (S + 1) / 2;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    double A[S][S], R[S][S];
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = i; j < S; ++j) {
+        const double vij = vraw[(int64_t)e * npts + x];
+        A[i][j] = vij;
+        A[j][i] = vij;
+        ++e;
+      }
+    jacobi_sym<S>(A, R);
+    double flat[2 * NE];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) flat[i * S + j] = R[i][j];
+#pragma unroll
+    for (int l = 0; l < S; ++l) flat[S * S + l] = A[l][l];
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+      out[table_index(npts, NE, tile, n, 0, q, x)] = cx<double>{flat[2 * q], flat[2 * q + 1]};
+  }
+}
+
+// vraw = vbase + sum_k delta_k dv_k (the potential is linear in its parameters).
+__global__ void __launch_bounds__(256)
+    k_vparams(double* __restrict__ vraw, const double* __restrict__ vbase,
+              const double* __restrict__ dv, const double* __restrict__ delta, int nparams,
+              int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = vbase[i];
+    for (int k = 0; k < nparams; ++k) v += delta[k] * dv[(int64_t)k * n + i];
+    vraw[i] = v;
+  }
+}
+
+// lambda_s = w_s psi_s (seed of the adjoint sweep for L = sum_s w_s P_s).
+__global__ void __launch_bounds__(256)
+    k_scale_surfaces(cx<double>* __restrict__ lam, const cx<double>* __restrict__ psi,
+                     const double* __restrict__ w, int S, int64_t npts) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)S * npts;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double ws = w[i / npts];
+    lam[i] = cx<double>{ws * psi[i].re, ws * psi[i].im};
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Per block: g_k = sum_x sum_e qacc[e][x] dv[k][e][x], k < NP.
+template <int NP>
+__global__ void __launch_bounds__(kReduceThreads)
+    k_grad_partials(const double* __restrict__ qacc, const double* __restrict__ dv, int NE,
+                    int64_t npts, double* __restrict__ partials) {
+  double acc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * kReduceThreads) {
+    for (int e = 0; e < NE; ++e) {
+      const double q = qacc[(int64_t)e * npts + x];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] += q * dv[((int64_t)k * NE + e) * npts + x];
+    }
+  }
+  block_sum<NP>(acc, partials + (size_t)blockIdx.x * NP);
+}
+
 template <int S, typename T>
 hipError_t form_impl(const DevView& d, const double* vraw, const double* taus, int ntau, int tile,
                      void* out) {
@@ -319,6 +403,83 @@ hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, kpart, kReduceBlocks,
                      1, out_dev + nv);
+  return hipGetLastError();
+}
+
+hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* out) {
+  int blocks = (int)((d.npts + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  switch (d.S) {
+    case 1: hipLaunchKernelGGL(k_form_eig<1>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    case 2: hipLaunchKernelGGL(k_form_eig<2>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    case 3: hipLaunchKernelGGL(k_form_eig<3>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_vparams(const DevView& d, double* vraw, const double* vbase, const double* dv,
+                       const double* delta_dev, int nparams) {
+  const int64_t n = (int64_t)d.S * (d.S + 1) / 2 * d.npts;
+  hipLaunchKernelGGL(k_vparams, dim3(2048), dim3(256), 0, d.stream, vraw, vbase, dv, delta_dev,
+                     nparams, n);
+  return hipGetLastError();
+}
+
+hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const double* w_dev,
+                        double* qacc) {
+  hipLaunchKernelGGL(k_scale_surfaces, dim3(2048), dim3(256), 0, d.stream, (cx<double>*)lam,
+                     (const cx<double>*)psi, w_dev, d.S, d.npts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, d.stream, qacc,
+                     (int64_t)d.S * (d.S + 1) / 2 * d.npts);
+  return hipGetLastError();
+}
+
+hipError_t grad_reduce(const DevView& d, const double* qacc, const double* dv, int nparams,
+                       double* partials, double* out_dev) {
+  const int NE = d.S * (d.S + 1) / 2;
+  switch (nparams) {
+#define SOP_GRAD_CASE(K)                                                                    \
+  case K:                                                                                   \
+    hipLaunchKernelGGL(k_grad_partials<K>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,    \
+                       d.stream, qacc, dv, NE, d.npts, partials);                           \
+    break;
+    SOP_GRAD_CASE(1)
+    SOP_GRAD_CASE(2)
+    SOP_GRAD_CASE(3)
+    SOP_GRAD_CASE(4)
+    SOP_GRAD_CASE(5)
+    SOP_GRAD_CASE(6)
+    SOP_GRAD_CASE(7)
+    SOP_GRAD_CASE(8)
+#undef SOP_GRAD_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials, kReduceBlocks,
+                     nparams, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t pops_reduce(const DevView& d, const void* psi, const double* vraw_dev,
+                       double* partials, double* out_dev) {
+  hipError_t e;
+  switch (d.S) {
+    case 1: e = d.f64 ? obs_points_impl<1, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<1, float>(d, psi, vraw_dev, partials); break;
+    case 2: e = d.f64 ? obs_points_impl<2, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<2, float>(d, psi, vraw_dev, partials); break;
+    case 3: e = d.f64 ? obs_points_impl<3, double>(d, psi, vraw_dev, partials)
+                      : obs_points_impl<3, float>(d, psi, vraw_dev, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials, kReduceBlocks,
+                     d.S + 1, out_dev);
   return hipGetLastError();
 }
 

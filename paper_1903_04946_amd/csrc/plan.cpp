@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -191,6 +192,12 @@ struct sop_plan {
   size_t table_bytes = 0;
   int tile = 0;  // potential-table layout (0 = [u][entry][point])
   sop::Timer* timer = nullptr;
+  int nparams = 0;
+  double* d_vbase = nullptr;  // V at theta = 0
+  double* d_dv = nullptr;     // [nparams][NE][npts]
+  double* d_theta = nullptr;  // [nparams]
+  void* d_eig = nullptr;      // adjoint eigen table (FP64, tile layout)
+  double* d_w = nullptr;      // [S] adjoint weights
 };
 
 namespace {
@@ -198,7 +205,8 @@ namespace {
 void free_plan(sop_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
-                  p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out};
+                  p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
+                  p->d_dv, p->d_theta, p->d_eig, p->d_w};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p->timer;
@@ -263,6 +271,9 @@ sop_status validate(const sop_plan_desc* d) {
   if (!(d->dt != 0) || !std::isfinite(d->dt)) return fail(SOP_ERR_INVALID, "dt must be finite and nonzero");
   if (!(d->hbar > 0) || !std::isfinite(d->hbar)) return fail(SOP_ERR_INVALID, "hbar must be > 0");
   if (d->dtype != SOP_C128 && d->dtype != SOP_C64) return fail(SOP_ERR_INVALID, "bad dtype");
+  if (d->nparams < 0 || d->nparams > sop::kMaxParams)
+    return fail(SOP_ERR_INVALID, "nparams must be 0..8");
+  if (d->nparams > 0 && !d->dvtables) return fail(SOP_ERR_INVALID, "dvtables required");
   return SOP_OK;
 }
 
@@ -384,7 +395,7 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
       hipMalloc((void**)&p->d_prog, prog.size() * sizeof(int)) != hipSuccess ||
       hipMalloc((void**)&p->d_prog1, 2 * sizeof(int)) != hipSuccess ||
       hipMalloc((void**)&p->d_taus, (vc.size() + 1) * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&p->d_part, (size_t)sop::kReduceBlocks * (S + 2) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&p->d_part, (size_t)sop::kReduceBlocks * (S + 2 + sop::kMaxParams) * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&p->d_out, 8 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SOP_ERR_NOMEM, "device allocation failed for the plan tables");
@@ -428,6 +439,26 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
 
   p->tile = p->ndim == 3 ? sop::k3d_table_tile(p->n[0], f64) : 0;
   HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
+  p->nparams = desc->nparams;
+  if (p->nparams > 0) {
+    const size_t dvb = (size_t)p->nparams * vbytes;
+    if (hipMalloc((void**)&p->d_vbase, vbytes) != hipSuccess ||
+        hipMalloc((void**)&p->d_dv, dvb) != hipSuccess ||
+        hipMalloc((void**)&p->d_theta, sop::kMaxParams * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&p->d_w, 8 * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SOP_ERR_NOMEM, "device allocation failed for the parameter tables");
+    }
+    HIPTRY(hipMemcpyAsync(p->d_vbase, p->d_vraw, vbytes, hipMemcpyDeviceToDevice, stream));
+    HIPTRY(hipMemcpyAsync(p->d_dv, desc->dvtables, dvb, hipMemcpyHostToDevice, stream));
+    if (p->ndim == 3 && f64 && sop::k3d_adjoint_supported(p->n[0], S, f64)) {
+      if (hipMalloc(&p->d_eig, (size_t)NE * p->npts * sizeof(double) * 2) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SOP_ERR_NOMEM, "device allocation failed for the eigen table");
+      }
+      HIPTRY(sop::form_eig(d, p->d_vraw, p->tile, p->d_eig));
+    }
+  }
   HIPTRY(hipStreamSynchronize(stream));
   guard.keep = true;
   *out = p;
@@ -551,6 +582,106 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
     HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
   // the host staging buffers above must outlive the copies
   HIPTRY(hipStreamSynchronize(d.stream));
+  return SOP_OK;
+}
+
+sop_status sop_plan_set_params(sop_plan* p, const double* theta) {
+  if (!p || !theta) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (p->nparams == 0) return fail(SOP_ERR_STATE, "plan has no parameters");
+  for (int k = 0; k < p->nparams; ++k)
+    if (!std::isfinite(theta[k])) return fail(SOP_ERR_INVALID, "theta must be finite");
+  hipStream_t st = p->dv.stream;
+  HIPTRY(hipMemcpyAsync(p->d_theta, theta, p->nparams * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
+  HIPTRY(sop::form_vexp(p->dv, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
+  if (p->d_eig) HIPTRY(sop::form_eig(p->dv, p->d_vraw, p->tile, p->d_eig));
+  HIPTRY(hipStreamSynchronize(st));
+  return SOP_OK;
+}
+
+namespace {
+
+struct AdjLayout {
+  size_t psi = 0, qacc = 0, ckpt = 0, total = 0;
+  int64_t ncp = 0;
+};
+
+sop_status adjoint_check(const sop_plan* p, int64_t nsteps, int K, AdjLayout* lay) {
+  if (!p) return fail(SOP_ERR_INVALID, "plan is NULL");
+  if (nsteps < 1 || K < 1) return fail(SOP_ERR_INVALID, "nsteps and K must be >= 1");
+  if (p->nparams == 0) return fail(SOP_ERR_STATE, "plan has no parameters (nparams = 0)");
+  if (!p->d_eig) return fail(SOP_ERR_UNSUPPORTED, "the adjoint needs an FP64 3D plan with n in {32, 64, 128, 256}");
+  const size_t sb = (size_t)p->S * p->npts * sizeof(double) * 2;
+  lay->ncp = (nsteps + K - 1) / K;
+  lay->psi = 0;                                   // psi then lambda: 2 * sb
+  lay->qacc = 2 * sb;                             // NE * npts doubles
+  const size_t qb = (size_t)p->S * (p->S + 1) / 2 * p->npts * sizeof(double);
+  lay->ckpt = lay->qacc + ((qb + 255) / 256) * 256;
+  lay->total = lay->ckpt + (size_t)lay->ncp * sb;
+  return SOP_OK;
+}
+
+}  // namespace
+
+sop_status sop_adjoint_workspace_bytes(const sop_plan* p, int64_t nsteps, int K, size_t* bytes) {
+  if (!bytes) return fail(SOP_ERR_INVALID, "bytes is NULL");
+  AdjLayout lay;
+  sop_status st = adjoint_check(p, nsteps, K, &lay);
+  if (st != SOP_OK) return st;
+  *bytes = lay.total;
+  return SOP_OK;
+}
+
+sop_status sop_adjoint_forward(sop_plan* p, const void* psi0, int64_t nsteps, int K, void* ws,
+                               double* pops_out) {
+  AdjLayout lay;
+  sop_status st = adjoint_check(p, nsteps, K, &lay);
+  if (st != SOP_OK) return st;
+  if (!psi0 || !ws || !pops_out) return fail(SOP_ERR_INVALID, "NULL argument");
+  hipStream_t s = p->dv.stream;
+  char* w = (char*)ws;
+  const size_t sb = (size_t)p->S * p->npts * sizeof(double) * 2;
+  HIPTRY(hipMemcpyAsync(w + lay.psi, psi0, sb, hipMemcpyDeviceToDevice, s));
+  int64_t done = 0;
+  for (int64_t c = 0; done < nsteps; ++c) {
+    HIPTRY(hipMemcpyAsync(w + lay.ckpt + (size_t)c * sb, w + lay.psi, sb, hipMemcpyDeviceToDevice, s));
+    const int64_t k = std::min<int64_t>(K, nsteps - done);
+    HIPTRY(sop::k3d_propagate(p->dv, w + lay.psi, k, 0));
+    done += k;
+  }
+  HIPTRY(sop::pops_reduce(p->dv, w + lay.psi, p->d_vraw, p->d_part, p->d_out));
+  double raw[8];
+  HIPTRY(hipMemcpyAsync(raw, p->d_out, (p->S + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  for (int q = 0; q < p->S; ++q) pops_out[q] = raw[q] * p->dV;
+  return SOP_OK;
+}
+
+sop_status sop_adjoint_backward(sop_plan* p, int64_t nsteps, int K, const double* weights,
+                                void* ws, double* grad_out) {
+  AdjLayout lay;
+  sop_status st = adjoint_check(p, nsteps, K, &lay);
+  if (st != SOP_OK) return st;
+  if (!weights || !ws || !grad_out) return fail(SOP_ERR_INVALID, "NULL argument");
+  for (int q = 0; q < p->S; ++q)
+    if (!std::isfinite(weights[q])) return fail(SOP_ERR_INVALID, "weights must be finite");
+  hipStream_t s = p->dv.stream;
+  char* w = (char*)ws;
+  const size_t sb = (size_t)p->S * p->npts * sizeof(double) * 2;
+  HIPTRY(hipMemcpyAsync(p->d_w, weights, p->S * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPTRY(sop::adjoint_seed(p->dv, w + lay.psi + sb, w + lay.psi, p->d_w, (double*)(w + lay.qacc)));
+  sop::AdjointView a;
+  a.stacked = w + lay.psi;
+  a.eig = p->d_eig;
+  a.qacc = (double*)(w + lay.qacc);
+  a.taus = p->d_taus;
+  a.checkpoints = w + lay.ckpt;
+  HIPTRY(sop::k3d_adjoint_backward(p->dv, a, nsteps, K));
+  HIPTRY(sop::grad_reduce(p->dv, a.qacc, p->d_dv, p->nparams, p->d_part, p->d_out));
+  double raw[sop::kMaxParams];
+  HIPTRY(hipMemcpyAsync(raw, p->d_out, p->nparams * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(hipStreamSynchronize(s));
+  for (int k = 0; k < p->nparams; ++k) grad_out[k] = 2.0 * p->dV * raw[k];
   return SOP_OK;
 }
 

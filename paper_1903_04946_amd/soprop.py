@@ -35,7 +35,8 @@ class _Desc(ctypes.Structure):
                 ("inv_mass", ctypes.POINTER(ctypes.c_double)),
                 ("vtable", ctypes.POINTER(ctypes.c_double)),
                 ("split", ctypes.c_int), ("comp", ctypes.c_int), ("order", ctypes.c_int),
-                ("dt", ctypes.c_double), ("hbar", ctypes.c_double), ("dtype", ctypes.c_int)]
+                ("dt", ctypes.c_double), ("hbar", ctypes.c_double), ("dtype", ctypes.c_int),
+                ("nparams", ctypes.c_int), ("dvtables", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Info(ctypes.Structure):
@@ -49,7 +50,8 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
            "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_apply_action", "sop_plan_set_timing", "sop_timing_read"]
+           "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
+           "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward"]
 KINDS = ["zpass", "ypass", "xpass", "k1d", "other"]
 
 _lib = None
@@ -80,10 +82,16 @@ def lib():
     L.sop_overlap.argtypes = [vp, vp, vp, dp]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    L.sop_plan_set_params.argtypes = [vp, dp]
+    L.sop_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_size_t)]
+    L.sop_adjoint_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, dp]
+    L.sop_adjoint_backward.argtypes = [vp, ctypes.c_int64, ctypes.c_int, dp, vp, dp]
     L.sop_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_apply_action", "sop_plan_set_timing", "sop_timing_read"):
+              "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
+              "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward"):
         getattr(L, f).restype = ctypes.c_int
     L.sop_supported_length.restype = ctypes.c_int
     _lib = L
@@ -151,7 +159,7 @@ class Plan:
     """
 
     def __init__(self, n, lo, hi, nsurf, inv_mass, vtable, split="VTV", comp="strang",
-                 order=2, dt=0.01, hbar=1.0, dtype=None, stream=None):
+                 order=2, dt=0.01, hbar=1.0, dtype=None, stream=None, dvtables=None):
         import torch
         if dtype is None:
             dtype = torch.complex128
@@ -184,6 +192,13 @@ class Plan:
         d.dt = float(dt)
         d.hbar = float(hbar)
         d.dtype = C128 if dtype == torch.complex128 else C64
+        self.nparams = 0
+        if dvtables is not None:
+            self._dv = np.ascontiguousarray(dvtables, dtype=np.float64).reshape(-1, ne,
+                                                                               self._vt.shape[1])
+            self.nparams = self._dv.shape[0]
+            d.nparams = self.nparams
+            d.dvtables = _dp(self._dv)
         self._stream = stream
         h = ctypes.c_void_p()
         _check(L.sop_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)),
@@ -194,6 +209,40 @@ class Plan:
     def from_model(cls, model, **kw):
         return cls(model.n, model.lo, model.hi, model.nsurf, model.inv_mass, model.vtable,
                    hbar=model.hbar, **kw)
+
+    def set_params(self, theta):
+        """V <- vtable + sum_k theta_k dvtables[k]; tables formed again."""
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.nparams)
+        _check(lib().sop_plan_set_params(self._h, _dp(th)), "sop_plan_set_params")
+
+    def adjoint_workspace_bytes(self, nsteps: int, K: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().sop_adjoint_workspace_bytes(self._h, int(nsteps), int(K), ctypes.byref(b)),
+               "sop_adjoint_workspace_bytes")
+        return int(b.value)
+
+    def adjoint_workspace(self, nsteps: int, K: int):
+        import torch
+        return torch.empty(self.adjoint_workspace_bytes(nsteps, K), dtype=torch.uint8,
+                           device="cuda")
+
+    def adjoint_forward(self, psi0, nsteps: int, K: int, workspace) -> np.ndarray:
+        """Populations P_s(T) after nsteps from psi0, checkpoints every K steps."""
+        self._check_psi(psi0)
+        pops = np.zeros(self.nsurf)
+        _check(lib().sop_adjoint_forward(self._h, ctypes.c_void_p(psi0.data_ptr()), int(nsteps),
+                                         int(K), ctypes.c_void_p(workspace.data_ptr()), _dp(pops)),
+               "sop_adjoint_forward")
+        return pops
+
+    def adjoint_backward(self, nsteps: int, K: int, weights, workspace) -> np.ndarray:
+        """sum_s weights[s] dP_s/dtheta_k after adjoint_forward."""
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(self.nsurf)
+        g = np.zeros(self.nparams)
+        _check(lib().sop_adjoint_backward(self._h, int(nsteps), int(K), _dp(w),
+                                          ctypes.c_void_p(workspace.data_ptr()), _dp(g)),
+               "sop_adjoint_backward")
+        return g
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -270,3 +319,45 @@ class Plan:
         _check(lib().sop_overlap(self._h, ctypes.c_void_p(psi.data_ptr()),
                                  ctypes.c_void_p(phi.data_ptr()), _dp(out)), "sop_overlap")
         return complex(out[0], out[1])
+
+
+def _populations_fn():
+    import torch
+
+    class PopulationsFn(torch.autograd.Function):
+        """P(theta): final surface populations as a function of the plan's
+        parameters; the backward pass runs the library's adjoint sweep.
+
+        apply(theta, plan, psi0, nsteps, K) -> tensor [S] (float64, CPU)
+        theta: float64 CPU tensor [nparams]; plan: Plan with dvtables;
+        psi0: device tensor of the plan's shape and dtype (complex128).
+        """
+
+        @staticmethod
+        def forward(ctx, theta, plan, psi0, nsteps, K):
+            plan.set_params(theta.detach().cpu().numpy())
+            ws = plan.adjoint_workspace(nsteps, K)
+            pops = plan.adjoint_forward(psi0, nsteps, K, ws)
+            ctx.plan, ctx.ws, ctx.nsteps, ctx.K = plan, ws, nsteps, K
+            return torch.from_numpy(pops)
+
+        @staticmethod
+        def backward(ctx, grad_pops):
+            g = ctx.plan.adjoint_backward(ctx.nsteps, ctx.K, grad_pops.detach().cpu().numpy(),
+                                          ctx.ws)
+            ctx.ws = None
+            return torch.from_numpy(g), None, None, None, None
+
+    return PopulationsFn
+
+
+_PFN = None
+
+
+def __getattr__(name):
+    global _PFN
+    if name == "PopulationsFn":
+        if _PFN is None:
+            _PFN = _populations_fn()
+        return _PFN
+    raise AttributeError(name)
