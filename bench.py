@@ -109,6 +109,160 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
                       f"FP64 oracle step loop ({sec:.2f} s, plan-time eigendecomposition excluded)"}
 
 
+# ---------------------------------------------------------------- time to error
+TTE_SCHEMES = [("strang", 2), ("triple_jump", 4), ("triple_jump", 6), ("triple_jump", 8),
+               ("triple_jump", 10), ("suzuki", 4), ("suzuki", 6), ("suzuki", 8), ("suzuki", 10)]
+
+
+def _interp_time(points, eps):
+    """Log-log interpolation of wall time at error eps from (time, err) points
+    ordered by decreasing dt; None if eps is not bracketed."""
+    import math
+    for (t1, e1), (t2, e2) in zip(points, points[1:]):
+        if e1 > eps >= e2 and e1 > 0 and e2 > 0:
+            f = (math.log(eps) - math.log(e1)) / (math.log(e2) - math.log(e1))
+            return math.exp(math.log(t1) + f * (math.log(t2) - math.log(t1)))
+    if points and points[0][1] <= eps:
+        return points[0][0]
+    return None
+
+
+def time_to_error(torch, soprop, tf=10.0, kmax=10, kmax_strang=16, members=256, fp32=True):
+    """Wall time to reach a final-time L2 error (config-2 model: 1D two-surface,
+    N = 1024), against a TJ-10 reference at dt = 2^-12, for every scheme.
+
+    FP64 runs are single runs (one wavepacket).  FP32 runs propagate `members`
+    wavepackets in one launch (x0 ~ U[-3, 3], p0 ~ U[-2, 2], seed 4946), each
+    compared with its own FP64 reference; time is amortised per member.
+    """
+    import numpy as np
+    from paper_1903_04946_amd import synth
+
+    base = synth.two_surface_1d(n=1024)
+    dV = base.dV
+
+    def run(model_psi, comp, order, dt, nsteps, dtype, count=1, label=""):
+        """Propagates in chunks of at most ~10 s each, printing progress."""
+        plan = soprop.Plan.from_model(base, comp=comp, order=order, dt=dt, dtype=dtype)
+        psi = torch.from_numpy(model_psi).to(dtype).cuda()
+        done, total = 0, 0.0
+        chunk = max(1, min(nsteps, 256))
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if count == 1:
+                plan.propagate(psi, k)
+            else:
+                plan.propagate_many(psi, k)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3
+            total += sec
+            done += k
+            # grow the chunk towards ~10 s per launch
+            chunk = max(1, min(nsteps, int(k * min(4.0, 10.0 / max(sec, 1e-4)))))
+            if total > 5.0:
+                print(f"[tte] {label} {comp}-{order} dt={dt:.3g} {done}/{nsteps} steps {total:.1f} s",
+                      file=sys.stderr, flush=True)
+        return psi.cpu().numpy().astype(np.complex128), total
+
+    def err(a, b):
+        return float(np.sqrt(np.sum(np.abs(a - b) ** 2, axis=tuple(range(a.ndim - 2, a.ndim))) * dV).max()
+                     if a.ndim > 2 else np.sqrt(np.sum(np.abs(a - b) ** 2) * dV))
+
+    out = {"model": "two-surface 1D, N = 1024, t_f = 10 a.u.", "reference": "TJ-10, dt = 2^-12, FP64"}
+    kref = 12
+    ref, tref = run(base.psi0, "triple_jump", 10, 2.0**-kref, int(tf * 2**kref), torch.complex128,
+                    label="reference")
+    # cross-check of the reference with SF-10 at 2^-9
+    chk, _ = run(base.psi0, "suzuki", 10, 2.0**-9, int(tf * 2**9), torch.complex128, label="check")
+    out["reference_check_sf10_dt2^-9"] = err(chk, ref)
+    print(f"[tte] reference {tref:.1f} s, SF-10 check error {out['reference_check_sf10_dt2^-9']:.2e}",
+          file=sys.stderr, flush=True)
+    fp64 = {}
+    for comp, order in TTE_SCHEMES:
+        pts = []
+        top = kmax_strang if comp == "strang" else kmax
+        prev = None
+        for k in range(1, top + 1):
+            nsteps = int(tf * 2**k)
+            psi, sec = run(base.psi0, comp, order, tf / nsteps, nsteps, torch.complex128)
+            e = err(psi, ref)
+            pts.append((sec, e, k))
+            print(f"[tte] fp64 {comp}-{order} dt=2^-{k} err={e:.3e} {sec:.3f} s",
+                  file=sys.stderr, flush=True)
+            if e < 1e-11 or (prev is not None and e > prev and e < 1e-8):
+                break
+            prev = e
+        name = f"{comp}-{order}"
+        tte = _interp_time([(t, e) for t, e, _ in pts], 1e-10)
+        rec = {"runs": [{"dt": f"2^-{k}", "seconds": t, "error": e} for t, e, k in pts],
+               "time_to_1e-10_s": tte}
+        if tte is None and comp == "strang":
+            # extrapolate along the dt^2 asymptote fitted to the two finest
+            # points above the round-off floor
+            good = [(t, e, k) for t, e, k in pts if e > 1e-9]
+            if len(good) >= 2:
+                (t1, e1, k1), (t2, e2, k2) = good[-2], good[-1]
+                c = e2 / (2.0**-k2) ** 2
+                dt_star = (1e-10 / c) ** 0.5
+                sec_per_step = t2 / (tf * 2**k2)
+                rec["time_to_1e-10_s"] = sec_per_step * tf / dt_star
+                rec["extrapolated"] = True
+        fp64[name] = rec
+    out["fp64_single_run"] = fp64
+    best = min((v["time_to_1e-10_s"], k) for k, v in fp64.items()
+               if v["time_to_1e-10_s"] is not None and not k.startswith("strang"))
+    st = fp64["strang-2"]["time_to_1e-10_s"]
+    out["fp64_best"] = {"scheme": best[1], "seconds": best[0],
+                        "speedup_vs_strang": (st / best[0]) if st else None,
+                        "strang_extrapolated": bool(fp64["strang-2"].get("extrapolated"))}
+    if fp32:
+        rng = np.random.Generator(np.random.PCG64(4946))
+        x = base.axes()[0]
+        psis = np.zeros((members, 2, 1024), complex)
+        for i in range(members):
+            psis[i, 0] = synth.gaussian_1d(x, rng.uniform(-3, 3), rng.uniform(-2, 2), base.meta["sigma"])
+            psis[i] = synth.normalise(psis[i], dV)
+        refs, tref_b = run(psis, "triple_jump", 10, 2.0**-kref, int(tf * 2**kref), torch.complex128,
+                           count=members, label="batched references")
+        b32 = {}
+        for comp, order in [("strang", 2), ("triple_jump", 4), ("suzuki", 4), ("suzuki", 6),
+                            ("triple_jump", 6)]:
+            pts = []
+            for k in range(1, 13):
+                nsteps = int(tf * 2**k)
+                dtype = torch.complex64
+                psi, sec = run(psis, comp, order, tf / nsteps, nsteps, dtype, count=members)
+                e = err(psi, refs)
+                pts.append((sec / members, e, k))
+                print(f"[tte] fp32 x{members} {comp}-{order} dt=2^-{k} max err={e:.3e} "
+                      f"{sec:.3f} s", file=sys.stderr, flush=True)
+                if e < 1e-6:
+                    break
+            b32[f"{comp}-{order}"] = {
+                "runs": [{"dt": f"2^-{k}", "seconds_per_member": t, "max_error": e} for t, e, k in pts],
+                "time_to_1e-5_s_per_member": _interp_time([(t, e) for t, e, _ in pts], 1e-5)}
+        out["fp32_batched"] = {"members": members, "schemes": b32}
+        # FP64 Strang, batched the same way, for comparison
+        pts = []
+        for k in range(1, 14):
+            nsteps = int(tf * 2**k)
+            psi, sec = run(psis, "strang", 2, tf / nsteps, nsteps, torch.complex128, count=members)
+            e = err(psi, refs)
+            pts.append((sec / members, e))
+            print(f"[tte] fp64 x{members} strang dt=2^-{k} max err={e:.3e} {sec:.3f} s",
+                  file=sys.stderr, flush=True)
+            if e < 1e-6:
+                break
+        out["fp64_strang_batched_time_to_1e-5_s_per_member"] = _interp_time(pts, 1e-5)
+        out["fp64_strang_single_time_to_1e-5_s"] = _interp_time(
+            [(r["seconds"], r["error"]) for r in fp64["strang-2"]["runs"]], 1e-5)
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +270,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-to-error", action="store_true",
+                    help="also run the config-2 time-to-error sweep (about a minute)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -185,6 +341,7 @@ def main(argv=None) -> int:
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(model, comp, order, dt, M)
+    tte = time_to_error(torch, soprop) if a.time_to_error else None
 
     out = {
         "metric": METRIC,
@@ -210,6 +367,7 @@ def main(argv=None) -> int:
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch},
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "time_to_error": tte,
         "checks": {"norm_after": norm, "wall_s_timed": wall},
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -167,6 +167,13 @@ sop_status sop_plan_set_stream(sop_plan* plan, void* hip_stream);
  * evolution operator").  nsteps = 0 is a no-op.  Asynchronous. */
 sop_status sop_propagate(sop_plan* plan, void* psi_dev, int64_t nsteps, int direction);
 
+/* Propagates count independent states of this plan stored contiguously,
+ * psi_dev = [count][nsurf][n...], each as sop_propagate does (1D: one
+ * launch, one persistent workgroup per state; 3D: the states in turn).
+ * count in 1..65535.  Asynchronous. */
+sop_status sop_propagate_many(sop_plan* plan, void* psi_dev, int count, int64_t nsteps,
+                              int direction);
+
 /* Observables of psi in FP64 (Sec. "Geometric properties of the exact
  * evolution operator"): out[0] = <psi|psi>, out[1] = <psi|H|psi>,
  * out[2+s] = population of surface s (s < nsurf), out[2+S] = <T>,
@@ -219,6 +226,13 @@ sop_status sop_adjoint_forward(sop_plan* plan, const void* psi0_dev, int64_t nst
  * Synchronises.  The workspace's psi is consumed. */
 sop_status sop_adjoint_backward(sop_plan* plan, int64_t nsteps, int K, const double* weights,
                                 void* workspace_dev, double* grad_out);
+
+/* Plan options.  SOP_OPT_GRAPHS (default 1): on 3D grids, runs of 4 or more
+ * steps launch the first step, the steady step (replayed) and the final
+ * pass as HIP graphs captured once per state pointer, direction and count;
+ * 0 launches every pass eagerly.  Both give bitwise identical results. */
+enum { SOP_OPT_GRAPHS = 1 };
+sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
 /* Per-kernel timing (measurement aid).  While enabled, every kernel launch
  * of the plan is bracketed by HIP events on the plan's stream.

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,6 +47,44 @@ struct Timer {
   }
 };
 
+// One pass of the 3D executor.
+struct PassDesc {
+  enum Kind { Z = 0, YF = 1, YI = 2, XP = 3 };
+  int kind = Z;
+  bool pre_inv = false, post_fwd = false;
+  int nv = 0, iv0 = 0, iv1 = 0;  // z-pass potential actions
+  int tidx = 0;                  // x-pass kinetic factor set
+  bool operator==(const PassDesc& o) const {
+    return kind == o.kind && pre_inv == o.pre_inv && post_fwd == o.post_fwd && nv == o.nv &&
+           iv0 == o.iv0 && iv1 == o.iv1 && tidx == o.tidx;
+  }
+};
+
+// Instantiated HIP graphs of step segments (first step, steady step, final
+// flush), captured on a private stream and launched on the plan's stream.
+struct GraphCache {
+  struct Key {
+    const void* psi;
+    int conj, count, seg;
+    bool operator<(const Key& o) const {
+      if (psi != o.psi) return psi < o.psi;
+      if (conj != o.conj) return conj < o.conj;
+      if (count != o.count) return count < o.count;
+      return seg < o.seg;
+    }
+  };
+  hipStream_t capture = nullptr;
+  std::map<Key, hipGraphExec_t> execs;
+  void clear() {
+    for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
+    execs.clear();
+  }
+  ~GraphCache() {
+    clear();
+    if (capture) (void)hipStreamDestroy(capture);
+  }
+};
+
 // Device-side view of a plan that the launchers need.
 struct DevView {
   int ndim = 1;
@@ -62,6 +101,8 @@ struct DevView {
   int nact = 0;
   std::vector<int> hprog;      // host copy of the step program
   Timer* timer = nullptr;      // non-null while timing is enabled
+  GraphCache* graphs = nullptr;  // non-null when 3D steps may be graph-captured
+  int count = 1;               // states of a batch processed by each 3D launch
 };
 
 // Brackets one launch with timing events when the plan's timer is on.
@@ -85,7 +126,8 @@ struct TimedLaunch {
 
 // kernels_1d.hip
 bool k1d_supported(int n, int S);
-hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
+// count states [count][S][N] of the same plan, one workgroup each
+hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj, int count = 1);
 hipError_t k1d_fft_forward(const DevView& d, void* psi);
 
 // Device buffers of an adjoint sweep (FP64 only).

@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(SC::TPC)
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
   const int t = threadIdx.x;
+  psi += (size_t)blockIdx.x * S * N;  // one workgroup per state
   const T csign = conj ? (T)-1 : (T)1;
   cx<T> v[S][E];
 #pragma unroll
@@ -127,15 +128,15 @@ __global__ void __launch_bounds__(SC::TPC)
 constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename T, class SC, int S>
-hipError_t launch_prop(const DevView& d, void* psi, int64_t nsteps, int conj) {
+hipError_t launch_prop(const DevView& d, void* psi, int64_t nsteps, int conj, int count) {
   constexpr size_t one = (size_t)lds_pencil<SC>() * sizeof(cx<T>);
-  TimedLaunch tl(d, KIND_1D, 2.0 * S * SC::N * sizeof(cx<T>));
+  TimedLaunch tl(d, KIND_1D, 2.0 * S * SC::N * sizeof(cx<T>) * count);
   if (one * S <= kMaxLds) {
     auto k = k1d_prop_kernel<T, SC, S, S>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(one * S));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(1), dim3(SC::TPC), one * S, d.stream, (cx<T>*)psi,
+    hipLaunchKernelGGL(k, dim3(count), dim3(SC::TPC), one * S, d.stream, (cx<T>*)psi,
                        (const cx<T>*)d.vexp, (const cx<T>*)d.kin, (const cx<T>*)d.tw[0], d.prog,
                        d.nact, nsteps, conj);
   } else {
@@ -143,7 +144,7 @@ hipError_t launch_prop(const DevView& d, void* psi, int64_t nsteps, int conj) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)one);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(1), dim3(SC::TPC), one, d.stream, (cx<T>*)psi,
+    hipLaunchKernelGGL(k, dim3(count), dim3(SC::TPC), one, d.stream, (cx<T>*)psi,
                        (const cx<T>*)d.vexp, (const cx<T>*)d.kin, (const cx<T>*)d.tw[0], d.prog,
                        d.nact, nsteps, conj);
   }
@@ -204,9 +205,9 @@ bool k1d_supported(int n, int S) {
   }
 }
 
-hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) {
+hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj, int count) {
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
-    return launch_prop<T, SC, S>(d, psi, nsteps, conj);
+    return launch_prop<T, SC, S>(d, psi, nsteps, conj, count);
   });
 }
 

@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const uint32_t off0 = (uint32_t)y * N + x;
   const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
   const LayStrided lay{col, 0, C};  // one surface at a time through LDS
+  psi += (size_t)blockIdx.z * S * npts;  // member of a batch of states
   cx<T> v[S][E];
   constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
 #pragma unroll
@@ -375,6 +376,81 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
 }
 
 // ---------------------------------------------------------------- launchers
+// Pass program of the 3D executor.  The machine walks the step program:
+// a potential action opens (or joins, up to two) a z-pass that inverts the
+// z transform first when the state is z-transformed; a kinetic action closes
+// the open z-pass with a forward z transform (or adds a transform-only
+// z-pass) and adds y-forward, x (phase), y-inverse.
+struct PassMachine {
+  bool zk = false, zopen = false, zpre = false;
+  int zv[2] = {0, 0}, znv = 0;
+  bool operator==(const PassMachine& o) const {
+    return zk == o.zk && zopen == o.zopen && zpre == o.zpre && znv == o.znv &&
+           (znv < 1 || zv[0] == o.zv[0]) && (znv < 2 || zv[1] == o.zv[1]);
+  }
+};
+
+void flush_z(PassMachine& m, bool post_fwd, std::vector<PassDesc>& out) {
+  PassDesc p;
+  p.kind = PassDesc::Z;
+  p.pre_inv = m.zpre;
+  p.post_fwd = post_fwd;
+  p.nv = m.znv;
+  p.iv0 = m.zv[0];
+  p.iv1 = m.zv[1];
+  out.push_back(p);
+  m.zopen = false;
+  m.znv = 0;
+  m.zk = post_fwd;
+}
+
+void emit_step(const DevView& d, PassMachine& m, std::vector<PassDesc>& out) {
+  for (int a = 0; a < d.nact; ++a) {
+    const int code = d.hprog[a];
+    const int idx = prog_idx(code);
+    if (prog_op(code) == OP_V) {
+      if (m.zopen && m.znv == 2) flush_z(m, false, out);
+      if (!m.zopen) {
+        m.zopen = true;
+        m.zpre = m.zk;
+        m.znv = 0;
+        m.zk = false;
+      }
+      m.zv[m.znv++] = idx;
+    } else {
+      if (m.zopen) {
+        flush_z(m, true, out);
+      } else if (!m.zk) {
+        PassDesc p;
+        p.kind = PassDesc::Z;
+        p.post_fwd = true;
+        out.push_back(p);
+        m.zk = true;
+      }
+      PassDesc y, x, yi;
+      y.kind = PassDesc::YF;
+      x.kind = PassDesc::XP;
+      x.tidx = idx;
+      yi.kind = PassDesc::YI;
+      out.push_back(y);
+      out.push_back(x);
+      out.push_back(yi);
+    }
+  }
+}
+
+void emit_flush(PassMachine& m, std::vector<PassDesc>& out) {
+  if (m.zopen) {
+    flush_z(m, false, out);
+  } else if (m.zk) {
+    PassDesc p;
+    p.kind = PassDesc::Z;
+    p.pre_inv = true;
+    out.push_back(p);
+    m.zk = false;
+  }
+}
+
 template <typename K>
 hipError_t set_lds(K k, size_t bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
@@ -399,7 +475,7 @@ struct Passes {
 
   // algorithmic bytes of one pass: psi read + written, plus tables read
   static double pass_bytes(const DevView& d, int ntables) {
-    return (2.0 * S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>);
+    return (2.0 * S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>) * d.count;
   }
 
   template <bool PI, bool PF>
@@ -409,7 +485,7 @@ struct Passes {
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
-    hipLaunchKernelGGL(k, dim3(N / CZ, N), dim3(CZ * SC::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / CZ, N, d.count), dim3(CZ * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0]);
     return hipGetLastError();
   }
@@ -427,7 +503,7 @@ struct Passes {
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
-    hipLaunchKernelGGL(k, dim3(N / C, N, d.S), dim3(C * XS::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / C, N, d.S * d.count), dim3(C * XS::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[1]);
     return hipGetLastError();
   }
@@ -439,57 +515,96 @@ struct Passes {
     if (e != hipSuccess) return e;
     const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
     TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));
-    hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S), dim3(ROWS * XS::TPC), lds, d.stream, psi,
+    hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S * d.count), dim3(ROWS * XS::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.tw[2], kin, conj);
     return hipGetLastError();
   }
 
-  // Walks the action program for nsteps steps and emits the passes.
+  // Launches one pass descriptor.
+  static hipError_t launch(const DevView& d, cx<T>* psi, const PassDesc& p, int conj) {
+    switch (p.kind) {
+      case PassDesc::Z: return zpass(d, psi, p.pre_inv, p.post_fwd, p.nv, p.iv0, p.iv1, conj);
+      case PassDesc::YF: return ypass<false>(d, psi);
+      case PassDesc::YI: return ypass<true>(d, psi);
+      default: return xpass<XP_PHASE>(d, psi, p.tidx, conj);
+    }
+  }
+  static hipError_t launch_all(const DevView& d, cx<T>* psi, const std::vector<PassDesc>& v,
+                               int conj) {
+    for (const PassDesc& p : v) {
+      hipError_t e = launch(d, psi, p, conj);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
   static hipError_t propagate(const DevView& d, void* vpsi, int64_t nsteps, int conj) {
     cx<T>* psi = (cx<T>*)vpsi;
-    bool zk = false;        // z axis currently in the momentum representation
-    bool zopen = false;     // a z-pass is being assembled
-    bool zpre = false;
-    int zv[2] = {0, 0}, znv = 0;
-    hipError_t e = hipSuccess;
-    auto flush = [&](bool post_fwd) -> hipError_t {
-      hipError_t r = zpass(d, psi, zpre, post_fwd, znv, zv[0], zv[1], conj);
-      zopen = false;
-      znv = 0;
-      zk = post_fwd;
-      return r;
-    };
-    for (int64_t step = 0; step < nsteps; ++step) {
-      for (int a = 0; a < d.nact; ++a) {
-        const int code = d.hprog[a];
-        const int idx = prog_idx(code);
-        if (prog_op(code) == OP_V) {
-          if (zopen && znv == 2) {
-            if ((e = flush(false)) != hipSuccess) return e;
-          }
-          if (!zopen) {
-            zopen = true;
-            zpre = zk;
-            znv = 0;
-            zk = false;
-          }
-          zv[znv++] = idx;
-        } else {
-          if (zopen) {
-            if ((e = flush(true)) != hipSuccess) return e;
-          } else if (!zk) {
-            if ((e = zpass(d, psi, false, true, 0, 0, 0, conj)) != hipSuccess) return e;
-            zk = true;
-          }
-          if ((e = ypass<false>(d, psi)) != hipSuccess) return e;
-          if ((e = xpass<XP_PHASE>(d, psi, idx, conj)) != hipSuccess) return e;
-          if ((e = ypass<true>(d, psi)) != hipSuccess) return e;
-        }
+    PassMachine m0;
+    std::vector<PassDesc> first, body, tail;
+    PassMachine m1 = m0;
+    emit_step(d, m1, first);
+    const bool use_graph = d.graphs != nullptr && d.timer == nullptr && nsteps >= 4;
+    if (!use_graph) {
+      hipError_t e = launch_all(d, psi, first, conj);
+      if (e != hipSuccess) return e;
+      PassMachine m = m1;
+      for (int64_t step = 1; step < nsteps; ++step) {
+        body.clear();
+        emit_step(d, m, body);
+        if ((e = launch_all(d, psi, body, conj)) != hipSuccess) return e;
       }
+      emit_flush(m, tail);
+      return launch_all(d, psi, tail, conj);
     }
-    if (zopen) return flush(false);
-    if (zk) return zpass(d, psi, true, false, 0, 0, 0, conj);
-    return hipSuccess;
+    PassMachine m2 = m1;
+    emit_step(d, m2, body);
+    PassMachine m3 = m2;
+    std::vector<PassDesc> body2;
+    emit_step(d, m3, body2);
+    if (!(m2 == m3) || !(body == body2)) {  // no steady state: launch eagerly
+      DevView e = d;
+      e.graphs = nullptr;
+      return propagate(e, vpsi, nsteps, conj);
+    }
+    emit_flush(m2, tail);
+    // graphs keyed by (state pointer, direction, member count, segment)
+    auto seg = [&](int which, const std::vector<PassDesc>& v, hipGraphExec_t* out) -> hipError_t {
+      GraphCache::Key key{(const void*)psi, conj, d.count, which};
+      auto it = d.graphs->execs.find(key);
+      if (it != d.graphs->execs.end()) {
+        *out = it->second;
+        return hipSuccess;
+      }
+      DevView c = d;
+      c.stream = d.graphs->capture;
+      hipError_t e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      hipError_t le = launch_all(c, psi, v, conj);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(c.stream, &g);
+      if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le;
+      }
+      if (e != hipSuccess) return e;
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return e;
+      d.graphs->execs[key] = x;
+      *out = x;
+      return hipSuccess;
+    };
+    hipGraphExec_t g1, g2, g3;
+    hipError_t e;
+    if ((e = seg(0, first, &g1)) != hipSuccess) return e;
+    if ((e = seg(1, body, &g2)) != hipSuccess) return e;
+    if ((e = seg(2, tail, &g3)) != hipSuccess) return e;
+    if ((e = hipGraphLaunch(g1, d.stream)) != hipSuccess) return e;
+    for (int64_t step = 1; step < nsteps; ++step)
+      if ((e = hipGraphLaunch(g2, d.stream)) != hipSuccess) return e;
+    return hipGraphLaunch(g3, d.stream);
   }
 
   static hipError_t fft_forward(const DevView& d, void* vpsi) {

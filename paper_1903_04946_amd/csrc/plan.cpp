@@ -198,6 +198,8 @@ struct sop_plan {
   double* d_theta = nullptr;  // [nparams]
   void* d_eig = nullptr;      // adjoint eigen table (FP64, tile layout)
   double* d_w = nullptr;      // [S] adjoint weights
+  sop::GraphCache* graphs = nullptr;
+  bool use_graphs = true;
 };
 
 namespace {
@@ -207,6 +209,7 @@ void free_plan(sop_plan* p) {
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
                   p->d_dv, p->d_theta, p->d_eig, p->d_w};
+  delete p->graphs;
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p->timer;
@@ -439,6 +442,12 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
 
   p->tile = p->ndim == 3 ? sop::k3d_table_tile(p->n[0], f64) : 0;
   HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
+  if (p->ndim == 3) {
+    p->graphs = new (std::nothrow) sop::GraphCache();
+    if (!p->graphs) return fail(SOP_ERR_NOMEM, "host allocation failed");
+    HIPTRY(hipStreamCreateWithFlags(&p->graphs->capture, hipStreamNonBlocking));
+    d.graphs = p->graphs;
+  }
   p->nparams = desc->nparams;
   if (p->nparams > 0) {
     const size_t dvb = (size_t)p->nparams * vbytes;
@@ -503,10 +512,31 @@ sop_status sop_propagate(sop_plan* p, void* psi, int64_t nsteps, int direction) 
   if (direction != 1 && direction != -1) return fail(SOP_ERR_INVALID, "direction must be +1 or -1");
   if (nsteps == 0) return SOP_OK;
   const int conj = direction < 0 ? 1 : 0;
+  if (p->graphs && p->graphs->execs.size() > 48) {
+    HIPTRY(hipStreamSynchronize(p->dv.stream));
+    p->graphs->clear();
+  }
   if (p->ndim == 1)
     HIPTRY(sop::k1d_propagate(p->dv, psi, nsteps, conj));
   else
     HIPTRY(sop::k3d_propagate(p->dv, psi, nsteps, conj));
+  return SOP_OK;
+}
+
+sop_status sop_propagate_many(sop_plan* p, void* psi, int count, int64_t nsteps, int direction) {
+  if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (count < 1 || count > 65535) return fail(SOP_ERR_INVALID, "count must be 1..65535");
+  if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
+  if (direction != 1 && direction != -1) return fail(SOP_ERR_INVALID, "direction must be +1 or -1");
+  if (nsteps == 0) return SOP_OK;
+  const int conj = direction < 0 ? 1 : 0;
+  if (p->ndim == 1) {
+    HIPTRY(sop::k1d_propagate(p->dv, psi, nsteps, conj, count));
+  } else {
+    sop::DevView d = p->dv;
+    d.count = count;
+    HIPTRY(sop::k3d_propagate(d, psi, nsteps, conj));
+  }
   return SOP_OK;
 }
 
@@ -683,6 +713,18 @@ sop_status sop_adjoint_backward(sop_plan* p, int64_t nsteps, int K, const double
   HIPTRY(hipStreamSynchronize(s));
   for (int k = 0; k < p->nparams; ++k) grad_out[k] = 2.0 * p->dV * raw[k];
   return SOP_OK;
+}
+
+sop_status sop_plan_set_option(sop_plan* p, int option, int value) {
+  if (!p) return fail(SOP_ERR_INVALID, "plan is NULL");
+  switch (option) {
+    case SOP_OPT_GRAPHS:
+      p->use_graphs = value != 0;
+      p->dv.graphs = (p->use_graphs && p->graphs) ? p->graphs : nullptr;
+      return SOP_OK;
+    default:
+      return fail(SOP_ERR_INVALID, "unknown option");
+  }
 }
 
 sop_status sop_plan_set_timing(sop_plan* p, int enable) {

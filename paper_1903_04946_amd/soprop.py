@@ -51,7 +51,8 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
-           "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward"]
+           "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
+           "sop_propagate_many", "sop_plan_set_option"]
 KINDS = ["zpass", "ypass", "xpass", "k1d", "other"]
 
 _lib = None
@@ -83,6 +84,8 @@ def lib():
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
+    L.sop_propagate_many.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+    L.sop_plan_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sop_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_size_t)]
     L.sop_adjoint_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, dp]
@@ -91,7 +94,8 @@ def lib():
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
               "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
-              "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward"):
+              "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
+              "sop_propagate_many", "sop_plan_set_option"):
         getattr(L, f).restype = ctypes.c_int
     L.sop_supported_length.restype = ctypes.c_int
     _lib = L
@@ -282,11 +286,27 @@ class Plan:
                                    int(direction)), "sop_propagate")
         return psi
 
+    def propagate_many(self, psis, nsteps: int, direction: int = 1):
+        """Propagates a contiguous [count, S, n...] tensor of states in place."""
+        import torch
+        if not isinstance(psis, torch.Tensor) or not psis.is_cuda or psis.dtype != self.dtype:
+            raise TypeError("psis must be a CUDA tensor of the plan's dtype")
+        if tuple(psis.shape[1:]) != self.shape or not psis.is_contiguous() or psis.dim() < 2:
+            raise ValueError(f"psis must be contiguous of shape [count, {self.shape}]")
+        _check(lib().sop_propagate_many(self._h, ctypes.c_void_p(psis.data_ptr()),
+                                        int(psis.shape[0]), int(nsteps), int(direction)),
+               "sop_propagate_many")
+        return psis
+
     def apply_action(self, psi, op: str, coef: float):
         self._check_psi(psi)
         _check(lib().sop_apply_action(self._h, ctypes.c_void_p(psi.data_ptr()),
                                       0 if op == "V" else 1, float(coef)), "sop_apply_action")
         return psi
+
+    def set_graphs(self, enable: bool):
+        """3D runs of >= 4 steps as captured HIP graphs (default on)."""
+        _check(lib().sop_plan_set_option(self._h, 1, int(bool(enable))), "sop_plan_set_option")
 
     def set_timing(self, enable: bool):
         """Brackets every kernel launch with HIP events (measurement aid)."""

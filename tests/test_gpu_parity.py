@@ -357,3 +357,60 @@ def test_3d_256_strang(torch_cuda, orc):
     got, _ = gpu_run(torch, m, "VTV", "strang", 2, 10.0, 1)
     ref = oracle_run(orc, m, "VTV", "strang", 2, 10.0, 1)
     assert rel_l2(got, ref) < FP64_TOL
+
+
+def test_propagate_many_equals_single_runs(torch_cuda):
+    """Several states of one plan in one launch: each equals its single run."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.two_surface_1d(n=1024)
+    plan = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=0.05)
+    rng = np.random.default_rng(2)
+    x = m.axes()[0]
+    states = np.zeros((5, 2, 1024), complex)
+    for i in range(5):
+        states[i, 0] = synth.gaussian_1d(x, rng.uniform(-3, 3), rng.uniform(-2, 2), 0.7)
+        states[i] = synth.normalise(states[i], m.dV)
+    many = torch.from_numpy(states.copy()).cuda()
+    plan.propagate_many(many, 15)
+    for i in range(5):
+        one = torch.from_numpy(states[i].copy()).cuda()
+        plan.propagate(one, 15)
+        np.testing.assert_array_equal(many[i].cpu().numpy(), one.cpu().numpy())
+
+
+def test_3d_graph_replays_match_eager(torch_cuda, orc):
+    """Step segments captured as HIP graphs and replayed: every replay is
+    bitwise equal to eager launches, with eager work and synchronisations
+    between the replays; the result also matches the oracle."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32)
+    g = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=10.0)
+    e = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=10.0)
+    e.set_graphs(False)
+    pg = torch.from_numpy(m.psi0.copy()).cuda()
+    pe = torch.from_numpy(m.psi0.copy()).cuda()
+    for rep in range(4):
+        g.propagate(pg, 6)
+        torch.cuda.synchronize()
+        e.propagate(pe, 6)
+        torch.cuda.synchronize()
+        scratch = torch.ones(1000, device="cuda").sum()  # unrelated eager work
+        np.testing.assert_array_equal(pg.cpu().numpy(), pe.cpu().numpy())
+    ref = oracle_run(orc, m, "VTV", "triple_jump", 4, 10.0, 24)
+    assert rel_l2(pg.cpu().numpy(), ref) < FP64_TOL
+
+
+def test_3d_propagate_many(torch_cuda):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32)
+    plan = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=10.0)
+    states = np.stack([m.psi0, np.roll(m.psi0, 3, axis=1), np.roll(m.psi0, -2, axis=3)])
+    many = torch.from_numpy(states.copy()).cuda()
+    plan.propagate_many(many, 5)
+    for i in range(3):
+        one = torch.from_numpy(states[i].copy()).cuda()
+        plan.propagate(one, 5)
+        np.testing.assert_array_equal(many[i].cpu().numpy(), one.cpu().numpy())
