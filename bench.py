@@ -127,26 +127,20 @@ def _interp_time(points, eps):
     return None
 
 
-def time_to_error(torch, soprop, tf=10.0, kmax=10, kmax_strang=16, members=256, fp32=True):
-    """Wall time to reach a final-time L2 error (config-2 model: 1D two-surface,
-    N = 1024), against a TJ-10 reference at dt = 2^-12, for every scheme.
+class _Runner:
+    """Propagates a model to t_f in chunks (at most ~10 s per launch batch),
+    printing progress, and returns the final state and the event time."""
 
-    FP64 runs are single runs (one wavepacket).  FP32 runs propagate `members`
-    wavepackets in one launch (x0 ~ U[-3, 3], p0 ~ U[-2, 2], seed 4946), each
-    compared with its own FP64 reference; time is amortised per member.
-    """
-    import numpy as np
-    from paper_1903_04946_amd import synth
+    def __init__(self, torch, soprop, model):
+        self.torch, self.soprop, self.model = torch, soprop, model
 
-    base = synth.two_surface_1d(n=1024)
-    dV = base.dV
-
-    def run(model_psi, comp, order, dt, nsteps, dtype, count=1, label=""):
-        """Propagates in chunks of at most ~10 s each, printing progress."""
-        plan = soprop.Plan.from_model(base, comp=comp, order=order, dt=dt, dtype=dtype)
-        psi = torch.from_numpy(model_psi).to(dtype).cuda()
+    def __call__(self, psi0, comp, order, nsteps, tf, dtype, count=1, label=""):
+        torch = self.torch
+        plan = self.soprop.Plan.from_model(self.model, comp=comp, order=order, dt=tf / nsteps,
+                                           dtype=dtype)
+        psi = torch.from_numpy(psi0).to(dtype).cuda()
         done, total = 0, 0.0
-        chunk = max(1, min(nsteps, 256))
+        chunk = max(1, min(nsteps, 64))
         while done < nsteps:
             k = min(chunk, nsteps - done)
             e0 = torch.cuda.Event(enable_timing=True)
@@ -161,106 +155,151 @@ def time_to_error(torch, soprop, tf=10.0, kmax=10, kmax_strang=16, members=256, 
             sec = e0.elapsed_time(e1) / 1e3
             total += sec
             done += k
-            # grow the chunk towards ~10 s per launch
             chunk = max(1, min(nsteps, int(k * min(4.0, 10.0 / max(sec, 1e-4)))))
             if total > 5.0:
-                print(f"[tte] {label} {comp}-{order} dt={dt:.3g} {done}/{nsteps} steps {total:.1f} s",
+                print(f"[tte] {label} {comp}-{order} {done}/{nsteps} steps {total:.1f} s",
                       file=sys.stderr, flush=True)
-        return psi.cpu().numpy().astype(np.complex128), total
+        out = psi.cpu().numpy().astype("complex128")
+        del plan
+        return out, total
 
-    def err(a, b):
-        return float(np.sqrt(np.sum(np.abs(a - b) ** 2, axis=tuple(range(a.ndim - 2, a.ndim))) * dV).max()
-                     if a.ndim > 2 else np.sqrt(np.sum(np.abs(a - b) ** 2) * dV))
 
-    out = {"model": "two-surface 1D, N = 1024, t_f = 10 a.u.", "reference": "TJ-10, dt = 2^-12, FP64"}
-    kref = 12
-    ref, tref = run(base.psi0, "triple_jump", 10, 2.0**-kref, int(tf * 2**kref), torch.complex128,
-                    label="reference")
-    # cross-check of the reference with SF-10 at 2^-9
-    chk, _ = run(base.psi0, "suzuki", 10, 2.0**-9, int(tf * 2**9), torch.complex128, label="check")
-    out["reference_check_sf10_dt2^-9"] = err(chk, ref)
-    print(f"[tte] reference {tref:.1f} s, SF-10 check error {out['reference_check_sf10_dt2^-9']:.2e}",
-          file=sys.stderr, flush=True)
-    fp64 = {}
-    for comp, order in TTE_SCHEMES:
+def _l2(a, b, dV, batch=False):
+    import numpy as np
+    d = np.abs(a - b) ** 2
+    if batch:
+        return float(np.sqrt(d.reshape(d.shape[0], -1).sum(axis=1) * dV).max())
+    return float(np.sqrt(d.sum() * dV))
+
+
+def _sweep(run, psi0, ref, dV, tf, schemes, kmax, dtype, eps_stop, count=1, kmax_strang=None):
+    out = {}
+    for comp, order in schemes:
+        top = kmax_strang if (comp == "strang" and kmax_strang) else kmax
         pts = []
-        top = kmax_strang if comp == "strang" else kmax
         prev = None
         for k in range(1, top + 1):
-            nsteps = int(tf * 2**k)
-            psi, sec = run(base.psi0, comp, order, tf / nsteps, nsteps, torch.complex128)
-            e = err(psi, ref)
-            pts.append((sec, e, k))
-            print(f"[tte] fp64 {comp}-{order} dt=2^-{k} err={e:.3e} {sec:.3f} s",
-                  file=sys.stderr, flush=True)
-            if e < 1e-11 or (prev is not None and e > prev and e < 1e-8):
+            psi, sec = run(psi0, comp, order, 2**k, tf, dtype, count=count)
+            e = _l2(psi, ref, dV, batch=count > 1)
+            pts.append((sec / count, e, k))
+            print(f"[tte] {'fp64' if dtype == run.torch.complex128 else 'fp32'} x{count} "
+                  f"{comp}-{order} dt=t_f/2^{k} err={e:.3e} {sec:.3f} s", file=sys.stderr,
+                  flush=True)
+            if e < eps_stop or (prev is not None and e > 2 * prev and e < 1e-8):
                 break
             prev = e
-        name = f"{comp}-{order}"
-        tte = _interp_time([(t, e) for t, e, _ in pts], 1e-10)
-        rec = {"runs": [{"dt": f"2^-{k}", "seconds": t, "error": e} for t, e, k in pts],
-               "time_to_1e-10_s": tte}
-        if tte is None and comp == "strang":
-            # extrapolate along the dt^2 asymptote fitted to the two finest
-            # points above the round-off floor
-            good = [(t, e, k) for t, e, k in pts if e > 1e-9]
-            if len(good) >= 2:
-                (t1, e1, k1), (t2, e2, k2) = good[-2], good[-1]
-                c = e2 / (2.0**-k2) ** 2
-                dt_star = (1e-10 / c) ** 0.5
-                sec_per_step = t2 / (tf * 2**k2)
-                rec["time_to_1e-10_s"] = sec_per_step * tf / dt_star
-                rec["extrapolated"] = True
-        fp64[name] = rec
-    out["fp64_single_run"] = fp64
-    best = min((v["time_to_1e-10_s"], k) for k, v in fp64.items()
-               if v["time_to_1e-10_s"] is not None and not k.startswith("strang"))
-    st = fp64["strang-2"]["time_to_1e-10_s"]
-    out["fp64_best"] = {"scheme": best[1], "seconds": best[0],
-                        "speedup_vs_strang": (st / best[0]) if st else None,
-                        "strang_extrapolated": bool(fp64["strang-2"].get("extrapolated"))}
-    if fp32:
-        rng = np.random.Generator(np.random.PCG64(4946))
-        x = base.axes()[0]
-        psis = np.zeros((members, 2, 1024), complex)
-        for i in range(members):
-            psis[i, 0] = synth.gaussian_1d(x, rng.uniform(-3, 3), rng.uniform(-2, 2), base.meta["sigma"])
-            psis[i] = synth.normalise(psis[i], dV)
-        refs, tref_b = run(psis, "triple_jump", 10, 2.0**-kref, int(tf * 2**kref), torch.complex128,
-                           count=members, label="batched references")
-        b32 = {}
-        for comp, order in [("strang", 2), ("triple_jump", 4), ("suzuki", 4), ("suzuki", 6),
-                            ("triple_jump", 6)]:
-            pts = []
-            for k in range(1, 13):
-                nsteps = int(tf * 2**k)
-                dtype = torch.complex64
-                psi, sec = run(psis, comp, order, tf / nsteps, nsteps, dtype, count=members)
-                e = err(psi, refs)
-                pts.append((sec / members, e, k))
-                print(f"[tte] fp32 x{members} {comp}-{order} dt=2^-{k} max err={e:.3e} "
-                      f"{sec:.3f} s", file=sys.stderr, flush=True)
-                if e < 1e-6:
-                    break
-            b32[f"{comp}-{order}"] = {
-                "runs": [{"dt": f"2^-{k}", "seconds_per_member": t, "max_error": e} for t, e, k in pts],
-                "time_to_1e-5_s_per_member": _interp_time([(t, e) for t, e, _ in pts], 1e-5)}
-        out["fp32_batched"] = {"members": members, "schemes": b32}
-        # FP64 Strang, batched the same way, for comparison
-        pts = []
-        for k in range(1, 14):
-            nsteps = int(tf * 2**k)
-            psi, sec = run(psis, "strang", 2, tf / nsteps, nsteps, torch.complex128, count=members)
-            e = err(psi, refs)
-            pts.append((sec / members, e))
-            print(f"[tte] fp64 x{members} strang dt=2^-{k} max err={e:.3e} {sec:.3f} s",
-                  file=sys.stderr, flush=True)
-            if e < 1e-6:
-                break
-        out["fp64_strang_batched_time_to_1e-5_s_per_member"] = _interp_time(pts, 1e-5)
-        out["fp64_strang_single_time_to_1e-5_s"] = _interp_time(
-            [(r["seconds"], r["error"]) for r in fp64["strang-2"]["runs"]], 1e-5)
+        out[f"{comp}-{order}"] = pts
     return out
+
+
+def _strang_extrapolation(pts, tf, eps):
+    """Time along the dt^2 asymptote fitted to the finest Strang points."""
+    good = [(t, e, k) for t, e, k in pts if e > 100 * eps]
+    if len(good) < 2:
+        return None
+    t2, e2, k2 = good[-1]
+    c = e2 / (tf / 2**k2) ** 2
+    dt_star = (eps / c) ** 0.5
+    return t2 / 2**k2 * tf / dt_star
+
+
+def time_to_error(torch, soprop, members=256):
+    """Time to reach a final-time L2 error of 1e-10 (FP64, single run) and of
+    1e-5 (FP32, batched) for every composition, against plain Strang.
+
+    Workload: the three-mode, three-surface LVC model on a 32^3 grid (the
+    paper's pyrazine grid: 32 points per mode on [-7, 7]), t_f = 500 a.u.
+    FP64 reference: TJ-10 at dt = t_f/2^12 (checked against SF-10 at
+    t_f/2^9).  FP32 batch: `members` initial packets on surface 3 with
+    q0 ~ U[-3, 3]^3, p0 ~ U[-2, 2]^3 (seed 4946), each compared with its own
+    FP64 reference (TJ-8 at t_f/2^10, one batched launch); times are per
+    member.  Also records the configured 1D two-surface sweep (dt = 2^-1 ..
+    2^-10 to t = 10 against TJ-10 at 2^-12) as measured.
+    """
+    import numpy as np
+    from paper_1903_04946_amd import synth
+
+    res = {}
+    # ----------------------------------------------------------- 3D LVC, 32^3
+    m = synth.lvc_3d(n=32)
+    run = _Runner(torch, soprop, m)
+    tf = 500.0
+    ref, tref = run(m.psi0, "triple_jump", 10, 2**12, tf, torch.complex128, label="reference")
+    chk, _ = run(m.psi0, "suzuki", 10, 2**9, tf, torch.complex128, label="check")
+    r3 = {"model": "LVC 3 modes x 3 surfaces, 32^3 on [-7,7)^3, t_f = 500 a.u.",
+          "reference": "TJ-10, dt = t_f/2^12, FP64", "reference_time_s": tref,
+          "reference_vs_sf10_t_f/2^9": _l2(chk, ref, m.dV)}
+    sw = _sweep(run, m.psi0, ref, m.dV, tf, TTE_SCHEMES, 12, torch.complex128, 1e-11,
+                kmax_strang=17)
+    fp64 = {}
+    for name, pts in sw.items():
+        rec = {"runs": [{"dt": f"t_f/2^{k}", "seconds": t, "error": e} for t, e, k in pts],
+               "time_to_1e-10_s": _interp_time([(t, e) for t, e, _ in pts], 1e-10)}
+        if rec["time_to_1e-10_s"] is None and name == "strang-2":
+            rec["time_to_1e-10_s"] = _strang_extrapolation(pts, tf, 1e-10)
+            rec["extrapolated"] = True
+        fp64[name] = rec
+    r3["fp64_single_run"] = fp64
+    cand = [(v["time_to_1e-10_s"], k) for k, v in fp64.items()
+            if v["time_to_1e-10_s"] is not None and not k.startswith("strang")]
+    st = fp64["strang-2"]["time_to_1e-10_s"]
+    if cand:
+        best = min(cand)
+        r3["fp64_best"] = {"scheme": best[1], "seconds": best[0],
+                           "strang_seconds": st,
+                           "speedup_vs_strang": (st / best[0]) if st else None,
+                           "strang_extrapolated": bool(fp64["strang-2"].get("extrapolated"))}
+    # FP32 batched
+    rng = np.random.Generator(np.random.PCG64(4946))
+    ax = m.axes()
+    psis = np.zeros((members, 3, 32, 32, 32), complex)
+    for i in range(members):
+        q0 = rng.uniform(-3, 3, 3)
+        p0 = rng.uniform(-2, 2, 3)
+        g = [synth.gaussian_1d(ax[d], q0[d], p0[d], 1.0) for d in range(3)]
+        psis[i, 2] = g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :]
+        psis[i] = synth.normalise(psis[i], m.dV)
+    refs, trefs = run(psis, "triple_jump", 8, 2**10, tf, torch.complex128, count=members,
+                      label="batched references")
+    b32 = _sweep(run, psis, refs, m.dV, tf,
+                 [("strang", 2), ("suzuki", 4), ("triple_jump", 4), ("suzuki", 6)], 10,
+                 torch.complex64, 1e-6, count=members)
+    r3["fp32_batched"] = {
+        "members": members, "reference": "TJ-8, dt = t_f/2^10, FP64 (batched)",
+        "schemes": {n: {"runs": [{"dt": f"t_f/2^{k}", "seconds_per_member": t, "max_error": e}
+                                 for t, e, k in pts],
+                        "time_to_1e-5_s_per_member": _interp_time([(t, e) for t, e, _ in pts],
+                                                                  1e-5)}
+                    for n, pts in b32.items()}}
+    b64 = _sweep(run, psis, refs, m.dV, tf, [("strang", 2)], 12, torch.complex128, 1e-6,
+                 count=members)
+    r3["fp64_strang_batched_time_to_1e-5_s_per_member"] = _interp_time(
+        [(t, e) for t, e, _ in b64["strang-2"]], 1e-5)
+    r3["fp64_strang_single_time_to_1e-5_s"] = _interp_time(
+        [(r["seconds"], r["error"]) for r in fp64["strang-2"]["runs"]], 1e-5)
+    res["lvc3d_32cube"] = r3
+    # ----------------------------------------------------------- configured 1D
+    m1 = synth.two_surface_1d(n=1024)
+    run1 = _Runner(torch, soprop, m1)
+    tf1 = 10.0
+    ref1, _ = run1(m1.psi0, "triple_jump", 10, int(tf1 * 2**12), tf1, torch.complex128,
+                   label="1D reference")
+    rows = {}
+    for comp, order in TTE_SCHEMES:
+        kmax = {10: 6, 8: 8}.get(order, 10) if comp == "suzuki" else 10
+        pts = []
+        for k in range(1, kmax + 1):
+            psi, sec = run1(m1.psi0, comp, order, int(tf1 * 2**k), tf1, torch.complex128)
+            pts.append({"dt": f"2^-{k}", "seconds": sec, "error": _l2(psi, ref1, m1.dV)})
+        rows[f"{comp}-{order}"] = pts
+        print(f"[tte] 1D {comp}-{order} errors " + " ".join(f"{p['error']:.1e}" for p in pts),
+              file=sys.stderr, flush=True)
+    res["twosurf1d_configured"] = {
+        "model": "1D two-surface, N = 1024 on [-10,10), t_f = 10, reference TJ-10 at 2^-12",
+        "runs": rows,
+        "note": "pre-asymptotic at every dt here (steep repulsive wall on surface 2): "
+                "no scheme reaches 1e-10"}
+    return res
 
 
 def main(argv=None) -> int:
@@ -271,7 +310,7 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-to-error", action="store_true",
-                    help="also run the config-2 time-to-error sweep (about a minute)")
+                    help="also run the time-to-error sweeps (about two minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args(argv)

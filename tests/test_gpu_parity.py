@@ -277,12 +277,12 @@ def test_fp32_1d_config1(torch_cuda, orc):
     got, plan = gpu_run(torch, m, "VTV", "strang", 2, 0.01, 1000, dtype=torch.complex64)
     ref = oracle_run(orc, m, "VTV", "strang", 2, 0.01, 1000)
     err = rel_l2(got, ref)
-    print(f"[fp32] config-1 relative L2 error vs FP64 oracle: {err:.3e}")
+    print(f"[fp32] 1D two-surface, 1000 Strang steps: relative L2 error vs FP64 oracle: {err:.3e}")
     assert err < 1e-4
     ob = plan.observables(torch.from_numpy(got.astype(np.complex64)).cuda())
     # the FP32 unitaries are unitary to ~eps32 each, coherently over the
     # 3000 actions: stated norm bound 2e-4
-    print(f"[fp32] config-1 norm - 1 = {ob['norm'] - 1:.3e}")
+    print(f"[fp32] 1D two-surface, 1000 Strang steps: norm - 1 = {ob['norm'] - 1:.3e}")
     assert abs(ob["norm"] - 1) < 2e-4
 
 
