@@ -51,6 +51,8 @@ WORKLOADS = {
     "twosurf1d_1024_sf10_vtv_c128": (1, 1024, "suzuki", 10, 2.0**-6, "c128"),
 }
 DEFAULT = "lvc3d_128cube_x3_tj6_vtv_c128"
+# batched ensembles: 256 members of uneven grids, orders, dt and step counts
+ENSEMBLES = {"ensemble256_mixed_c128": "c128", "ensemble256_mixed_c64": "c64"}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
                   "paper_1903_04946_amd/csrc/fft_core.hpp"]
@@ -302,12 +304,126 @@ def time_to_error(torch, soprop, members=256):
     return res
 
 
+def _time_batch(torch, batch, psis, ns, steps, warmup):
+    for _ in range(warmup):
+        batch.propagate(psis, ns)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        batch.propagate(psis, ns)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def ensemble_cpu_baseline(models, man, Ms, budget_s=10.0):
+    """The FP64 oracle on one step of members in manifest order, until the
+    time budget is spent."""
+    from oracle import oracle as O
+    comp_id = {"strang": O.STRANG, "triple_jump": O.TRIPLE_JUMP, "suzuki": O.SUZUKI}
+    units = 0
+    sec = 0.0
+    used = 0
+    threads = 1
+    for m, e, M in zip(models, man, Ms):
+        P = O.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
+        _, t, threads = O.propagate_timed(P, m.psi0, O.VTV, comp_id[e["scheme"]], e["order"],
+                                          e["dt"], 1)
+        units += m.nsurf * m.npts * M
+        sec += t
+        used += 1
+        if sec > budget_s:
+            break
+    return {"value": units / sec, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"one step of each of the first {used} ensemble members "
+                      f"({sec:.2f} s of FP64 oracle step loops)"}
+
+
+def run_ensemble(a, torch, soprop):
+    """One step = one batch propagate call advancing all 256 members of the
+    ensemble to t_final (uneven step counts), as one graph launch."""
+    from paper_1903_04946_amd import synth
+    dts = ENSEMBLES[a.workload]
+    dtype = torch.complex128 if dts == "c128" else torch.complex64
+    cs = 16 if dts == "c128" else 8
+    man = synth.batch_manifest()
+    models = [synth.ensemble_model(e) for e in man]
+    plans = [soprop.Plan.from_model(m, comp=e["scheme"], order=e["order"], dt=e["dt"],
+                                    dtype=dtype) for e, m in zip(man, models)]
+    ns = [e["nsteps"] for e in man]
+    Ms = [p.info.M for p in plans]
+    units = sum(m.nsurf * m.npts * M * k for m, M, k in zip(models, Ms, ns))
+    t0 = time.perf_counter()
+    batch = soprop.Batch(plans)
+    create_s = time.perf_counter() - t0
+    psis = [torch.from_numpy(m.psi0).to(dtype).cuda() for m in models]
+    t0 = time.perf_counter()
+    ms = _time_batch(torch, batch, psis, ns, a.steps, a.warmup)
+    wall = time.perf_counter() - t0
+    desc = batch.describe()
+    # the 1D members alone and the 3D members alone
+    parts = {}
+    for kind in ("1d", "3d"):
+        idx = [i for i, e in enumerate(man) if e["kind"] == kind]
+        sub = soprop.Batch([plans[i] for i in idx])
+        sp = [psis[i] for i in idx]
+        parts[kind] = {"members": len(idx),
+                       "ms": _time_batch(torch, sub, sp, [ns[i] for i in idx], a.steps, 1),
+                       "units": sum(models[i].nsurf * models[i].npts * Ms[i] * ns[i]
+                                    for i in idx)}
+        sub.close()
+    # algorithmic HBM bytes of the 3D lockstep passes: every pass reads and
+    # writes the state; each potential action reads one table
+    b3 = 0.0
+    for i, e in enumerate(man):
+        if e["kind"] != "3d":
+            continue
+        m = models[i]
+        ne = m.nsurf * (m.nsurf + 1) // 2
+        cyc = Ms[i] * ns[i]
+        b3 += ((4 * cyc + 1) * 2 * m.nsurf + (Ms[i] + 1) * ns[i] * ne) * m.npts * cs
+    ach3 = b3 / (parts["3d"]["ms"] / 1e3) / 1e9
+    norms = [p.observables(x)["norm"] for p, x in zip(plans, psis)]
+    cpu = None if a.no_cpu_baseline else ensemble_cpu_baseline(models, man, Ms)
+    counts = {}
+    for e in man:
+        k = f"{e['kind']}_{e['n']}"
+        counts[k] = counts.get(k, 0) + 1
+    return {
+        "metric": METRIC, "value": units / (ms / 1e3), "unit": UNIT, "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if dts == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "members": len(man), "grids": counts,
+                   "t_final": 0.5, "dt_range": [0.005, 0.05], "orders": [2, 4, 6, 8],
+                   "substep_units_per_call": units, "state_dtype": dts},
+        "roofline": {"bound": "hbm", "kernel": "3d lockstep passes (all kinds)",
+                     "achieved": ach3, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach3 / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_call": b3},
+        "parts": {k: {"members": v["members"], "ms_per_call": v["ms"],
+                      "value": v["units"] / (v["ms"] / 1e3)} for k, v in parts.items()},
+        "batch": {"create_s": create_s, "graph": desc["graph"],
+                  "graph_nodes": desc["graph_nodes"], "branches": desc["branches"],
+                  "families": [{k: f[k] for k in ("n", "S", "variant", "schedule", "tuned_ms")}
+                               | {"members": len(f["members"])} for f in desc["families"]],
+                  "groups": [{k: g[k] for k in ("n", "S", "z_cols", "y_cols", "x_rows",
+                                                "tuned_ms", "max_cycles")}
+                             | {"members": len(g["members"])} for g in desc["groups"]]},
+        "cpu_baseline": cpu,
+        "checks": {"norm_max_dev": max(abs(x - 1) for x in norms), "wall_s_timed": wall},
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(ENSEMBLES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-to-error", action="store_true",
                     help="also run the time-to-error sweeps (about two minutes)")
@@ -332,6 +448,9 @@ def main(argv=None) -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload in ENSEMBLES:
+        print(json.dumps(run_ensemble(a, torch, soprop)))
+        return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64
     model = make_model(ndim, n)

@@ -245,6 +245,54 @@ enum { SOP_KIND_ZPASS = 0, SOP_KIND_YPASS = 1, SOP_KIND_XPASS = 2, SOP_KIND_1D =
 sop_status sop_plan_set_timing(sop_plan* plan, int enable);
 sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* bytes);
 
+/* ------------------------------------------------------------------ batches
+ * A batch propagates many independent plans -- any mix of 1D and 3D grids,
+ * surfaces, precisions, compositions, orders and dt -- with one HIP graph
+ * launch per call.  Members are grouped by the kernel that runs them
+ * together: 1D members of one (grid length, surfaces, precision) family run
+ * in one persistent launch, one workgroup per member for its whole run;
+ * 3D members on 32^3, 48^3 or 64^3 grids with a VTV program run in lockstep
+ * passes shared by every member of one (n, surfaces, precision) group, each
+ * member taking its own tables, coefficients and step count; any other
+ * member runs its own plan's executor in a branch of the same graph.  The
+ * per-member arithmetic is that of sop_propagate (3D members: bitwise the
+ * same result; 1D members: the same DFTs, possibly in another radix order,
+ * so equal up to rounding).
+ *
+ * sop_batch_create: plans[0..count) (1 <= count <= 65535; a plan may appear
+ * more than once; the batch keeps pointers, so the plans must outlive it)
+ * and the HIP stream that propagate calls run on.  It times the schedule
+ * variants of each family (values per thread and radix order) and the tile
+ * widths of each lockstep group's z, y and x passes on scratch states with
+ * the members' own tables, and keeps the fastest.  Environment:
+ * SOPROP_TUNE=0 keeps the default variants; SOPROP_TUNE_CACHE=<path> reads
+ * the choices from, and records new ones in, a JSON file of "key": "variant"
+ * pairs.  Synchronises the stream.
+ *
+ * sop_batch_propagate: psi_devs[i] is member i's state (device memory, the
+ * layout and dtype of plans[i]; states must not overlap), nsteps[i] >= 0 its
+ * step count, direction +1 or -1 for all members.  Asynchronous on the
+ * batch's stream.  The graph is captured on the first call and replayed
+ * while psi_devs, nsteps and direction stay the same; a call that changes
+ * them synchronises the stream once to rewrite the member descriptors.
+ * Runs longer than 200000 kernel launches are enqueued without a graph.
+ *
+ * sop_batch_set_option(SOP_OPT_GRAPHS, 0) enqueues the branches directly
+ * (same kernels, same results).
+ *
+ * sop_batch_describe writes a NUL-terminated JSON description (families,
+ * groups, chosen variants, tuning times in ms, branch count, whether the
+ * last call used a graph) into buf[0..len) (truncated if short; buf may be
+ * NULL) and the size it needs, NUL included, into *needed (may be NULL). */
+typedef struct sop_batch sop_batch;
+sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
+                            sop_batch** out);
+sop_status sop_batch_destroy(sop_batch* batch);
+sop_status sop_batch_propagate(sop_batch* batch, void* const* psi_devs, const int64_t* nsteps,
+                               int direction);
+sop_status sop_batch_set_option(sop_batch* batch, int option, int value);
+sop_status sop_batch_describe(const sop_batch* batch, char* buf, size_t len, size_t* needed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,8 +19,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsoprop.so")
-SOURCES = ["kernels_1d.hip", "kernels_3d.hip", "kernels_aux.hip", "plan.cpp"]
-HEADERS = ["fft_core.hpp", "internal.hpp"]
+SOURCES = ["kernels_3d.hip", "kernels_batch3d.hip", "kernels_batch1d.hip", "kernels_1d.hip",
+           "kernels_aux.hip", "plan.cpp", "batch.cpp"]
+HEADERS = ["fft_core.hpp", "internal.hpp", "body_1d.hpp", "passes_3d.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++20", "-O3", "--offload-arch=gfx950", "-fPIC",
          # never emit packed FP32 instructions
@@ -48,7 +49,7 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
-def build(force: bool = False, jobs: int = 4) -> str:
+def build(force: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
@@ -65,7 +66,7 @@ def build(force: bool = False, jobs: int = 4) -> str:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--force", action="store_true")
-    ap.add_argument("-j", "--jobs", type=int, default=4)
+    ap.add_argument("-j", "--jobs", type=int, default=6)
     a = ap.parse_args(argv)
     print(build(a.force, a.jobs))
     return 0

@@ -168,6 +168,57 @@ hipError_t grad_reduce(const DevView& d, const double* qacc, const double* dv, i
 // out_dev[0..S) = sum |psi_s|^2, out_dev[S] = sum psi^dag V psi (raw sums)
 hipError_t pops_reduce(const DevView& d, const void* psi, const double* vraw_dev,
                        double* partials, double* out_dev);
+// ------------------------------------------------------------------ batches
+// Device descriptor of one 1D member of a batch (kernels_batch1d.hip).
+struct BMember1 {
+  void* psi;          // [S][N]
+  const void* vexp;   // [n_vtab][S(S+1)/2][N]
+  const void* kin;    // [n_ttab][N]
+  const void* tw;     // [N] twiddles
+  const int* prog;    // step program
+  int64_t nsteps;
+  int nact;
+  int conj;
+};
+// Device descriptor of one 3D member of a lockstep group
+// (kernels_batch3d.hip).  The member's program is the pruned VTV sequence
+// V T V ... T V (nact = 2M + 1); cycle c < cycles = M * nsteps is its
+// kinetic action number c, cycle c = cycles its closing potential action.
+struct BMember3 {
+  void* psi;          // [S][n^3]
+  const void* vexp;   // tile-layout potential tables
+  const void* kin;    // [n_ttab][3][kin_stride]
+  const void* tw;     // [3][n] twiddles (z, y, x blocks)
+  const int* prog;
+  int64_t cycles;
+  int M;
+  int conj;
+  int kin_stride;
+  int pad;
+};
+
+// plan.cpp: the device view of a plan, and the thread-local error text that
+// sop_last_error returns.
+const DevView* plan_view(const sop_plan* p);
+void set_last_error(const std::string& msg);
+
+// 1D families: candidate schedules ("variants") of each length; variant 0 is
+// the schedule of the single-plan kernel.
+int k1b_variants(int n);
+const char* k1b_variant_name(int n, int variant);
+// Runs members mem[0..count) (one workgroup each, in order) with the variant.
+hipError_t k1b_launch(int n, int S, bool f64, int variant, const BMember1* mem, int count,
+                      hipStream_t stream);
+
+// 3D lockstep groups.  kind: 0 z-pass, 1 y forward, 2 x (phase), 3 y inverse;
+// the y variants apply to both y kinds.
+enum { B3_Z = 0, B3_YF = 1, B3_XP = 2, B3_YI = 3 };
+bool k3b_supported(int n, int S);
+int k3b_variants(int kind, int n, bool f64);
+int k3b_variant_width(int kind, int n, bool f64, int variant);  // columns or rows per tile
+hipError_t k3b_launch(int kind, int n, int S, bool f64, int variant, const BMember3* mem,
+                      int count, int64_t cycle, hipStream_t stream);
+
 constexpr int kMaxParams = 8;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;

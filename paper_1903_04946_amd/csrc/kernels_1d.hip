@@ -1,38 +1,11 @@
 // kernels_1d.hip -- one-dimensional grids: the whole composed time step runs
-// inside one persistent workgroup per wavepacket.
-//
-// The S-surface state stays in registers (radix-R_first ownership) for all
-// nsteps x (N_A + N_B) actions of the pruned sequence (Sec. "Pruning
-// splitting coefficients"); only the FFT stage exchanges touch LDS, and HBM
-// sees psi at entry and exit.  A potential action is the S x S matvec with
-// the stored table exp(-i a dt V(x)/hbar) of its unique coefficient
-// (Eq. range_index_unq); a kinetic action is forward FFT -> phase (with 1/N
-// folded in) -> inverse FFT (Sec. "Dynamic Fourier method").  A direction of
-// -1 conjugates every table, which is U(-dt).
-#include "fft_core.hpp"
-#include "internal.hpp"
+// inside one persistent workgroup per wavepacket (the step body is run_1d).
+#include "body_1d.hpp"
 
 namespace sop {
 namespace {
 
-// schedules: (N, E, forward radices, inverse radices = reversed, first, last).
-// Eight values per thread and surface keep a two-surface FP64 state plus a
-// radix-8 butterfly in about 128 VGPRs.
-using S16 = Sched<16, 4, RList<4, 4>, RList<4, 4>, 4, 4>;
-using S32 = Sched<32, 8, RList<8, 4>, RList<4, 8>, 8, 4>;
-using S64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
-using S128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
-using S256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
-using S512 = Sched<512, 8, RList<8, 8, 8>, RList<8, 8, 8>, 8, 8>;
-using S1024 = Sched<1024, 8, RList<8, 4, 4, 8>, RList<8, 4, 4, 8>, 8, 8>;
-using S2048 = Sched<2048, 8, RList<8, 8, 4, 8>, RList<8, 4, 8, 8>, 8, 8>;
-using S4096 = Sched<4096, 8, RList<8, 8, 8, 8>, RList<8, 8, 8, 8>, 8, 8>;
-using S8192 = Sched<8192, 8, RList<8, 8, 8, 8, 2>, RList<2, 8, 8, 8, 8>, 8, 2>;
-
-template <class SC>
-constexpr int lds_pencil() {
-  return SC::N + SC::N / 16;
-}
+using namespace s1d;
 
 // PL = pencils exchanged through LDS at once (S, or 1 when S pencils do not fit).
 template <typename T, class SC, int S, int PL>
@@ -42,67 +15,8 @@ __global__ void __launch_bounds__(SC::TPC)
                     const int* __restrict__ prog, int nact, int64_t nsteps, int conj) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
-  const int t = threadIdx.x;
-  psi += (size_t)blockIdx.x * S * N;  // one workgroup per state
-  const T csign = conj ? (T)-1 : (T)1;
-  cx<T> v[S][E];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = psi[s * N + own_idx<N, E, SC::RF>(t, q)];
-  const LayPadded lay{0, lds_pencil<SC>()};
-
-  for (int64_t step = 0; step < nsteps; ++step) {
-    for (int a = 0; a < nact; ++a) {
-      const int code = prog[a];
-      const int idx = code & 0xffff;
-      if ((code >> 16) == OP_V) {
-        const cx<T>* U = vexp + (size_t)idx * NE * N;
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-          const int x = own_idx<N, E, SC::RF>(t, q);
-          cx<T> u[NE];
-#pragma unroll
-          for (int e = 0; e < NE; ++e) {
-            u[e] = U[e * N + x];
-            u[e].im *= csign;
-          }
-          cx<T> w[S];
-#pragma unroll
-          for (int s = 0; s < S; ++s) w[s] = v[s][q];
-          apply_u<T, S>(w, u);
-#pragma unroll
-          for (int s = 0; s < S; ++s) v[s][q] = w[s];
-        }
-      } else {
-        if constexpr (PL == S) {
-          fft_forward<SC, S>(v, lds, lay, tw, t);
-        } else {
-#pragma unroll
-          for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
-        }
-        const cx<T>* F = kin + (size_t)idx * N;
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-          cx<T> f = F[own_idx<N, E, SC::RL>(t, q)];
-          f.im *= csign;
-#pragma unroll
-          for (int s = 0; s < S; ++s) v[s][q] = cmul(v[s][q], f);
-        }
-        if constexpr (PL == S) {
-          fft_inverse<SC, S>(v, lds, lay, tw, t);
-        } else {
-#pragma unroll
-          for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int q = 0; q < E; ++q) psi[s * N + own_idx<N, E, SC::RF>(t, q)] = v[s][q];
+  psi += (size_t)blockIdx.x * S * SC::N;  // one workgroup per state
+  run_1d<T, SC, S, PL>(psi, vexp, kin, tw, prog, nact, nsteps, conj, lds);
 }
 
 // Forward transform of every surface (natural order in and out), used for

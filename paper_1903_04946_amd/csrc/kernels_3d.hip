@@ -22,17 +22,12 @@
 #include <type_traits>
 #include <vector>
 
-#include "fft_core.hpp"
-#include "internal.hpp"
+#include "passes_3d.hpp"
 
 namespace sop {
 namespace {
 
-using Z32 = Sched<32, 8, RList<8, 4>, RList<4, 8>, 8, 4>;
-using Z48 = Sched<48, 12, RList<4, 4, 3>, RList<3, 4, 4>, 4, 3>;
-using Z64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
-using Z128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
-using Z256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
+using namespace s3d;
 
 // Schedules of the adjoint z-pass (2S pencils per thread): four values per
 // thread and pencil.
@@ -55,108 +50,22 @@ struct AdjSched<Z256> {
   using type = Sched<256, 4, RList<4, 4, 4, 4>, RList<4, 4, 4, 4>, 4, 4>;
 };
 
-// Schedules of the single-pencil y and x passes: sixteen values per thread
-// where that saves an LDS exchange.
-template <class SC>
-struct XYSched {
-  using type = SC;
-};
-template <>
-struct XYSched<Z128> {
-  using type = Sched<128, 16, RList<16, 8>, RList<8, 16>, 16, 8>;
-};
-template <>
-struct XYSched<Z256> {
-  using type = Sched<256, 16, RList<16, 16>, RList<16, 16>, 16, 16>;
-};
-
-// Columns per tile of the y-pass: at least a full wave per block and
-// 128-byte contiguous row segments.
-template <class SC, typename T>
-constexpr int cols() {
-  constexpr int seg = 128 / (int)sizeof(cx<T>);
-  return SC::TPC * seg >= 64 ? seg : 64 / SC::TPC;
-}
-// Columns per tile of the z-pass (16 in both precisions: 256-byte FP64 and
-// 128-byte FP32 segments of psi; the potential table is stored
-// tile-contiguous, see below).
+// Columns per tile of the z-pass: the table tile width.
 template <class SC, typename T>
 constexpr int zcols() {
-  return 16;
+  return kTableCols;
 }
 
 // ---------------------------------------------------------------- z-pass
-// Potential tables are stored per z-pass tile: for table u, tile
-// (y, x / C) holds [z][entry][x % C] contiguously, N * NE * C complex, so a
-// tile reads its table as one contiguous stream.
 template <typename T, class SC, int S, int C, bool PRE_INV, bool POST_FWD>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
               int conj, const cx<T>* __restrict__ tw) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
-  const int lane = threadIdx.x;
-  const int col = lane % C, t = lane / C;
-  const int x = blockIdx.x * C + col, y = blockIdx.y;
-  constexpr uint32_t plane = (uint32_t)N * N;
-  constexpr int64_t npts = (int64_t)plane * N;
-  constexpr uint32_t tile = (uint32_t)N * NE * C;
-  const uint32_t off0 = (uint32_t)y * N + x;
-  const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
-  const LayStrided lay{col, 0, C};  // one surface at a time through LDS
-  psi += (size_t)blockIdx.z * S * npts;  // member of a batch of states
-  cx<T> v[S][E];
-  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
-#pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
-  }
-  if constexpr (PRE_INV) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
-    // normalisation of the z round trip (exact for power-of-two N)
-    constexpr T inv_n = (T)1 / (T)N;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int q = 0; q < E; ++q) v[s][q] = cx<T>{v[s][q].re * inv_n, v[s][q].im * inv_n};
-  }
-  const T csign = conj ? (T)-1 : (T)1;
-  auto vact = [&](int iv) {
-    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * C) + col;
-      cx<T> u[NE];
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        u[e] = ld<T>(ru, pt + e * C);
-        u[e].im *= csign;
-      }
-      cx<T> w[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) w[s] = v[s][q];
-      apply_u<T, S>(w, u);
-#pragma unroll
-      for (int s = 0; s < S; ++s) v[s][q] = w[s];
-    }
-  };
-  if (nv >= 1) vact(iv0);
-  if (nv >= 2) vact(iv1);
-  if constexpr (POST_FWD) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
-  }
-  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
-#pragma unroll
-    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
-  }
+  psi += (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member of a batch
+  zpass_body<T, SC, S, C, C, PRE_INV, POST_FWD>(psi, vexp, nv, iv0, iv1, conj, tw, lds,
+                                                blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- adjoint z-pass
@@ -307,72 +216,26 @@ __global__ void __launch_bounds__(C * SC::TPC)
 }
 
 // ---------------------------------------------------------------- y-pass
+// grid (N / C, N, surfaces x states): blockIdx.z picks one surface pencil set
 template <typename T, class SC, int C, bool INV>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_ypass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  constexpr int N = SC::N, E = SC::E;
-  const int lane = threadIdx.x;
-  const int col = lane % C, t = lane / C;
-  const int x = blockIdx.x * C + col, z = blockIdx.y, s = blockIdx.z;
-  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
-  const auto base = rsrc(psi + s * npts + z * plane, (uint32_t)plane);
-  const LayStrided lay{col, 0, C};
-  cx<T> v[1][E];
-  constexpr int RIN = INV ? SC::RL : SC::RF;
-  constexpr int ROUT = INV ? SC::RF : SC::RL;
-#pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) * N + x);
-  if constexpr (INV)
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
-  else
-    fft_forward<SC, 1>(v, lds, lay, tw, t);
-#pragma unroll
-  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) * N + x, v[0][q]);
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  ypass_body<T, SC, C, INV>(psi + blockIdx.z * npts, tw, lds, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- x-pass
-enum { XP_PHASE = 0, XP_FWD = 1, XP_INV = 2 };
-
 template <typename T, class SC, int ROWS, int MODE>
 __global__ void __launch_bounds__(ROWS * SC::TPC)
     k3d_xpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
               const cx<T>* __restrict__ kin, int conj) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
-  const int lane = threadIdx.x;
-  const int t = lane % TPC, row = lane / TPC;
-  const int y = blockIdx.x * ROWS + row, z = blockIdx.y, s = blockIdx.z;
-  constexpr int64_t plane = (int64_t)N * N, npts = plane * N;
-  const auto base = rsrc(psi + s * npts + z * plane, (uint32_t)plane);
-  const uint32_t yo = (uint32_t)y * N;
-  const LayPadded lay{row * (N + N / 16), 0};
-  cx<T> v[1][E];
-  constexpr int RIN = MODE == XP_INV ? SC::RL : SC::RF;
-#pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) + yo);
-  if constexpr (MODE == XP_INV) {
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
-  } else {
-    fft_forward<SC, 1>(v, lds, lay, tw, t);
-  }
-  if constexpr (MODE == XP_PHASE) {
-    const T csign = conj ? (T)-1 : (T)1;
-    cx<T> fzy = cmul(kin[z], kin[N + y]);
-    fzy.im *= csign;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(t, q)];
-      fx.im *= csign;
-      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
-    }
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
-  }
-  constexpr int ROUT = MODE == XP_FWD ? SC::RL : SC::RF;
-#pragma unroll
-  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) + yo, v[0][q]);
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  xpass_body<T, SC, ROWS, MODE>(psi + blockIdx.z * npts, tw, kin, conj, lds, blockIdx.x,
+                                blockIdx.y);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -464,13 +327,7 @@ struct Passes {
   using XS = typename XYSched<SC>::type;
   static constexpr int C = cols<XS, T>();
   static constexpr int CZ = zcols<SC, T>();
-  // rows per x-pass block: about 128 threads, and a divisor of N
-  static constexpr int rows() {
-    int r = XS::TPC >= 16 ? 8 : 128 / XS::TPC;
-    while (N % r != 0) r /= 2;
-    return r;
-  }
-  static constexpr int ROWS = rows();
+  static constexpr int ROWS = xrows<XS>();
   static_assert(N % C == 0 && N % CZ == 0 && N % ROWS == 0, "tiles must cover the grid");
 
   // algorithmic bytes of one pass: psi read + written, plus tables read

@@ -1,0 +1,261 @@
+// kernels_batch3d.hip -- three-dimensional members of a batch: lockstep
+// passes over every member of one (n, surfaces, precision) group.
+//
+// Each member runs the pruned VTV step program V(a_1) T(b_1) ... T(b_M)
+// V(a_{M+1}) of its own plan (own order, dt, tables and step count).  Its
+// pass sequence is periodic: cycle c (c < cycles = M nsteps) is the z-pass
+// that applies the potential action(s) before kinetic action number c, then
+// the y forward, x (phase) and y inverse passes of that kinetic action; the
+// z-pass of cycle c = cycles applies the closing V(a_{M+1}) and returns z to
+// position space.  At a step boundary the z-pass applies V(a_{M+1}) of the
+// finished step and V(a_1) of the next one (Sec. "Pruning splitting
+// coefficients": the same actions the single-plan executor launches).
+// Launch c of a kind covers every member; a member derives its own pass
+// parameters from c and its program on the device, and members whose run is
+// shorter than c leave at once.  The pass bodies are those of the
+// single-plan kernels, so a member's result equals its single-plan run.
+#include "passes_3d.hpp"
+
+namespace sop {
+namespace {
+
+using namespace s3d;
+
+constexpr int prog_index(int code) { return code & 0xffff; }
+
+// z-pass of cycle c; PI = the state arrives z-transformed (every c > 0).
+template <typename T, class SC, int S, int C, bool PI>
+__global__ void __launch_bounds__(C * SC::TPC)
+    k3b_zpass(const BMember3* __restrict__ mem, int64_t c) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const BMember3 m = mem[blockIdx.z];
+  if (m.cycles <= 0 || c > m.cycles) return;
+  const int M = m.M;
+  int nv = 1, iv0, iv1 = 0;
+  bool pf = true;
+  if (c == m.cycles) {  // closing potential action
+    iv0 = prog_index(m.prog[2 * M]);
+    pf = false;
+  } else {
+    const int i = (int)(c % M);
+    if (c > 0 && i == 0) {  // step boundary: V(a_{M+1}) then V(a_1)
+      nv = 2;
+      iv0 = prog_index(m.prog[2 * M]);
+      iv1 = prog_index(m.prog[0]);
+    } else {
+      iv0 = prog_index(m.prog[2 * i]);
+    }
+  }
+  cx<T>* psi = (cx<T>*)m.psi;
+  const cx<T>* vexp = (const cx<T>*)m.vexp;
+  const cx<T>* tw = (const cx<T>*)m.tw;
+  if constexpr (PI) {
+    if (pf)
+      zpass_body<T, SC, S, C, kTableCols, true, true>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
+                                                      blockIdx.x, blockIdx.y);
+    else
+      zpass_body<T, SC, S, C, kTableCols, true, false>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
+                                                       blockIdx.x, blockIdx.y);
+  } else {
+    zpass_body<T, SC, S, C, kTableCols, false, true>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
+                                                     blockIdx.x, blockIdx.y);
+  }
+}
+
+// y-pass of cycle c: grid (N / C, N, S x members).
+template <typename T, class SC, int C, bool INV>
+__global__ void __launch_bounds__(C * SC::TPC)
+    k3b_ypass(const BMember3* __restrict__ mem, int S, int64_t c) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = blockIdx.z / S, s = blockIdx.z % S;
+  const BMember3 m = mem[mi];
+  if (c >= m.cycles) return;
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  ypass_body<T, SC, C, INV>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + SC::N, lds,
+                            blockIdx.x, blockIdx.y);
+}
+
+// x-pass (forward, kinetic phase of action c mod M, inverse) of cycle c.
+template <typename T, class SC, int ROWS>
+__global__ void __launch_bounds__(ROWS * SC::TPC)
+    k3b_xpass(const BMember3* __restrict__ mem, int S, int64_t c) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = blockIdx.z / S, s = blockIdx.z % S;
+  const BMember3 m = mem[mi];
+  if (c >= m.cycles) return;
+  const int tidx = prog_index(m.prog[2 * (int)(c % m.M) + 1]);
+  const cx<T>* kin = (const cx<T>*)m.kin + (size_t)tidx * 3 * m.kin_stride;
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  xpass_body<T, SC, ROWS, XP_PHASE>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + 2 * SC::N,
+                                    kin, m.conj, lds, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- variants
+// z: pass tile of 16 or 8 columns (the table tile is 16 wide).
+constexpr int zwidth(int v) { return v == 0 ? kTableCols : kTableCols / 2; }
+// y: default columns, twice, half; x: default rows, twice, half.
+constexpr int scaled(int base, int v) { return v == 0 ? base : (v == 1 ? 2 * base : base / 2); }
+
+template <class SC, typename T>
+constexpr int ywidth(int v) {
+  return scaled(cols<SC, T>(), v);
+}
+template <class SC>
+constexpr int xwidth(int v) {
+  return scaled(xrows<SC>(), v);
+}
+template <class SC>
+constexpr bool valid_width(int w) {
+  return w >= 1 && SC::N % w == 0 && w * SC::TPC <= 1024 && w * SC::TPC >= 32;
+}
+
+template <typename K>
+hipError_t set_lds(K k, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <typename T, class SC, int S, int V>
+hipError_t launch_z(const BMember3* mem, int count, int64_t c, hipStream_t st) {
+  constexpr int C = zwidth(V);
+  const size_t lds = (size_t)C * SC::N * sizeof(cx<T>);
+  const dim3 grid(SC::N / C, SC::N, count), block(C * SC::TPC);
+  if (c == 0) {
+    auto k = k3b_zpass<T, SC, S, C, false>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, block, lds, st, mem, c);
+  } else {
+    auto k = k3b_zpass<T, SC, S, C, true>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, block, lds, st, mem, c);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, class SC, int V>
+hipError_t launch_y(bool inv, int S, const BMember3* mem, int count, int64_t c, hipStream_t st) {
+  constexpr int C = ywidth<SC, T>(V);
+  if constexpr (!valid_width<SC>(C)) {
+    return hipErrorInvalidValue;
+  } else {
+    const size_t lds = (size_t)C * SC::N * sizeof(cx<T>);
+    const dim3 grid(SC::N / C, SC::N, S * count), block(C * SC::TPC);
+    if (inv) {
+      auto k = k3b_ypass<T, SC, C, true>;
+      hipError_t e = set_lds(k, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, grid, block, lds, st, mem, S, c);
+    } else {
+      auto k = k3b_ypass<T, SC, C, false>;
+      hipError_t e = set_lds(k, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, grid, block, lds, st, mem, S, c);
+    }
+    return hipGetLastError();
+  }
+}
+
+template <typename T, class SC, int V>
+hipError_t launch_x(int S, const BMember3* mem, int count, int64_t c, hipStream_t st) {
+  constexpr int R = xwidth<SC>(V);
+  if constexpr (!valid_width<SC>(R)) {
+    return hipErrorInvalidValue;
+  } else {
+    auto k = k3b_xpass<T, SC, R>;
+    const size_t lds = (size_t)R * (SC::N + SC::N / 16) * sizeof(cx<T>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(SC::N / R, SC::N, S * count), dim3(R * SC::TPC), lds, st, mem, S,
+                       c);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, class SC>
+hipError_t launch_kind(int kind, int S, int v, const BMember3* mem, int count, int64_t c,
+                       hipStream_t st) {
+  switch (kind) {
+    case B3_Z: {
+      auto z = [&]<int V>() -> hipError_t {
+        if (S == 1) return launch_z<T, SC, 1, V>(mem, count, c, st);
+        if (S == 2) return launch_z<T, SC, 2, V>(mem, count, c, st);
+        if (S == 3) return launch_z<T, SC, 3, V>(mem, count, c, st);
+        return hipErrorInvalidValue;
+      };
+      if (v == 0) return z.template operator()<0>();
+      if (v == 1) return z.template operator()<1>();
+      return hipErrorInvalidValue;
+    }
+    case B3_YF:
+    case B3_YI: {
+      const bool inv = kind == B3_YI;
+      if (v == 0) return launch_y<T, SC, 0>(inv, S, mem, count, c, st);
+      if (v == 1) return launch_y<T, SC, 1>(inv, S, mem, count, c, st);
+      if (v == 2) return launch_y<T, SC, 2>(inv, S, mem, count, c, st);
+      return hipErrorInvalidValue;
+    }
+    case B3_XP:
+      if (v == 0) return launch_x<T, SC, 0>(S, mem, count, c, st);
+      if (v == 1) return launch_x<T, SC, 1>(S, mem, count, c, st);
+      if (v == 2) return launch_x<T, SC, 2>(S, mem, count, c, st);
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <class F>
+hipError_t by_grid(int n, bool f64, F&& f) {
+  switch (n) {
+    case 32: return f64 ? f.template operator()<double, Z32>() : f.template operator()<float, Z32>();
+    case 48: return f64 ? f.template operator()<double, Z48>() : f.template operator()<float, Z48>();
+    case 64: return f64 ? f.template operator()<double, Z64>() : f.template operator()<float, Z64>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// widths of the variants (0 if the variant does not exist)
+template <typename T, class SC>
+int width_of(int kind, int v) {
+  if (kind == B3_Z) return (v == 0 || v == 1) ? zwidth(v) : 0;
+  if (v < 0 || v > 2) return 0;
+  const int w = (kind == B3_XP) ? scaled(xrows<SC>(), v) : scaled(cols<SC, T>(), v);
+  const bool ok = w >= 1 && SC::N % w == 0 && w * SC::TPC <= 1024 && w * SC::TPC >= 32;
+  return ok ? w : 0;
+}
+
+}  // namespace
+
+bool k3b_supported(int n, int S) { return (n == 32 || n == 48 || n == 64) && S >= 1 && S <= 3; }
+
+int k3b_variant_width(int kind, int n, bool f64, int variant) {
+  int w = 0;
+  (void)by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
+    w = width_of<T, SC>(kind, variant);
+    return hipSuccess;
+  });
+  return w;
+}
+
+int k3b_variants(int kind, int n, bool f64) {
+  (void)n;
+  (void)f64;
+  return kind == B3_Z ? 2 : 3;
+}
+
+hipError_t k3b_launch(int kind, int n, int S, bool f64, int variant, const BMember3* mem,
+                      int count, int64_t cycle, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (k3b_variant_width(kind, n, f64, variant) == 0) return hipErrorInvalidValue;
+  return by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
+    return launch_kind<T, SC>(kind, S, variant, mem, count, cycle, stream);
+  });
+}
+
+}  // namespace sop

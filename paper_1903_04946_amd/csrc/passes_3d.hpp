@@ -1,0 +1,211 @@
+// passes_3d.hpp -- pencil schedules and the bodies of the three pass kinds of
+// the 3D executor, as device functions of one workgroup tile.  The kernels
+// of a single plan (kernels_3d.hip) and of a batch of plans
+// (kernels_batch3d.hip) wrap the same bodies, so both compute identical values.
+//
+// A substep (one potential action followed by one kinetic action, Sec.
+// "Dynamic Fourier method") is four passes over psi[s][z][y][x]:
+//   z-pass : [inverse FFT along z] -> potential unitary(ies) -> [forward FFT z]
+//   y-pass : forward (or inverse) FFT along y;
+//   x-pass : forward FFT along x -> kinetic phase -> inverse FFT along x.
+#pragma once
+
+#include "fft_core.hpp"
+#include "internal.hpp"
+
+namespace sop {
+namespace s3d {
+
+using Z32 = Sched<32, 8, RList<8, 4>, RList<4, 8>, 8, 4>;
+using Z48 = Sched<48, 12, RList<4, 4, 3>, RList<3, 4, 4>, 4, 3>;
+using Z64 = Sched<64, 8, RList<8, 8>, RList<8, 8>, 8, 8>;
+using Z128 = Sched<128, 8, RList<8, 4, 4>, RList<4, 4, 8>, 8, 4>;
+using Z256 = Sched<256, 8, RList<8, 8, 4>, RList<4, 8, 8>, 8, 4>;
+
+// Schedules of the single-pencil y and x passes: sixteen values per thread
+// where that saves an LDS exchange.
+template <class SC>
+struct XYSched {
+  using type = SC;
+};
+template <>
+struct XYSched<Z128> {
+  using type = Sched<128, 16, RList<16, 8>, RList<8, 16>, 16, 8>;
+};
+template <>
+struct XYSched<Z256> {
+  using type = Sched<256, 16, RList<16, 16>, RList<16, 16>, 16, 16>;
+};
+
+// Columns per tile of the y-pass: at least a full wave per block and
+// 128-byte contiguous row segments.
+template <class SC, typename T>
+constexpr int cols() {
+  constexpr int seg = 128 / (int)sizeof(cx<T>);
+  return SC::TPC * seg >= 64 ? seg : 64 / SC::TPC;
+}
+
+// Rows per x-pass block: about 128 threads, and a divisor of N.
+template <class XS>
+constexpr int xrows() {
+  int r = XS::TPC >= 16 ? 8 : 128 / XS::TPC;
+  while (XS::N % r != 0) r /= 2;
+  return r;
+}
+
+// Column width of the potential-table tiles (and of the default z-pass tile):
+// 16 in both precisions, 256-byte FP64 and 128-byte FP32 segments of psi.
+constexpr int kTableCols = 16;
+
+}  // namespace s3d
+
+// ---------------------------------------------------------------- z-pass
+// Potential tables are stored per tile of TC x-columns: for table u, tile
+// (y, x / TC) holds [z][entry][x % TC] contiguously, N * NE * TC complex, so
+// a tile reads its table as one contiguous stream.  The pass tile is C
+// columns wide (C divides TC); block (bx, by) owns columns bx*C .. bx*C+C-1
+// of row y = by.  `psi` is one state [S][N^3].
+template <typename T, class SC, int S, int C, int TC, bool PRE_INV, bool POST_FWD>
+__device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
+                                           const cx<T>* __restrict__ vexp, int nv, int iv0,
+                                           int iv1, int conj, const cx<T>* __restrict__ tw,
+                                           cx<T>* lds, int bx, int by) {
+  static_assert(TC % C == 0, "pass tile must divide the table tile");
+  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
+  const int lane = threadIdx.x;
+  const int col = lane % C, t = lane / C;
+  const int x = bx * C + col, y = by;
+  constexpr uint32_t plane = (uint32_t)N * N;
+  constexpr int64_t npts = (int64_t)plane * N;
+  constexpr uint32_t tile = (uint32_t)N * NE * TC;
+  const uint32_t off0 = (uint32_t)y * N + x;
+  const int tx = (C == TC) ? bx : (bx * C) / TC;            // table tile
+  const int tcol = (C == TC) ? col : (bx * C) % TC + col;   // column within it
+  const size_t tbase = ((size_t)y * (N / TC) + tx) * tile;
+  const LayStrided lay{col, 0, C};  // one surface at a time through LDS
+  cx<T> v[S][E];
+  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
+  }
+  if constexpr (PRE_INV) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
+    // normalisation of the z round trip (exact for power-of-two N)
+    constexpr T inv_n = (T)1 / (T)N;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[s][q] = cx<T>{v[s][q].re * inv_n, v[s][q].im * inv_n};
+  }
+  const T csign = conj ? (T)-1 : (T)1;
+  auto vact = [&](int iv) {
+    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
+      cx<T> u[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        u[e] = ld<T>(ru, pt + e * TC);
+        u[e].im *= csign;
+      }
+      cx<T> w[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) w[s] = v[s][q];
+      apply_u<T, S>(w, u);
+#pragma unroll
+      for (int s = 0; s < S; ++s) v[s][q] = w[s];
+    }
+  };
+  if (nv >= 1) vact(iv0);
+  if (nv >= 2) vact(iv1);
+  if constexpr (POST_FWD) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
+  }
+  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
+#pragma unroll
+    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
+  }
+}
+
+// ---------------------------------------------------------------- y-pass
+// One surface `psi_s` [N^3]; block (bx, z) owns columns bx*C .. bx*C+C-1 of
+// plane z.
+template <typename T, class SC, int C, bool INV>
+__device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
+                                           const cx<T>* __restrict__ tw, cx<T>* lds, int bx,
+                                           int z) {
+  constexpr int N = SC::N, E = SC::E;
+  const int lane = threadIdx.x;
+  const int col = lane % C, t = lane / C;
+  const int x = bx * C + col;
+  constexpr int64_t plane = (int64_t)N * N;
+  const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
+  const LayStrided lay{col, 0, C};
+  cx<T> v[1][E];
+  constexpr int RIN = INV ? SC::RL : SC::RF;
+  constexpr int ROUT = INV ? SC::RF : SC::RL;
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) * N + x);
+  if constexpr (INV)
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  else
+    fft_forward<SC, 1>(v, lds, lay, tw, t);
+#pragma unroll
+  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) * N + x, v[0][q]);
+}
+
+// ---------------------------------------------------------------- x-pass
+enum { XP_PHASE = 0, XP_FWD = 1, XP_INV = 2 };
+
+// One surface `psi_s`; block (bx, z) owns rows bx*ROWS .. bx*ROWS+ROWS-1 of
+// plane z.  `kin` = the three per-axis factors [f_z | f_y | f_x] of one
+// kinetic coefficient (XP_PHASE only).
+template <typename T, class SC, int ROWS, int MODE>
+__device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
+                                           const cx<T>* __restrict__ tw,
+                                           const cx<T>* __restrict__ kin, int conj, cx<T>* lds,
+                                           int bx, int z) {
+  constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
+  const int lane = threadIdx.x;
+  const int t = lane % TPC, row = lane / TPC;
+  const int y = bx * ROWS + row;
+  constexpr int64_t plane = (int64_t)N * N;
+  const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
+  const uint32_t yo = (uint32_t)y * N;
+  const LayPadded lay{row * (N + N / 16), 0};
+  cx<T> v[1][E];
+  constexpr int RIN = MODE == XP_INV ? SC::RL : SC::RF;
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) + yo);
+  if constexpr (MODE == XP_INV) {
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  } else {
+    fft_forward<SC, 1>(v, lds, lay, tw, t);
+  }
+  if constexpr (MODE == XP_PHASE) {
+    const T csign = conj ? (T)-1 : (T)1;
+    cx<T> fzy = cmul(kin[z], kin[N + y]);
+    fzy.im *= csign;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(t, q)];
+      fx.im *= csign;
+      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
+    }
+    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+  }
+  constexpr int ROUT = MODE == XP_FWD ? SC::RL : SC::RF;
+#pragma unroll
+  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) + yo, v[0][q]);
+}
+
+}  // namespace sop

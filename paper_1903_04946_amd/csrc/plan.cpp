@@ -202,6 +202,11 @@ struct sop_plan {
   bool use_graphs = true;
 };
 
+namespace sop {
+const DevView* plan_view(const sop_plan* p) { return &p->dv; }
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace sop
+
 namespace {
 
 void free_plan(sop_plan* p) {

@@ -52,7 +52,9 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
-           "sop_propagate_many", "sop_plan_set_option"]
+           "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
+           "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
+           "sop_batch_describe"]
 KINDS = ["zpass", "ypass", "xpass", "k1d", "other"]
 
 _lib = None
@@ -91,11 +93,20 @@ def lib():
     L.sop_adjoint_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, dp]
     L.sop_adjoint_backward.argtypes = [vp, ctypes.c_int64, ctypes.c_int, dp, vp, dp]
     L.sop_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
+    L.sop_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.sop_batch_destroy.argtypes = [vp]
+    L.sop_batch_propagate.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int]
+    L.sop_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.sop_batch_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_size_t)]
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
               "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
               "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
-              "sop_propagate_many", "sop_plan_set_option"):
+              "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
+              "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
+              "sop_batch_describe"):
         getattr(L, f).restype = ctypes.c_int
     L.sop_supported_length.restype = ctypes.c_int
     _lib = L
@@ -339,6 +350,60 @@ class Plan:
         _check(lib().sop_overlap(self._h, ctypes.c_void_p(psi.data_ptr()),
                                  ctypes.c_void_p(phi.data_ptr()), _dp(out)), "sop_overlap")
         return complex(out[0], out[1])
+
+
+class Batch:
+    """Many independent plans propagated by one graph launch (sop_batch_create).
+
+    plans: Plan objects (kept alive by the batch); stream: the torch stream
+    the propagate calls run on (default: the current stream).
+    """
+
+    def __init__(self, plans, stream=None):
+        L = lib()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(L.sop_batch_create(arr, len(self.plans), _stream_handle(stream), ctypes.byref(h)),
+               "sop_batch_create")
+        self._h = h
+
+    def propagate(self, psis, nsteps, direction: int = 1):
+        """psis[i] <- U_i(direction dt_i)^nsteps[i] psis[i] in place (asynchronous)."""
+        if len(psis) != len(self.plans):
+            raise ValueError("one state per member")
+        ns = np.ascontiguousarray(np.broadcast_to(np.asarray(nsteps, dtype=np.int64),
+                                                  (len(self.plans),)))
+        for p, x in zip(self.plans, psis):
+            p._check_psi(x)
+        ptrs = (ctypes.c_void_p * len(psis))(*[x.data_ptr() for x in psis])
+        _check(lib().sop_batch_propagate(self._h, ptrs,
+                                         ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         int(direction)), "sop_batch_propagate")
+        return psis
+
+    def set_graphs(self, enable: bool):
+        _check(lib().sop_batch_set_option(self._h, 1, int(bool(enable))), "sop_batch_set_option")
+
+    def describe(self) -> dict:
+        import json
+        need = ctypes.c_size_t()
+        _check(lib().sop_batch_describe(self._h, None, 0, ctypes.byref(need)),
+               "sop_batch_describe")
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().sop_batch_describe(self._h, buf, need.value, None), "sop_batch_describe")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sop_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _populations_fn():

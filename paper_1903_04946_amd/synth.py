@@ -201,13 +201,14 @@ def random_state(shape, seed, dV=1.0) -> np.ndarray:
 
 
 # ----------------------------------------------------------------- batches
-def batch_manifest(count: int = 256, seed: int = 4946):
+def batch_manifest(count: int = 256, seed: int = 4946, t_final: float = 0.5):
     """Members of a batched ensemble: grid type, x0, p0, dt, order, scheme.
 
     Grid type uniform over {512, 1024, 2048, 4096, 8192 (1D, two surfaces),
     32^3, 48^3 (3D, three surfaces)}; x0 ~ U[-3, 3], p0 ~ U[-2, 2] (per mode
-    in 3D); dt ~ U[0.005, 0.05] snapped so that nsteps * dt = 10; order in
-    {2, 4, 6, 8}; triple jump or Suzuki fractal for order >= 4.
+    in 3D); dt ~ U[0.005, 0.05], snapped so that every member reaches the
+    same final time (nsteps * dt = t_final, so the step counts are uneven);
+    order in {2, 4, 6, 8}; triple jump or Suzuki fractal for order >= 4.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     grids = [("1d", 512), ("1d", 1024), ("1d", 2048), ("1d", 4096), ("1d", 8192),
@@ -219,10 +220,19 @@ def batch_manifest(count: int = 256, seed: int = 4946):
         x0 = rng.uniform(-3, 3, size=ndim)
         p0 = rng.uniform(-2, 2, size=ndim)
         dt = rng.uniform(0.005, 0.05)
-        nsteps = int(np.ceil(10.0 / dt))
-        dt = 10.0 / nsteps
+        nsteps = int(np.ceil(t_final / dt))
+        dt = t_final / nsteps
         order = int(rng.choice([2, 4, 6, 8]))
         scheme = "strang" if order == 2 else ("triple_jump" if rng.integers(0, 2) == 0 else "suzuki")
         out.append({"kind": kind, "n": n, "x0": x0.tolist(), "p0": p0.tolist(), "dt": dt,
                     "nsteps": nsteps, "order": order, "scheme": scheme})
     return out
+
+
+def ensemble_model(entry) -> Model:
+    """The model of one manifest entry: the 1D two-surface model with its
+    packet at (x0, p0), or the 32^3 / 48^3 three-surface LVC model with the
+    packet on surface 3 at (q0, p0)."""
+    if entry["kind"] == "1d":
+        return two_surface_1d(n=entry["n"], x0=entry["x0"][0], p0=entry["p0"][0])
+    return lvc_3d(n=entry["n"], q0=tuple(entry["x0"]), p0=tuple(entry["p0"]))

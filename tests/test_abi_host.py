@@ -136,3 +136,18 @@ def test_null_arguments(L):
     assert L.sop_propagate(None, None, 1, 1) == 1
     assert L.sop_observables(None, None, None) == 1
     assert L.sop_plan_destroy(None) == 0
+
+
+def test_batch_argument_checks(L):
+    """Batch calls reject bad arguments before touching a device."""
+    h = ctypes.c_void_p()
+    assert L.sop_batch_create(None, 1, None, ctypes.byref(h)) == 1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.sop_batch_create(arr, 0, None, ctypes.byref(h)) == 1
+    assert L.sop_batch_create(arr, 2, None, ctypes.byref(h)) == 1  # NULL plans
+    assert "NULL" in L.sop_last_error().decode()
+    assert h.value is None
+    assert L.sop_batch_propagate(None, None, None, 1) == 1
+    assert L.sop_batch_set_option(None, 1, 0) == 1
+    assert L.sop_batch_describe(None, None, 0, None) == 1
+    assert L.sop_batch_destroy(None) == 0
