@@ -411,7 +411,7 @@ def run_ensemble(a, torch, soprop):
                   "families": [{k: f[k] for k in ("n", "S", "variant", "schedule", "tuned_ms")}
                                | {"members": len(f["members"])} for f in desc["families"]],
                   "groups": [{k: g[k] for k in ("n", "S", "z_cols", "y_cols", "x_rows",
-                                                "tuned_ms", "max_cycles")}
+                                                "tuned_ms", "max_cycles", "chains")}
                              | {"members": len(g["members"])} for g in desc["groups"]]},
         "cpu_baseline": cpu,
         "checks": {"norm_max_dev": max(abs(x - 1) for x in norms), "wall_s_timed": wall},

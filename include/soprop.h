@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SOP_ABI_VERSION 1
+#define SOP_ABI_VERSION 2
 
 typedef enum {
   SOP_OK = 0,
@@ -230,8 +230,12 @@ sop_status sop_adjoint_backward(sop_plan* plan, int64_t nsteps, int K, const dou
 /* Plan options.  SOP_OPT_GRAPHS (default 1): on 3D grids, runs of 4 or more
  * steps launch the first step, the steady step (replayed) and the final
  * pass as HIP graphs captured once per state pointer, direction and count;
- * 0 launches every pass eagerly.  Both give bitwise identical results. */
-enum { SOP_OPT_GRAPHS = 1 };
+ * 0 launches every pass eagerly.  SOP_OPT_PLANE_PASS (default 1): on 3D
+ * grids whose xy plane fits in LDS (n <= 64 in FP64, n <= 128 in FP32) the
+ * y-forward, x (phase) and y-inverse passes of a kinetic action run as one
+ * plane pass; 0 keeps three passes.  Every setting gives bitwise identical
+ * results. */
+enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2 };
 sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
 /* Per-kernel timing (measurement aid).  While enabled, every kernel launch
@@ -241,7 +245,7 @@ sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
  * algorithmic bytes (state read + written, tables read), then clears the
  * records.  ms, counts, bytes: host arrays of SOP_KIND_COUNT entries. */
 enum { SOP_KIND_ZPASS = 0, SOP_KIND_YPASS = 1, SOP_KIND_XPASS = 2, SOP_KIND_1D = 3,
-       SOP_KIND_OTHER = 4, SOP_KIND_COUNT = 5 };
+       SOP_KIND_OTHER = 4, SOP_KIND_PLANE = 5, SOP_KIND_COUNT = 6 };
 sop_status sop_plan_set_timing(sop_plan* plan, int enable);
 sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* bytes);
 
@@ -277,8 +281,9 @@ sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* 
  * them synchronises the stream once to rewrite the member descriptors.
  * Runs longer than 200000 kernel launches are enqueued without a graph.
  *
- * sop_batch_set_option(SOP_OPT_GRAPHS, 0) enqueues the branches directly
- * (same kernels, same results).
+ * sop_batch_set_option(SOP_OPT_GRAPHS, 0) enqueues the branches directly;
+ * SOP_OPT_PLANE_PASS 0 keeps three y/x/y passes in the lockstep groups (same
+ * results either way).
  *
  * sop_batch_describe writes a NUL-terminated JSON description (families,
  * groups, chosen variants, tuning times in ms, branch count, whether the

@@ -5,8 +5,12 @@
 //     one workgroup per member for its whole run, members in decreasing
 //     order of work;
 //   * 3D lockstep groups (n in {32, 48, 64}, surfaces, precision, VTV
-//     program): four pass launches per cycle over every member of the group
-//     (kernels_batch3d.hip);
+//     program): four pass launches per cycle (kernels_batch3d.hip).  The
+//     members are sorted by decreasing cycle count and cut into chains whose
+//     counts lie within a factor of 4 of the chain's longest; each chain is
+//     its own branch, so a few long runs proceed beside the bulk instead of
+//     after it, and launch c of a chain covers only the members still
+//     running at cycle c;
 //   * any other member runs its own plan's executor.
 // Every family, group and single member is one branch of a fork/join HIP
 // graph (branches on separate capture streams), so one propagate call is
@@ -44,7 +48,7 @@ namespace {
 // Largest graph (kernel nodes) a propagate call captures; longer runs are
 // launched eagerly on the same branch streams.
 constexpr int64_t kGraphNodeCap = 200000;
-constexpr int kMaxBranches = 8;
+constexpr int kMaxBranches = 12;
 
 sop_status fail(sop_status s, const std::string& msg) {
   sop::set_last_error(msg);
@@ -78,6 +82,10 @@ struct Group3 {
   bool from_cache = false;
   BMember3* d_mem = nullptr;
   int64_t max_cycles = 0;
+  // members sorted by decreasing cycle count; chains = contiguous ranges of
+  // similar counts, each launched on its own branch
+  std::vector<int64_t> cycles;
+  std::vector<std::pair<int, int>> chains;
 };
 
 // Steps of the pruned VTV program V T V ... T V: M = number of T actions, or
@@ -169,6 +177,7 @@ struct sop_batch {
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> joins;
   bool use_graphs = true;
+  bool use_plane = true;
   hipGraphExec_t exec = nullptr;
   int64_t graph_nodes = 0;
   bool last_graph = false;
@@ -318,22 +327,35 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
     if (e != hipSuccess) return e;
   }
   for (Group3& g : b->groups) {
-    if (g.max_cycles <= 0) continue;
-    hipStream_t st = next();
-    const int cnt = (int)g.members.size();
-    for (int64_t c = 0; c <= g.max_cycles; ++c) {
-      hipError_t e = sop::k3b_launch(sop::B3_Z, g.n, g.S, g.f64, g.vz, g.d_mem, cnt, c, st);
-      if (e != hipSuccess) return e;
-      if (c == g.max_cycles) break;
-      if ((e = sop::k3b_launch(sop::B3_YF, g.n, g.S, g.f64, g.vy, g.d_mem, cnt, c, st)) !=
-          hipSuccess)
-        return e;
-      if ((e = sop::k3b_launch(sop::B3_XP, g.n, g.S, g.f64, g.vx, g.d_mem, cnt, c, st)) !=
-          hipSuccess)
-        return e;
-      if ((e = sop::k3b_launch(sop::B3_YI, g.n, g.S, g.f64, g.vy, g.d_mem, cnt, c, st)) !=
-          hipSuccess)
-        return e;
+    for (const auto& ch : g.chains) {
+      hipStream_t st = next();
+      const int lo = ch.first, hi = ch.second;
+      const int64_t maxc = g.cycles[lo];
+      BMember3* mem = g.d_mem + lo;
+      const bool plane = b->use_plane && sop::k3b_plane(g.n, g.f64);
+      int nz = hi - lo, nyx = hi - lo;  // members with cycles >= c, > c
+      for (int64_t c = 0; c <= maxc; ++c) {
+        while (nz > 0 && g.cycles[lo + nz - 1] < c) --nz;
+        while (nyx > 0 && g.cycles[lo + nyx - 1] <= c) --nyx;
+        hipError_t e = sop::k3b_launch(sop::B3_Z, g.n, g.S, g.f64, g.vz, mem, nz, c, st);
+        if (e != hipSuccess) return e;
+        if (c == maxc) break;
+        if (plane) {
+          if ((e = sop::k3b_launch(sop::B3_XY, g.n, g.S, g.f64, 0, mem, nyx, c, st)) !=
+              hipSuccess)
+            return e;
+          continue;
+        }
+        if ((e = sop::k3b_launch(sop::B3_YF, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
+            hipSuccess)
+          return e;
+        if ((e = sop::k3b_launch(sop::B3_XP, g.n, g.S, g.f64, g.vx, mem, nyx, c, st)) !=
+            hipSuccess)
+          return e;
+        if ((e = sop::k3b_launch(sop::B3_YI, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
+            hipSuccess)
+          return e;
+      }
     }
   }
   for (int m : b->solo) {
@@ -367,7 +389,10 @@ hipError_t fork_join(sop_batch* b, hipStream_t origin, const std::vector<int64_t
 
 int64_t count_nodes(const sop_batch* b, const std::vector<int64_t>& nsteps) {
   int64_t n = (int64_t)b->fams.size();
-  for (const Group3& g : b->groups) n += 4 * g.max_cycles + 1;
+  for (const Group3& g : b->groups) {
+    const int per = (b->use_plane && sop::k3b_plane(g.n, g.f64)) ? 2 : 4;
+    for (const auto& ch : g.chains) n += per * g.cycles[ch.first] + 1;
+  }
   for (int m : b->solo) {
     const DevView& d = *b->views[m];
     n += d.ndim == 1 ? 1 : 4 * (int64_t)d.nact * nsteps[m] + 1;
@@ -445,7 +470,8 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
 
   // streams and events
   const int nbranch = std::max<int>(
-      1, std::min<int>(kMaxBranches, (int)(b->fams.size() + b->groups.size() + b->solo.size())));
+      1, std::min<int>(kMaxBranches,
+                       (int)(b->fams.size() + 6 * b->groups.size() + b->solo.size())));
   HIPTRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
   for (int i = 0; i < nbranch; ++i) {
     hipStream_t s;
@@ -566,10 +592,16 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
       HIPTRY(hipMemcpy(f.d_mem, h.data(), sizeof(BMember1) * h.size(), hipMemcpyHostToDevice));
     }
     for (Group3& g : b->groups) {
-      std::vector<BMember3> h(g.members.size());
+      std::vector<int> order = g.members;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (int64_t)vtv_m(*b->views[x]) * ns[x] > (int64_t)vtv_m(*b->views[y]) * ns[y];
+      });
+      std::vector<BMember3> h(order.size());
       g.max_cycles = 0;
-      for (size_t i = 0; i < g.members.size(); ++i) {
-        const int mi = g.members[i];
+      g.cycles.assign(order.size(), 0);
+      g.chains.clear();
+      for (size_t i = 0; i < order.size(); ++i) {
+        const int mi = order[i];
         const DevView& d = *b->views[mi];
         BMember3& m = h[i];
         std::memset(&m, 0, sizeof(m));
@@ -583,6 +615,11 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
         m.conj = conj;
         m.kin_stride = d.kin_stride;
         g.max_cycles = std::max(g.max_cycles, m.cycles);
+        g.cycles[i] = m.cycles;
+        if (m.cycles > 0 && (g.chains.empty() || 4 * m.cycles < g.cycles[g.chains.back().first]))
+          g.chains.push_back({(int)i, (int)i + 1});
+        else if (m.cycles > 0)
+          g.chains.back().second = (int)i + 1;
       }
       HIPTRY(hipMemcpy(g.d_mem, h.data(), sizeof(BMember3) * h.size(), hipMemcpyHostToDevice));
     }
@@ -622,9 +659,13 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
 
 sop_status sop_batch_set_option(sop_batch* b, int option, int value) {
   if (!b) return fail(SOP_ERR_INVALID, "batch is NULL");
-  if (option != SOP_OPT_GRAPHS) return fail(SOP_ERR_INVALID, "unknown option");
+  if (option != SOP_OPT_GRAPHS && option != SOP_OPT_PLANE_PASS)
+    return fail(SOP_ERR_INVALID, "unknown option");
   HIPTRY(hipStreamSynchronize(b->stream));
-  b->use_graphs = value != 0;
+  if (option == SOP_OPT_GRAPHS)
+    b->use_graphs = value != 0;
+  else
+    b->use_plane = value != 0;
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -672,13 +713,18 @@ sop_status sop_batch_describe(const sop_batch* b, char* buf, size_t len, size_t*
     o << ", \"z_cols\": " << sop::k3b_variant_width(sop::B3_Z, g.n, g.f64, g.vz)
       << ", \"y_cols\": " << sop::k3b_variant_width(sop::B3_YF, g.n, g.f64, g.vy)
       << ", \"x_rows\": " << sop::k3b_variant_width(sop::B3_XP, g.n, g.f64, g.vx)
+      << ", \"plane\": " << ((b->use_plane && sop::k3b_plane(g.n, g.f64)) ? "true" : "false")
       << ", \"from_cache\": " << (g.from_cache ? "true" : "false") << ", \"tuned_ms\": {\"z\": ";
     arr(g.ms_z);
     o << ", \"y\": ";
     arr(g.ms_y);
     o << ", \"x\": ";
     arr(g.ms_x);
-    o << "}, \"max_cycles\": " << g.max_cycles << "}";
+    o << "}, \"max_cycles\": " << g.max_cycles << ", \"chains\": [";
+    for (size_t c = 0; c < g.chains.size(); ++c)
+      o << (c ? ", " : "") << "[" << g.chains[c].second - g.chains[c].first << ", "
+        << g.cycles[g.chains[c].first] << "]";
+    o << "]}";
   }
   o << "], \"solo\": ";
   members(b->solo);

@@ -21,7 +21,8 @@ inline int prog_op(int e) { return e >> 16; }
 inline int prog_idx(int e) { return e & 0xffff; }
 
 // Kernel kinds reported by the timing hook.
-enum { KIND_ZPASS = 0, KIND_YPASS = 1, KIND_XPASS = 2, KIND_1D = 3, KIND_OTHER = 4, KIND_COUNT = 5 };
+enum { KIND_ZPASS = 0, KIND_YPASS = 1, KIND_XPASS = 2, KIND_1D = 3, KIND_OTHER = 4, KIND_PLANE = 5,
+       KIND_COUNT = 6 };
 
 // Optional per-launch timing: HIP events recorded on the plan's stream
 // around every kernel launch, resolved after a synchronisation.
@@ -49,7 +50,7 @@ struct Timer {
 
 // One pass of the 3D executor.
 struct PassDesc {
-  enum Kind { Z = 0, YF = 1, YI = 2, XP = 3 };
+  enum Kind { Z = 0, YF = 1, YI = 2, XP = 3, XY = 4 };
   int kind = Z;
   bool pre_inv = false, post_fwd = false;
   int nv = 0, iv0 = 0, iv1 = 0;  // z-pass potential actions
@@ -103,6 +104,7 @@ struct DevView {
   Timer* timer = nullptr;      // non-null while timing is enabled
   GraphCache* graphs = nullptr;  // non-null when 3D steps may be graph-captured
   int count = 1;               // states of a batch processed by each 3D launch
+  bool plane = true;           // fused xy plane pass where the plane fits in LDS
 };
 
 // Brackets one launch with timing events when the plan's timer is on.
@@ -147,6 +149,7 @@ hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t 
 // ([tile (y, x/C)][z][entry][x % C]) with this C.
 int k3d_table_tile(int n, bool f64);
 hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
+bool k3d_plane(int n, bool f64);  // the xy plane of an n^3 grid fits in LDS
 hipError_t k3d_fft_forward(const DevView& d, void* psi);
 
 // kernels_aux.hip
@@ -210,10 +213,12 @@ const char* k1b_variant_name(int n, int variant);
 hipError_t k1b_launch(int n, int S, bool f64, int variant, const BMember1* mem, int count,
                       hipStream_t stream);
 
-// 3D lockstep groups.  kind: 0 z-pass, 1 y forward, 2 x (phase), 3 y inverse;
-// the y variants apply to both y kinds.
-enum { B3_Z = 0, B3_YF = 1, B3_XP = 2, B3_YI = 3 };
+// 3D lockstep groups.  kind: 0 z-pass, 1 y forward, 2 x (phase), 3 y inverse,
+// 4 fused xy plane (kinds 1-3 in one pass, where the plane fits in LDS); the y
+// variants apply to both y kinds.
+enum { B3_Z = 0, B3_YF = 1, B3_XP = 2, B3_YI = 3, B3_XY = 4 };
 bool k3b_supported(int n, int S);
+bool k3b_plane(int n, bool f64);
 int k3b_variants(int kind, int n, bool f64);
 int k3b_variant_width(int kind, int n, bool f64, int variant);  // columns or rows per tile
 hipError_t k3b_launch(int kind, int n, int S, bool f64, int variant, const BMember3* mem,

@@ -238,6 +238,18 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
                                 blockIdx.y);
 }
 
+// ---------------------------------------------------------------- xy plane
+// grid (N planes, surfaces x states)
+template <typename T, class SC>
+__global__ void __launch_bounds__(SC::N * SC::TPC)
+    k3d_plane(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
+              const cx<T>* __restrict__ kin, int conj) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  plane_body<T, SC>(psi + blockIdx.y * npts, tw, kin, conj, lds, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- launchers
 // Pass program of the 3D executor.  The machine walks the step program:
 // a potential action opens (or joins, up to two) a z-pass that inverts the
@@ -267,7 +279,7 @@ void flush_z(PassMachine& m, bool post_fwd, std::vector<PassDesc>& out) {
   m.zk = post_fwd;
 }
 
-void emit_step(const DevView& d, PassMachine& m, std::vector<PassDesc>& out) {
+void emit_step(const DevView& d, PassMachine& m, std::vector<PassDesc>& out, bool xy) {
   for (int a = 0; a < d.nact; ++a) {
     const int code = d.hprog[a];
     const int idx = prog_idx(code);
@@ -289,6 +301,13 @@ void emit_step(const DevView& d, PassMachine& m, std::vector<PassDesc>& out) {
         p.post_fwd = true;
         out.push_back(p);
         m.zk = true;
+      }
+      if (xy) {
+        PassDesc p;
+        p.kind = PassDesc::XY;
+        p.tidx = idx;
+        out.push_back(p);
+        continue;
       }
       PassDesc y, x, yi;
       y.kind = PassDesc::YF;
@@ -377,12 +396,30 @@ struct Passes {
     return hipGetLastError();
   }
 
+  static constexpr bool PLANE = plane_fits<T, XS>();
+  static hipError_t plane(const DevView& d, cx<T>* psi, int tidx, int conj) {
+    if constexpr (!PLANE) {
+      return hipErrorInvalidValue;
+    } else {
+      auto k = k3d_plane<T, XS>;
+      const size_t lds = plane_lds_elems<T, XS>() * sizeof(cx<T>);
+      hipError_t e = set_lds(k, lds);
+      if (e != hipSuccess) return e;
+      const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
+      TimedLaunch tl(d, KIND_PLANE, pass_bytes(d, 0));
+      hipLaunchKernelGGL(k, dim3(N, d.S * d.count), dim3(N * XS::TPC), lds, d.stream, psi,
+                         (const cx<T>*)d.tw[0], kin, conj);
+      return hipGetLastError();
+    }
+  }
+
   // Launches one pass descriptor.
   static hipError_t launch(const DevView& d, cx<T>* psi, const PassDesc& p, int conj) {
     switch (p.kind) {
       case PassDesc::Z: return zpass(d, psi, p.pre_inv, p.post_fwd, p.nv, p.iv0, p.iv1, conj);
       case PassDesc::YF: return ypass<false>(d, psi);
       case PassDesc::YI: return ypass<true>(d, psi);
+      case PassDesc::XY: return plane(d, psi, p.tidx, conj);
       default: return xpass<XP_PHASE>(d, psi, p.tidx, conj);
     }
   }
@@ -397,10 +434,11 @@ struct Passes {
 
   static hipError_t propagate(const DevView& d, void* vpsi, int64_t nsteps, int conj) {
     cx<T>* psi = (cx<T>*)vpsi;
+    const bool xy = PLANE && d.plane;
     PassMachine m0;
     std::vector<PassDesc> first, body, tail;
     PassMachine m1 = m0;
-    emit_step(d, m1, first);
+    emit_step(d, m1, first, xy);
     const bool use_graph = d.graphs != nullptr && d.timer == nullptr && nsteps >= 4;
     if (!use_graph) {
       hipError_t e = launch_all(d, psi, first, conj);
@@ -408,17 +446,17 @@ struct Passes {
       PassMachine m = m1;
       for (int64_t step = 1; step < nsteps; ++step) {
         body.clear();
-        emit_step(d, m, body);
+        emit_step(d, m, body, xy);
         if ((e = launch_all(d, psi, body, conj)) != hipSuccess) return e;
       }
       emit_flush(m, tail);
       return launch_all(d, psi, tail, conj);
     }
     PassMachine m2 = m1;
-    emit_step(d, m2, body);
+    emit_step(d, m2, body, xy);
     PassMachine m3 = m2;
     std::vector<PassDesc> body2;
-    emit_step(d, m3, body2);
+    emit_step(d, m3, body2, xy);
     if (!(m2 == m3) || !(body == body2)) {  // no steady state: launch eagerly
       DevView e = d;
       e.graphs = nullptr;
@@ -598,6 +636,15 @@ hipError_t dispatch(int n, int S, bool f64, F&& f) {
 int k3d_table_tile(int n, bool f64) {
   (void)n;
   return f64 ? zcols<Z128, double>() : zcols<Z128, float>();
+}
+
+bool k3d_plane(int n, bool f64) {
+  bool r = false;
+  (void)dispatch(n, 1, f64, [&]<typename T, class SC, int S>() -> hipError_t {
+    r = Passes<T, SC, S>::PLANE;
+    return hipSuccess;
+  });
+  return r;
 }
 
 bool k3d_supported(int n, int S) {

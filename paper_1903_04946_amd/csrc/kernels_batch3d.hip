@@ -93,6 +93,22 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
                                     kin, m.conj, lds, blockIdx.x, blockIdx.y);
 }
 
+// fused xy plane pass (y forward, x phase, y inverse) of cycle c:
+// grid (N planes, S x members).
+template <typename T, class SC>
+__global__ void __launch_bounds__(SC::N * SC::TPC)
+    k3b_plane(const BMember3* __restrict__ mem, int S, int64_t c) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = blockIdx.y / S, s = blockIdx.y % S;
+  const BMember3 m = mem[mi];
+  if (c >= m.cycles) return;
+  const int tidx = prog_index(m.prog[2 * (int)(c % m.M) + 1]);
+  const cx<T>* kin = (const cx<T>*)m.kin + (size_t)tidx * 3 * m.kin_stride;
+  constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
+  plane_body<T, SC>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw, kin, m.conj, lds, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- variants
 // z: pass tile of 16 or 8 columns (the table tile is 16 wide).
 constexpr int zwidth(int v) { return v == 0 ? kTableCols : kTableCols / 2; }
@@ -178,9 +194,25 @@ hipError_t launch_x(int S, const BMember3* mem, int count, int64_t c, hipStream_
 }
 
 template <typename T, class SC>
+hipError_t launch_plane(int S, const BMember3* mem, int count, int64_t c, hipStream_t st) {
+  if constexpr (!plane_fits<T, SC>()) {
+    return hipErrorInvalidValue;
+  } else {
+    auto k = k3b_plane<T, SC>;
+    const size_t lds = plane_lds_elems<T, SC>() * sizeof(cx<T>);
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(SC::N, S * count), dim3(SC::N * SC::TPC), lds, st, mem, S, c);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, class SC>
 hipError_t launch_kind(int kind, int S, int v, const BMember3* mem, int count, int64_t c,
                        hipStream_t st) {
   switch (kind) {
+    case B3_XY:
+      return v == 0 ? launch_plane<T, SC>(S, mem, count, c, st) : hipErrorInvalidValue;
     case B3_Z: {
       auto z = [&]<int V>() -> hipError_t {
         if (S == 1) return launch_z<T, SC, 1, V>(mem, count, c, st);
@@ -223,6 +255,7 @@ hipError_t by_grid(int n, bool f64, F&& f) {
 // widths of the variants (0 if the variant does not exist)
 template <typename T, class SC>
 int width_of(int kind, int v) {
+  if (kind == B3_XY) return (v == 0 && plane_fits<T, SC>()) ? SC::N : 0;
   if (kind == B3_Z) return (v == 0 || v == 1) ? zwidth(v) : 0;
   if (v < 0 || v > 2) return 0;
   const int w = (kind == B3_XP) ? scaled(xrows<SC>(), v) : scaled(cols<SC, T>(), v);
@@ -246,8 +279,10 @@ int k3b_variant_width(int kind, int n, bool f64, int variant) {
 int k3b_variants(int kind, int n, bool f64) {
   (void)n;
   (void)f64;
-  return kind == B3_Z ? 2 : 3;
+  return kind == B3_XY ? 1 : (kind == B3_Z ? 2 : 3);
 }
+
+bool k3b_plane(int n, bool f64) { return k3b_variant_width(B3_XY, n, f64, 0) > 0; }
 
 hipError_t k3b_launch(int kind, int n, int S, bool f64, int variant, const BMember3* mem,
                       int count, int64_t cycle, hipStream_t stream) {

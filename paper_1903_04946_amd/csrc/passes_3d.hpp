@@ -208,4 +208,76 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
   for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) + yo, v[0][q]);
 }
 
+// ---------------------------------------------------------------- xy plane
+// The y-forward, x (forward, kinetic phase, inverse) and y-inverse passes of
+// one kinetic action fused for grids whose whole xy plane fits in LDS: block
+// = one plane z of one surface, N x TPC threads.  Column layout (lane ->
+// x = lane % N, t = lane / N) for the y transforms, row layout (lane ->
+// t = lane % TPC, y = lane / TPC) for the x transforms, LDS transposes in
+// between.  Every pencil sees the same stages, twiddles and phase products
+// as in the three separate passes, so the values are identical.
+template <typename T, class SC>
+constexpr size_t plane_lds_elems() {
+  return (size_t)SC::N * (SC::N + SC::N / 16);
+}
+template <typename T, class SC>
+constexpr bool plane_fits() {
+  return plane_lds_elems<T, SC>() * sizeof(cx<T>) <= 160 * 1024 && SC::N * SC::TPC <= 1024;
+}
+
+template <typename T, class SC>
+__device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
+                                           const cx<T>* __restrict__ tw,
+                                           const cx<T>* __restrict__ kin, int conj, cx<T>* lds,
+                                           int z) {
+  constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
+  constexpr int P = N + N / 16;  // padded row stride in LDS
+  const int lane = threadIdx.x;
+  const int col = lane % N, tc = lane / N;    // column layout
+  const int tr = lane % TPC, row = lane / TPC;  // row layout
+  constexpr int64_t plane = (int64_t)N * N;
+  const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
+  const cx<T>* twy = tw + N;
+  const cx<T>* twx = tw + 2 * N;
+  const LayStrided lcol{col, 0, N};
+  const LayPadded lrow{row * P, 0};
+  cx<T> v[1][E];
+  // y forward (columns)
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(tc, q) * N + col);
+  fft_forward<SC, 1>(v, lds, lcol, twy, tc);
+  // columns -> rows
+#pragma unroll
+  for (int q = 0; q < E; ++q) lds[own_idx<N, E, SC::RL>(tc, q) * P + col] = v[0][q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = lds[row * P + own_idx<N, E, SC::RF>(tr, q)];
+  __syncthreads();
+  // x forward, phase, x inverse (rows; row index = k_y, plane index = k_z)
+  fft_forward<SC, 1>(v, lds, lrow, twx, tr);
+  {
+    const T csign = conj ? (T)-1 : (T)1;
+    cx<T> fzy = cmul(kin[z], kin[N + row]);
+    fzy.im *= csign;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(tr, q)];
+      fx.im *= csign;
+      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
+    }
+  }
+  fft_inverse<SC, 1>(v, lds, lrow, twx, tr);
+  // rows -> columns
+#pragma unroll
+  for (int q = 0; q < E; ++q) lds[row * P + own_idx<N, E, SC::RF>(tr, q)] = v[0][q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[0][q] = lds[own_idx<N, E, SC::RL>(tc, q) * P + col];
+  __syncthreads();
+  // y inverse (columns)
+  fft_inverse<SC, 1>(v, lds, lcol, twy, tc);
+#pragma unroll
+  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, SC::RF>(tc, q) * N + col, v[0][q]);
+}
+
 }  // namespace sop

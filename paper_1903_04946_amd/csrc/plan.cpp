@@ -727,6 +727,13 @@ sop_status sop_plan_set_option(sop_plan* p, int option, int value) {
       p->use_graphs = value != 0;
       p->dv.graphs = (p->use_graphs && p->graphs) ? p->graphs : nullptr;
       return SOP_OK;
+    case SOP_OPT_PLANE_PASS:
+      if (p->graphs) {  // captured segments hold the old pass sequence
+        HIPTRY(hipStreamSynchronize(p->dv.stream));
+        p->graphs->clear();
+      }
+      p->dv.plane = value != 0;
+      return SOP_OK;
     default:
       return fail(SOP_ERR_INVALID, "unknown option");
   }

@@ -55,7 +55,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
            "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
            "sop_batch_describe"]
-KINDS = ["zpass", "ypass", "xpass", "k1d", "other"]
+KINDS = ["zpass", "ypass", "xpass", "k1d", "other", "plane"]
 
 _lib = None
 
@@ -319,6 +319,10 @@ class Plan:
         """3D runs of >= 4 steps as captured HIP graphs (default on)."""
         _check(lib().sop_plan_set_option(self._h, 1, int(bool(enable))), "sop_plan_set_option")
 
+    def set_plane_pass(self, enable: bool):
+        """Fused xy plane pass on 3D grids whose plane fits in LDS (default on)."""
+        _check(lib().sop_plan_set_option(self._h, 2, int(bool(enable))), "sop_plan_set_option")
+
     def set_timing(self, enable: bool):
         """Brackets every kernel launch with HIP events (measurement aid)."""
         _check(lib().sop_plan_set_timing(self._h, int(bool(enable))), "sop_plan_set_timing")
@@ -384,6 +388,9 @@ class Batch:
 
     def set_graphs(self, enable: bool):
         _check(lib().sop_batch_set_option(self._h, 1, int(bool(enable))), "sop_batch_set_option")
+
+    def set_plane_pass(self, enable: bool):
+        _check(lib().sop_batch_set_option(self._h, 2, int(bool(enable))), "sop_batch_set_option")
 
     def describe(self) -> dict:
         import json

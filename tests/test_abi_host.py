@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(soprop.EXPORTS)
-    assert L.sop_abi_version() == 1
+    assert L.sop_abi_version() == 2
 
 
 def test_supported_lengths(L):

@@ -316,3 +316,24 @@ def test_ensemble_manifest_bench_shape(torch_cuda):
             assert rel_l2(a, b) < FP64_TOL, f"member {i}"
     for i, (p, x) in enumerate(zip(plans, psis)):
         assert abs(p.observables(x)["norm"] - 1.0) < 1e-10, f"member {i}"
+
+
+def test_batch_plane_pass_equals_three_passes(torch_cuda):
+    """Lockstep groups with the fused xy plane pass and with three separate
+    passes give bitwise the same states."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    mix = [r for r in MIX if r[0] == "3d" and r[3] == "VTV"]
+    models, plans, ns = build_members(torch, torch.complex128, mix)
+    a = soprop.Batch(plans)
+    b = soprop.Batch(plans)
+    b.set_plane_pass(False)
+    assert all(g["plane"] for g in a.describe()["groups"])
+    pa = states(torch, models, torch.complex128)
+    pb = states(torch, models, torch.complex128)
+    a.propagate(pa, ns)
+    b.propagate(pb, ns)
+    torch.cuda.synchronize()
+    assert not any(g["plane"] for g in b.describe()["groups"])
+    for i in range(len(ns)):
+        np.testing.assert_array_equal(pa[i].cpu().numpy(), pb[i].cpu().numpy(), err_msg=f"{i}")

@@ -414,3 +414,28 @@ def test_3d_propagate_many(torch_cuda):
         one = torch.from_numpy(states[i].copy()).cuda()
         plan.propagate(one, 5)
         np.testing.assert_array_equal(many[i].cpu().numpy(), one.cpu().numpy())
+
+
+@pytest.mark.parametrize("n,c64", [(32, False), (48, False), (64, False), (128, True)])
+def test_3d_plane_pass_equals_three_passes(torch_cuda, n, c64):
+    """The fused xy plane pass gives bitwise the values of the separate
+    y-forward, x (phase) and y-inverse passes."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    dtype = torch.complex64 if c64 else torch.complex128
+    m = synth.lvc_3d(n=n, q0=(0.5, -0.3, 0.2), p0=(0.4, 0.1, -0.6))
+    a = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=10.0, dtype=dtype)
+    b = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=10.0, dtype=dtype)
+    b.set_plane_pass(False)
+    pa = torch.from_numpy(m.psi0.copy()).to(dtype).cuda()
+    pb = torch.from_numpy(m.psi0.copy()).to(dtype).cuda()
+    for nsteps in (1, 5):  # eager, then graph-captured segments
+        a.propagate(pa, nsteps)
+        b.propagate(pb, nsteps)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+    a.set_timing(True)
+    a.propagate(pa, 1)
+    kinds = a.timing_read()
+    a.set_timing(False)
+    assert "plane" in kinds and "ypass" not in kinds and "xpass" not in kinds
