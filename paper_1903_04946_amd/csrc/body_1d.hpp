@@ -38,28 +38,41 @@ constexpr int lds_pencil() {
   return SC::N + SC::N / 16;
 }
 
+// GUARD: pass the thread index through opaque() for every transform and
+// action, so that twiddles and addresses are recomputed instead of being
+// held for the whole run.  Measured per step on gfx950 (two surfaces, FP64):
+// N = 8192 55 us guarded vs 141 us held (spilled); 512 and 2048 slightly
+// faster guarded; 1024 and 4096 slightly faster without.
+constexpr bool guard_default(int n) { return n == 512 || n == 2048 || n >= 8192; }
+template <bool GUARD>
+__device__ __forceinline__ int guard(int t) {
+  if constexpr (GUARD) return opaque(t);
+  else return t;
+}
+
 // PL = pencils exchanged through LDS at once (S, or 1 when S pencils do not
-// fit).  `lds` holds PL padded pencils; t = thread index (< SC::TPC).
-template <typename T, class SC, int S, int PL>
+// fit).  `lds` holds PL padded pencils.
+template <typename T, class SC, int S, int PL, bool GUARD = guard_default(SC::N)>
 __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp,
                                        const cx<T>* __restrict__ kin,
                                        const cx<T>* __restrict__ tw,
                                        const int* __restrict__ prog, int nact, int64_t nsteps,
                                        int conj, cx<T>* lds) {
-  const int t = threadIdx.x;
+  const int t0 = threadIdx.x;
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
   const T csign = conj ? (T)-1 : (T)1;
   cx<T> v[S][E];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = psi[s * N + own_idx<N, E, SC::RF>(t, q)];
+    for (int q = 0; q < E; ++q) v[s][q] = psi[s * N + own_idx<N, E, SC::RF>(t0, q)];
   const LayPadded lay{0, lds_pencil<SC>()};
 
   for (int64_t step = 0; step < nsteps; ++step) {
     for (int a = 0; a < nact; ++a) {
       const int code = prog[a];
       const int idx = code & 0xffff;
+      const int t = guard<GUARD>(t0);
       if ((code >> 16) == OP_V) {
         const cx<T>* U = vexp + (size_t)idx * NE * N;
 #pragma unroll
@@ -80,10 +93,10 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
         }
       } else {
         if constexpr (PL == S) {
-          fft_forward<SC, S>(v, lds, lay, tw, t);
+          fft_forward<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
         } else {
 #pragma unroll
-          for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
+          for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, guard<GUARD>(t0));
         }
         const cx<T>* F = kin + (size_t)idx * N;
 #pragma unroll
@@ -94,10 +107,10 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
           for (int s = 0; s < S; ++s) v[s][q] = cmul(v[s][q], f);
         }
         if constexpr (PL == S) {
-          fft_inverse<SC, S>(v, lds, lay, tw, t);
+          fft_inverse<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
         } else {
 #pragma unroll
-          for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
+          for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, guard<GUARD>(t0));
         }
       }
     }
@@ -105,7 +118,7 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int q = 0; q < E; ++q) psi[s * N + own_idx<N, E, SC::RF>(t, q)] = v[s][q];
+    for (int q = 0; q < E; ++q) psi[s * N + own_idx<N, E, SC::RF>(t0, q)] = v[s][q];
 }
 
 }  // namespace sop

@@ -206,6 +206,15 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<fl
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(sop_u32x2, v), r, (int)(idx * 8u), 0, 0);
 }
 
+// The thread index passed through an empty asm statement: the compiler can no
+// longer prove two transforms use the same twiddle and LDS addresses, so it
+// reloads each transform's twiddles instead of keeping those of every stage
+// and surface live across the whole step (which spills large pencils).
+__device__ __forceinline__ int opaque(int t) {
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Element index owned by thread t in register slot `slot` for a radix-R stage.
 template <int N, int E, int R>
 __device__ __forceinline__ int own_idx(int t, int slot) {

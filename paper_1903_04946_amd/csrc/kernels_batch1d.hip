@@ -7,16 +7,17 @@
 // compute units as workgroups retire.  Each member has its own tables,
 // program, step count and direction; the family only fixes the kernel.
 //
-// The schedule of a family (values per thread E and the radix sequence) is
-// picked by the planner's tuner among the variants below; variant 0 is the
-// schedule of the single-plan kernel.  All variants compute the same DFTs,
-// in different radix orders.
+// The schedule of a family (values per thread E, the radix sequence, and
+// whether twiddles are recomputed per transform) is picked by the planner's
+// tuner among the variants below; variant 0 is the schedule of the
+// single-plan kernel.  All variants compute the same DFTs, in different
+// radix orders.
 #include "body_1d.hpp"
 
 namespace sop {
 namespace {
 
-// variants 1 and 2: four and sixteen values per thread
+// alternative schedules: four and sixteen values per thread
 template <int N>
 struct Alt;
 template <>
@@ -46,28 +47,28 @@ struct Alt<8192> {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-template <typename T, class SC, int S, int PL>
+template <typename T, class SC, int S, int PL, bool G>
 __global__ void __launch_bounds__(SC::TPC)
     k1b_kernel(const BMember1* __restrict__ mem) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const BMember1 m = mem[blockIdx.x];
   if (m.nsteps <= 0) return;
-  run_1d<T, SC, S, PL>((cx<T>*)m.psi, (const cx<T>*)m.vexp, (const cx<T>*)m.kin,
-                       (const cx<T>*)m.tw, m.prog, m.nact, m.nsteps, m.conj, lds);
+  run_1d<T, SC, S, PL, G>((cx<T>*)m.psi, (const cx<T>*)m.vexp, (const cx<T>*)m.kin,
+                          (const cx<T>*)m.tw, m.prog, m.nact, m.nsteps, m.conj, lds);
 }
 
-template <typename T, class SC, int S>
+template <typename T, class SC, int S, bool G>
 hipError_t launch(const BMember1* mem, int count, hipStream_t stream) {
   constexpr size_t one = (size_t)lds_pencil<SC>() * sizeof(cx<T>);
   if constexpr (one * S <= kMaxLds) {
-    auto k = k1b_kernel<T, SC, S, S>;
+    auto k = k1b_kernel<T, SC, S, S, G>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(one * S));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(count), dim3(SC::TPC), one * S, stream, mem);
   } else {
-    auto k = k1b_kernel<T, SC, S, 1>;
+    auto k = k1b_kernel<T, SC, S, 1, G>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)one);
     if (e != hipSuccess) return e;
@@ -76,28 +77,31 @@ hipError_t launch(const BMember1* mem, int count, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <class SC>
+template <class SC, bool G = guard_default(SC::N)>
 hipError_t by_type(int S, bool f64, const BMember1* mem, int count, hipStream_t stream) {
   if (f64) {
-    if (S == 1) return launch<double, SC, 1>(mem, count, stream);
-    if (S == 2) return launch<double, SC, 2>(mem, count, stream);
+    if (S == 1) return launch<double, SC, 1, G>(mem, count, stream);
+    if (S == 2) return launch<double, SC, 2, G>(mem, count, stream);
   } else {
-    if (S == 1) return launch<float, SC, 1>(mem, count, stream);
-    if (S == 2) return launch<float, SC, 2>(mem, count, stream);
+    if (S == 1) return launch<float, SC, 1, G>(mem, count, stream);
+    if (S == 2) return launch<float, SC, 2, G>(mem, count, stream);
   }
   return hipErrorInvalidValue;
 }
 
-// variants of one tuned length: default E8, E4 (if N/4 <= 1024 threads), E16
+// variants of one tuned length N <= 4096: 0 the default E8 schedule, 1 the
+// same with the other twiddle policy, 2 E4 and 3 E16 (recomputed twiddles);
+// N = 8192: 0 E8, 1 E16 (both recomputed).
 template <int N, class DEF>
 hipError_t tuned(int variant, int S, bool f64, const BMember1* mem, int count,
                  hipStream_t stream) {
   if (variant == 0) return by_type<DEF>(S, f64, mem, count, stream);
   if constexpr (N <= 4096) {
-    if (variant == 1) return by_type<typename Alt<N>::E4>(S, f64, mem, count, stream);
-    if (variant == 2) return by_type<typename Alt<N>::E16>(S, f64, mem, count, stream);
+    if (variant == 1) return by_type<DEF, !guard_default(N)>(S, f64, mem, count, stream);
+    if (variant == 2) return by_type<typename Alt<N>::E4, true>(S, f64, mem, count, stream);
+    if (variant == 3) return by_type<typename Alt<N>::E16, true>(S, f64, mem, count, stream);
   } else {
-    if (variant == 1) return by_type<typename Alt<N>::E16>(S, f64, mem, count, stream);
+    if (variant == 1) return by_type<typename Alt<N>::E16, true>(S, f64, mem, count, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -106,7 +110,7 @@ hipError_t tuned(int variant, int S, bool f64, const BMember1* mem, int count,
 
 int k1b_variants(int n) {
   switch (n) {
-    case 512: case 1024: case 2048: case 4096: return 3;
+    case 512: case 1024: case 2048: case 4096: return 4;
     case 8192: return 2;
     case 16: case 32: case 64: case 128: case 256: return 1;
     default: return 0;
@@ -114,37 +118,39 @@ int k1b_variants(int n) {
 }
 
 const char* k1b_variant_name(int n, int variant) {
-  if (variant == 0) {
+  const bool g = guard_default(n);
+  if (variant == 0 || (variant == 1 && n <= 4096)) {
+    const bool guarded = (variant == 0) ? g : !g;
     switch (n) {
       case 16: return "E4 radix 4.4";
       case 32: return "E8 radix 8.4";
       case 64: return "E8 radix 8.8";
       case 128: return "E8 radix 8.4.4";
       case 256: return "E8 radix 8.8.4";
-      case 512: return "E8 radix 8.8.8";
-      case 1024: return "E8 radix 8.4.4.8";
-      case 2048: return "E8 radix 8.8.4.8";
-      case 4096: return "E8 radix 8.8.8.8";
-      case 8192: return "E8 radix 8.8.8.8.2";
+      case 512: return guarded ? "E8 radix 8.8.8, recomputed twiddles" : "E8 radix 8.8.8";
+      case 1024: return guarded ? "E8 radix 8.4.4.8, recomputed twiddles" : "E8 radix 8.4.4.8";
+      case 2048: return guarded ? "E8 radix 8.8.4.8, recomputed twiddles" : "E8 radix 8.8.4.8";
+      case 4096: return guarded ? "E8 radix 8.8.8.8, recomputed twiddles" : "E8 radix 8.8.8.8";
+      case 8192: return "E8 radix 8.8.8.8.2, recomputed twiddles";
       default: return "?";
     }
   }
-  if (n == 8192) return variant == 1 ? "E16 radix 8.8.8.16" : "?";
-  if (variant == 1) {
-    switch (n) {
-      case 512: return "E4 radix 4.4.4.4.2";
-      case 1024: return "E4 radix 4.4.4.4.4";
-      case 2048: return "E4 radix 4.4.4.4.4.2";
-      case 4096: return "E4 radix 4.4.4.4.4.4";
-      default: return "?";
-    }
-  }
+  if (n == 8192) return variant == 1 ? "E16 radix 8.8.8.16, recomputed twiddles" : "?";
   if (variant == 2) {
     switch (n) {
-      case 512: return "E16 radix 16.8.4";
-      case 1024: return "E16 radix 16.16.4";
-      case 2048: return "E16 radix 16.16.8";
-      case 4096: return "E16 radix 16.16.16";
+      case 512: return "E4 radix 4.4.4.4.2, recomputed twiddles";
+      case 1024: return "E4 radix 4.4.4.4.4, recomputed twiddles";
+      case 2048: return "E4 radix 4.4.4.4.4.2, recomputed twiddles";
+      case 4096: return "E4 radix 4.4.4.4.4.4, recomputed twiddles";
+      default: return "?";
+    }
+  }
+  if (variant == 3) {
+    switch (n) {
+      case 512: return "E16 radix 16.8.4, recomputed twiddles";
+      case 1024: return "E16 radix 16.16.4, recomputed twiddles";
+      case 2048: return "E16 radix 16.16.8, recomputed twiddles";
+      case 4096: return "E16 radix 16.16.16, recomputed twiddles";
       default: return "?";
     }
   }
