@@ -5,12 +5,12 @@
 //     one workgroup per member for its whole run, members in decreasing
 //     order of work;
 //   * 3D lockstep groups (n in {32, 48, 64}, surfaces, precision, VTV
-//     program): four pass launches per cycle (kernels_batch3d.hip).  The
-//     members are sorted by decreasing cycle count and cut into chains whose
-//     counts lie within a factor of 4 of the chain's longest; each chain is
-//     its own branch, so a few long runs proceed beside the bulk instead of
-//     after it, and launch c of a chain covers only the members still
-//     running at cycle c;
+//     program): three pass launches per cycle, two with the plane pass
+//     (kernels_batch3d.hip).  The members are sorted by decreasing cycle
+//     count and cut into chains whose counts lie within a factor of 4 of
+//     the chain's longest; each chain is its own branch, so a few long runs
+//     proceed beside the bulk instead of after it, and launch c of a chain
+//     covers only the members still running at cycle c;
 //   * any other member runs its own plan's executor.
 // Every family, group and single member is one branch of a fork/join HIP
 // graph (branches on separate capture streams), so one propagate call is
@@ -298,8 +298,8 @@ sop_status tune_group(sop_batch* b, Group3& g) {
     }
   };
   pick(sop::B3_Z, g.ms_z, &g.vz);
-  pick(sop::B3_YF, g.ms_y, &g.vy);
-  pick(sop::B3_XP, g.ms_x, &g.vx);
+  pick(sop::B3_Y, g.ms_y, &g.vy);
+  pick(sop::B3_X, g.ms_x, &g.vx);
   (void)hipStreamSynchronize(b->stream);
   (void)hipFree(scratch);
   (void)hipFree(d_mem);
@@ -346,13 +346,10 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
             return e;
           continue;
         }
-        if ((e = sop::k3b_launch(sop::B3_YF, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
+        if ((e = sop::k3b_launch(sop::B3_Y, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
             hipSuccess)
           return e;
-        if ((e = sop::k3b_launch(sop::B3_XP, g.n, g.S, g.f64, g.vx, mem, nyx, c, st)) !=
-            hipSuccess)
-          return e;
-        if ((e = sop::k3b_launch(sop::B3_YI, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
+        if ((e = sop::k3b_launch(sop::B3_X, g.n, g.S, g.f64, g.vx, mem, nyx, c, st)) !=
             hipSuccess)
           return e;
       }
@@ -390,12 +387,12 @@ hipError_t fork_join(sop_batch* b, hipStream_t origin, const std::vector<int64_t
 int64_t count_nodes(const sop_batch* b, const std::vector<int64_t>& nsteps) {
   int64_t n = (int64_t)b->fams.size();
   for (const Group3& g : b->groups) {
-    const int per = (b->use_plane && sop::k3b_plane(g.n, g.f64)) ? 2 : 4;
+    const int per = (b->use_plane && sop::k3b_plane(g.n, g.f64)) ? 2 : 3;
     for (const auto& ch : g.chains) n += per * g.cycles[ch.first] + 1;
   }
   for (int m : b->solo) {
     const DevView& d = *b->views[m];
-    n += d.ndim == 1 ? 1 : 4 * (int64_t)d.nact * nsteps[m] + 1;
+    n += d.ndim == 1 ? 1 : 3 * (int64_t)d.nact * nsteps[m] + 1;
   }
   return n;
 }
@@ -517,7 +514,7 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
     auto ok = [&](int kind, int v) { return sop::k3b_variant_width(kind, g.n, g.f64, v) > 0; };
     int vz, vy, vx;
     if (cached(k + "/z", 2, &vz) && cached(k + "/y", 3, &vy) && cached(k + "/x", 3, &vx) &&
-        ok(sop::B3_Z, vz) && ok(sop::B3_YF, vy) && ok(sop::B3_XP, vx)) {
+        ok(sop::B3_Z, vz) && ok(sop::B3_Y, vy) && ok(sop::B3_X, vx)) {
       g.vz = vz;
       g.vy = vy;
       g.vx = vx;
@@ -711,8 +708,8 @@ sop_status sop_batch_describe(const sop_batch* b, char* buf, size_t len, size_t*
       << dtype_name(g.f64) << "\", \"members\": ";
     members(g.members);
     o << ", \"z_cols\": " << sop::k3b_variant_width(sop::B3_Z, g.n, g.f64, g.vz)
-      << ", \"y_cols\": " << sop::k3b_variant_width(sop::B3_YF, g.n, g.f64, g.vy)
-      << ", \"x_rows\": " << sop::k3b_variant_width(sop::B3_XP, g.n, g.f64, g.vx)
+      << ", \"y_cols\": " << sop::k3b_variant_width(sop::B3_Y, g.n, g.f64, g.vy)
+      << ", \"x_rows\": " << sop::k3b_variant_width(sop::B3_X, g.n, g.f64, g.vx)
       << ", \"plane\": " << ((b->use_plane && sop::k3b_plane(g.n, g.f64)) ? "true" : "false")
       << ", \"from_cache\": " << (g.from_cache ? "true" : "false") << ", \"tuned_ms\": {\"z\": ";
     arr(g.ms_z);

@@ -48,16 +48,18 @@ struct Timer {
   }
 };
 
-// One pass of the 3D executor.
+// One pass of the 3D executor: Z = potential action(s), then (kz) the z
+// factor of kinetic set tidx; Y, X = the y / x factor of set tidx; XY = both
+// in one plane pass.
 struct PassDesc {
-  enum Kind { Z = 0, YF = 1, YI = 2, XP = 3, XY = 4 };
+  enum Kind { Z = 0, Y = 1, X = 2, XY = 3 };
   int kind = Z;
-  bool pre_inv = false, post_fwd = false;
+  bool kz = false;
   int nv = 0, iv0 = 0, iv1 = 0;  // z-pass potential actions
-  int tidx = 0;                  // x-pass kinetic factor set
+  int tidx = 0;                  // kinetic factor set
   bool operator==(const PassDesc& o) const {
-    return kind == o.kind && pre_inv == o.pre_inv && post_fwd == o.post_fwd && nv == o.nv &&
-           iv0 == o.iv0 && iv1 == o.iv1 && tidx == o.tidx;
+    return kind == o.kind && kz == o.kz && nv == o.nv && iv0 == o.iv0 && iv1 == o.iv1 &&
+           tidx == o.tidx;
   }
 };
 
@@ -186,7 +188,8 @@ struct BMember1 {
 // Device descriptor of one 3D member of a lockstep group
 // (kernels_batch3d.hip).  The member's program is the pruned VTV sequence
 // V T V ... T V (nact = 2M + 1); cycle c < cycles = M * nsteps is its
-// kinetic action number c, cycle c = cycles its closing potential action.
+// kinetic action number c with the potential action(s) before it, cycle
+// c = cycles its closing potential action.
 struct BMember3 {
   void* psi;          // [S][n^3]
   const void* vexp;   // tile-layout potential tables
@@ -213,10 +216,10 @@ const char* k1b_variant_name(int n, int variant);
 hipError_t k1b_launch(int n, int S, bool f64, int variant, const BMember1* mem, int count,
                       hipStream_t stream);
 
-// 3D lockstep groups.  kind: 0 z-pass, 1 y forward, 2 x (phase), 3 y inverse,
-// 4 fused xy plane (kinds 1-3 in one pass, where the plane fits in LDS); the y
-// variants apply to both y kinds.
-enum { B3_Z = 0, B3_YF = 1, B3_XP = 2, B3_YI = 3, B3_XY = 4 };
+// 3D lockstep groups.  kind: 0 z-pass (potential, z factor), 1 y factor,
+// 2 x factor, 3 fused xy plane (kinds 1 and 2 in one pass, where the plane
+// fits in LDS).
+enum { B3_Z = 0, B3_Y = 1, B3_X = 2, B3_XY = 3 };
 bool k3b_supported(int n, int S);
 bool k3b_plane(int n, bool f64);
 int k3b_variants(int kind, int n, bool f64);

@@ -2,23 +2,20 @@
 // as a sequence of pencil passes over psi[s][z][y][x] (x fastest).
 //
 // A substep (one potential action followed by one kinetic action, Sec.
-// "Dynamic Fourier method") is four passes over the state:
-//   z-pass : [inverse FFT along z] -> potential unitary(ies) -> [forward FFT z]
+// "Dynamic Fourier method") is three passes over the state, each from and
+// back to the position representation (the kinetic propagator factors over
+// the axes, see passes_3d.hpp):
+//   z-pass : potential unitary(ies) -> forward FFT z -> f_z -> inverse FFT z
 //            (all S surfaces of a tile of x-columns, so the S x S matvec of
 //            Sec. "Molecular Hamiltonian in the diabatic basis" runs in
 //            registers);
-//   y-pass : forward FFT along y;
-//   x-pass : forward FFT along x -> kinetic phase -> inverse FFT along x;
-//   y-pass : inverse FFT along y.
-// Between passes the z axis stays in the momentum representation, so the
-// potential's own pass carries the z transforms.  The last potential action
-// of a step and the first of the next share one z-pass (two matvecs in
-// registers; the arithmetic is the same as two separate passes).
-// The kinetic factor is separable, exp(-i tau T(p)/hbar) / (n_y n_x) =
-// f_z(k_z) f_y(k_y) f_x(k_x); the planner stores the three per-axis factors
-// of each unique coefficient.  The 1/n_z of the z round trip is applied by
-// the z-pass after its inverse transform, because consecutive kinetic
-// actions (TVT at a step boundary) share one z round trip.
+//   y-pass : forward FFT y -> f_y -> inverse FFT y;
+//   x-pass : forward FFT x -> f_x -> inverse FFT x;
+// or, where the xy plane fits in LDS, the z-pass and one plane pass.  The
+// last potential action of a step and the first of the next share one
+// z-pass (two matvecs in registers; the arithmetic is the same as two
+// separate passes).  The planner stores the three per-axis factors
+// f_d = exp(-i tau hbar kappa^2 / (2 m_d)) / n_d of each unique coefficient.
 #include <type_traits>
 #include <vector>
 
@@ -57,15 +54,16 @@ constexpr int zcols() {
 }
 
 // ---------------------------------------------------------------- z-pass
-template <typename T, class SC, int S, int C, bool PRE_INV, bool POST_FWD>
+// grid (N / C, N, states); fz = the z factor of the kinetic set (AX_KIN)
+template <typename T, class SC, int S, int C, int AX>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
-              int conj, const cx<T>* __restrict__ tw) {
+              int conj, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fz) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   psi += (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member of a batch
-  zpass_body<T, SC, S, C, C, PRE_INV, POST_FWD>(psi, vexp, nv, iv0, iv1, conj, tw, lds,
-                                                blockIdx.x, blockIdx.y);
+  zpass_body<T, SC, S, C, C, AX>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds, blockIdx.x,
+                                 blockIdx.y);
 }
 
 // ---------------------------------------------------------------- adjoint z-pass
@@ -81,13 +79,15 @@ __global__ void __launch_bounds__(C * SC::TPC)
 //        = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2),
 // so that d P / d theta_k = 2 dV sum_x sum_ij Q_ij(x) D_k,ij(x) (Daleckii-
 // Krein form of the Frechet derivative of exp(-i tau V(theta))).  Q is kept
-// packed (Q_ii; Q_ij + Q_ji for i < j) in qacc[entry][point].
-template <class SC, int S, int C, bool PRE_INV, bool POST_FWD>
+// packed (Q_ii; Q_ij + Q_ji for i < j) in qacc[entry][point].  With KZ the
+// pass then applies the adjoint z factor K_z^dag (conjugated f_z) to all 2S
+// pencils.
+template <class SC, int S, int C, bool KZ>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ vexp,
                   const cx<double>* __restrict__ eig, double* __restrict__ qacc,
                   const double* __restrict__ taus, int nv, int iv0, int iv1,
-                  const cx<double>* __restrict__ tw) {
+                  const cx<double>* __restrict__ tw, const cx<double>* __restrict__ fz) {
   extern __shared__ char smem_raw[];
   cx<double>* lds = reinterpret_cast<cx<double>*>(smem_raw);
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2, P = 2 * S;
@@ -101,21 +101,12 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
   const LayStrided lay{col, 0, C};
   cx<double> v[P][E];
-  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const auto rs = rsrc(stk + s * npts, (uint32_t)npts);
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = ld<double>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
-  }
-  if constexpr (PRE_INV) {
-#pragma unroll
-    for (int s = 0; s < P; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
-    constexpr double inv_n = 1.0 / (double)N;
-#pragma unroll
-    for (int s = 0; s < P; ++s)
-#pragma unroll
-      for (int q = 0; q < E; ++q) v[s][q] = cx<double>{v[s][q].re * inv_n, v[s][q].im * inv_n};
+    for (int q = 0; q < E; ++q)
+      v[s][q] = ld<double>(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0);
   }
   auto vact = [&](int iv) {
     const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
@@ -202,40 +193,45 @@ __global__ void __launch_bounds__(C * SC::TPC)
   };
   if (nv >= 1) vact(iv0);
   if (nv >= 2) vact(iv1);
-  if constexpr (POST_FWD) {
+  if constexpr (KZ) {
 #pragma unroll
     for (int s = 0; s < P; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
+    axis_phase<double, SC, P>(v, fz, -1.0, t);
+#pragma unroll
+    for (int s = 0; s < P; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
   }
-  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const auto rs = rsrc(stk + s * npts, (uint32_t)npts);
 #pragma unroll
-    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, ROUT>(t, q) * plane + off0, v[s][q]);
+    for (int q = 0; q < E; ++q) st(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0, v[s][q]);
   }
 }
 
 // ---------------------------------------------------------------- y-pass
-// grid (N / C, N, surfaces x states): blockIdx.z picks one surface pencil set
-template <typename T, class SC, int C, bool INV>
+// grid (N / C, N, surfaces x states): blockIdx.z picks one surface pencil set;
+// fy = the y factor of the kinetic set (AX_KIN)
+template <typename T, class SC, int C, int AX>
 __global__ void __launch_bounds__(C * SC::TPC)
-    k3d_ypass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw) {
+    k3d_ypass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
+              const cx<T>* __restrict__ fy, int conj) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  ypass_body<T, SC, C, INV>(psi + blockIdx.z * npts, tw, lds, blockIdx.x, blockIdx.y);
+  ypass_body<T, SC, C, AX>(psi + blockIdx.z * npts, tw, fy, conj, lds, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- x-pass
-template <typename T, class SC, int ROWS, int MODE>
+// grid (N / ROWS, N, surfaces x states); fx = the x factor (AX_KIN)
+template <typename T, class SC, int ROWS, int AX>
 __global__ void __launch_bounds__(ROWS * SC::TPC)
     k3d_xpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
-              const cx<T>* __restrict__ kin, int conj) {
+              const cx<T>* __restrict__ fx, int conj) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  xpass_body<T, SC, ROWS, MODE>(psi + blockIdx.z * npts, tw, kin, conj, lds, blockIdx.x,
-                                blockIdx.y);
+  xpass_body<T, SC, ROWS, AX>(psi + blockIdx.z * npts, tw, fx, conj, lds, blockIdx.x,
+                              blockIdx.y);
 }
 
 // ---------------------------------------------------------------- xy plane
@@ -251,86 +247,59 @@ __global__ void __launch_bounds__(SC::N * SC::TPC)
 }
 
 // ---------------------------------------------------------------- launchers
-// Pass program of the 3D executor.  The machine walks the step program:
-// a potential action opens (or joins, up to two) a z-pass that inverts the
-// z transform first when the state is z-transformed; a kinetic action closes
-// the open z-pass with a forward z transform (or adds a transform-only
-// z-pass) and adds y-forward, x (phase), y-inverse.
+// Pass program of the 3D executor.  The machine walks the step program
+// (forward, or reversed for the adjoint sweep): potential actions are held
+// (up to two) until a kinetic action closes them into one z-pass that also
+// carries that action's z factor, followed by its y- and x-passes (or its
+// plane pass); potential actions still held at the end of the run form a
+// z-pass of their own.
 struct PassMachine {
-  bool zk = false, zopen = false, zpre = false;
   int zv[2] = {0, 0}, znv = 0;
   bool operator==(const PassMachine& o) const {
-    return zk == o.zk && zopen == o.zopen && zpre == o.zpre && znv == o.znv &&
-           (znv < 1 || zv[0] == o.zv[0]) && (znv < 2 || zv[1] == o.zv[1]);
+    return znv == o.znv && (znv < 1 || zv[0] == o.zv[0]) && (znv < 2 || zv[1] == o.zv[1]);
   }
 };
 
-void flush_z(PassMachine& m, bool post_fwd, std::vector<PassDesc>& out) {
+void flush_z(PassMachine& m, bool kz, int tidx, std::vector<PassDesc>& out) {
   PassDesc p;
   p.kind = PassDesc::Z;
-  p.pre_inv = m.zpre;
-  p.post_fwd = post_fwd;
+  p.kz = kz;
+  p.tidx = tidx;
   p.nv = m.znv;
   p.iv0 = m.zv[0];
   p.iv1 = m.zv[1];
   out.push_back(p);
-  m.zopen = false;
   m.znv = 0;
-  m.zk = post_fwd;
+}
+
+// One action of the program: code = prog_entry(op, table index).
+void emit_action(PassMachine& m, int code, std::vector<PassDesc>& out, bool xy) {
+  const int idx = prog_idx(code);
+  if (prog_op(code) == OP_V) {
+    if (m.znv == 2) flush_z(m, false, 0, out);
+    m.zv[m.znv++] = idx;
+    return;
+  }
+  flush_z(m, true, idx, out);
+  PassDesc p;
+  p.tidx = idx;
+  if (xy) {
+    p.kind = PassDesc::XY;
+    out.push_back(p);
+    return;
+  }
+  p.kind = PassDesc::Y;
+  out.push_back(p);
+  p.kind = PassDesc::X;
+  out.push_back(p);
 }
 
 void emit_step(const DevView& d, PassMachine& m, std::vector<PassDesc>& out, bool xy) {
-  for (int a = 0; a < d.nact; ++a) {
-    const int code = d.hprog[a];
-    const int idx = prog_idx(code);
-    if (prog_op(code) == OP_V) {
-      if (m.zopen && m.znv == 2) flush_z(m, false, out);
-      if (!m.zopen) {
-        m.zopen = true;
-        m.zpre = m.zk;
-        m.znv = 0;
-        m.zk = false;
-      }
-      m.zv[m.znv++] = idx;
-    } else {
-      if (m.zopen) {
-        flush_z(m, true, out);
-      } else if (!m.zk) {
-        PassDesc p;
-        p.kind = PassDesc::Z;
-        p.post_fwd = true;
-        out.push_back(p);
-        m.zk = true;
-      }
-      if (xy) {
-        PassDesc p;
-        p.kind = PassDesc::XY;
-        p.tidx = idx;
-        out.push_back(p);
-        continue;
-      }
-      PassDesc y, x, yi;
-      y.kind = PassDesc::YF;
-      x.kind = PassDesc::XP;
-      x.tidx = idx;
-      yi.kind = PassDesc::YI;
-      out.push_back(y);
-      out.push_back(x);
-      out.push_back(yi);
-    }
-  }
+  for (int a = 0; a < d.nact; ++a) emit_action(m, d.hprog[a], out, xy);
 }
 
 void emit_flush(PassMachine& m, std::vector<PassDesc>& out) {
-  if (m.zopen) {
-    flush_z(m, false, out);
-  } else if (m.zk) {
-    PassDesc p;
-    p.kind = PassDesc::Z;
-    p.pre_inv = true;
-    out.push_back(p);
-    m.zk = false;
-  }
+  if (m.znv > 0) flush_z(m, false, 0, out);
 }
 
 template <typename K>
@@ -353,46 +322,45 @@ struct Passes {
   static double pass_bytes(const DevView& d, int ntables) {
     return (2.0 * S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>) * d.count;
   }
+  // axis factor a (0 z, 1 y, 2 x) of kinetic set tidx
+  static const cx<T>* kfac(const DevView& d, int tidx, int a) {
+    return (const cx<T>*)d.kin + ((size_t)tidx * 3 + a) * d.kin_stride;
+  }
 
-  template <bool PI, bool PF>
-  static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int conj) {
-    auto k = k3d_zpass<T, SC, S, CZ, PI, PF>;
+  template <int AX>
+  static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int tidx,
+                      int conj) {
+    auto k = k3d_zpass<T, SC, S, CZ, AX>;
     const size_t lds = (size_t)CZ * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
     hipLaunchKernelGGL(k, dim3(N / CZ, N, d.count), dim3(CZ * SC::TPC), lds, d.stream, psi,
-                       (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0]);
+                       (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0],
+                       AX == AX_KIN ? kfac(d, tidx, 0) : nullptr);
     return hipGetLastError();
   }
-  static hipError_t zpass(const DevView& d, cx<T>* psi, bool pi, bool pf, int nv, int iv0,
-                          int iv1, int conj) {
-    if (pi && pf) return z<true, true>(d, psi, nv, iv0, iv1, conj);
-    if (pi) return z<true, false>(d, psi, nv, iv0, iv1, conj);
-    if (pf) return z<false, true>(d, psi, nv, iv0, iv1, conj);
-    return z<false, false>(d, psi, nv, iv0, iv1, conj);
-  }
-  template <bool INV>
-  static hipError_t ypass(const DevView& d, cx<T>* psi) {
-    auto k = k3d_ypass<T, XS, C, INV>;
+  template <int AX>
+  static hipError_t ypass(const DevView& d, cx<T>* psi, int tidx, int conj) {
+    auto k = k3d_ypass<T, XS, C, AX>;
     const size_t lds = (size_t)C * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
     hipLaunchKernelGGL(k, dim3(N / C, N, d.S * d.count), dim3(C * XS::TPC), lds, d.stream, psi,
-                       (const cx<T>*)d.tw[1]);
+                       (const cx<T>*)d.tw[1], AX == AX_KIN ? kfac(d, tidx, 1) : nullptr, conj);
     return hipGetLastError();
   }
-  template <int MODE>
+  template <int AX>
   static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj) {
-    auto k = k3d_xpass<T, XS, ROWS, MODE>;
+    auto k = k3d_xpass<T, XS, ROWS, AX>;
     const size_t lds = (size_t)ROWS * (N + N / 16) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
-    const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
     TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));
-    hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S * d.count), dim3(ROWS * XS::TPC), lds, d.stream, psi,
-                       (const cx<T>*)d.tw[2], kin, conj);
+    hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S * d.count), dim3(ROWS * XS::TPC), lds,
+                       d.stream, psi, (const cx<T>*)d.tw[2],
+                       AX == AX_KIN ? kfac(d, tidx, 2) : nullptr, conj);
     return hipGetLastError();
   }
 
@@ -405,10 +373,9 @@ struct Passes {
       const size_t lds = plane_lds_elems<T, XS>() * sizeof(cx<T>);
       hipError_t e = set_lds(k, lds);
       if (e != hipSuccess) return e;
-      const cx<T>* kin = (const cx<T>*)d.kin + (size_t)tidx * 3 * d.kin_stride;
       TimedLaunch tl(d, KIND_PLANE, pass_bytes(d, 0));
       hipLaunchKernelGGL(k, dim3(N, d.S * d.count), dim3(N * XS::TPC), lds, d.stream, psi,
-                         (const cx<T>*)d.tw[0], kin, conj);
+                         (const cx<T>*)d.tw[0], kfac(d, tidx, 0), conj);
       return hipGetLastError();
     }
   }
@@ -416,11 +383,12 @@ struct Passes {
   // Launches one pass descriptor.
   static hipError_t launch(const DevView& d, cx<T>* psi, const PassDesc& p, int conj) {
     switch (p.kind) {
-      case PassDesc::Z: return zpass(d, psi, p.pre_inv, p.post_fwd, p.nv, p.iv0, p.iv1, conj);
-      case PassDesc::YF: return ypass<false>(d, psi);
-      case PassDesc::YI: return ypass<true>(d, psi);
-      case PassDesc::XY: return plane(d, psi, p.tidx, conj);
-      default: return xpass<XP_PHASE>(d, psi, p.tidx, conj);
+      case PassDesc::Z:
+        return p.kz ? z<AX_KIN>(d, psi, p.nv, p.iv0, p.iv1, p.tidx, conj)
+                    : z<AX_NONE>(d, psi, p.nv, p.iv0, p.iv1, 0, conj);
+      case PassDesc::Y: return ypass<AX_KIN>(d, psi, p.tidx, conj);
+      case PassDesc::X: return xpass<AX_KIN>(d, psi, p.tidx, conj);
+      default: return plane(d, psi, p.tidx, conj);
     }
   }
   static hipError_t launch_all(const DevView& d, cx<T>* psi, const std::vector<PassDesc>& v,
@@ -491,30 +459,33 @@ struct Passes {
       *out = x;
       return hipSuccess;
     };
-    hipGraphExec_t g1, g2, g3;
+    hipGraphExec_t g1, g2, g3 = nullptr;
     hipError_t e;
     if ((e = seg(0, first, &g1)) != hipSuccess) return e;
     if ((e = seg(1, body, &g2)) != hipSuccess) return e;
-    if ((e = seg(2, tail, &g3)) != hipSuccess) return e;
+    if (!tail.empty() && (e = seg(2, tail, &g3)) != hipSuccess) return e;
     if ((e = hipGraphLaunch(g1, d.stream)) != hipSuccess) return e;
     for (int64_t step = 1; step < nsteps; ++step)
       if ((e = hipGraphLaunch(g2, d.stream)) != hipSuccess) return e;
-    return hipGraphLaunch(g3, d.stream);
+    return g3 ? hipGraphLaunch(g3, d.stream) : hipSuccess;
   }
 
+  // Forward transform of every surface (momentum representation, natural
+  // order, unnormalised) for the observables.
   static hipError_t fft_forward(const DevView& d, void* vpsi) {
     cx<T>* psi = (cx<T>*)vpsi;
-    hipError_t e = zpass(d, psi, false, true, 0, 0, 0, 0);
+    hipError_t e = z<AX_FWD>(d, psi, 0, 0, 0, 0, 0);
     if (e != hipSuccess) return e;
-    if ((e = ypass<false>(d, psi)) != hipSuccess) return e;
-    return xpass<XP_FWD>(d, psi, 0, 0);
+    if ((e = ypass<AX_FWD>(d, psi, 0, 0)) != hipSuccess) return e;
+    return xpass<AX_FWD>(d, psi, 0, 0);
   }
 
   // ------------------------------------------------------------ adjoint
-  template <bool PI, bool PF>
-  static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1) {
+  template <bool KZ>
+  static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1,
+                       int tidx) {
     using SA = typename AdjSched<SC>::type;
-    auto k = k3d_zpass_adj<SA, S, CZ, PI, PF>;
+    auto k = k3d_zpass_adj<SA, S, CZ, KZ>;
     const size_t lds = (size_t)CZ * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
@@ -526,15 +497,9 @@ struct Passes {
     hipLaunchKernelGGL(k, dim3(N / CZ, N), dim3(CZ * SA::TPC), lds, d.stream,
                        (cx<double>*)a.stacked, (const cx<double>*)d.vexp,
                        (const cx<double>*)a.eig, a.qacc, a.taus, nv, iv0, iv1,
-                       (const cx<double>*)d.tw[0]);
+                       (const cx<double>*)d.tw[0],
+                       KZ ? (const cx<double>*)kfac(d, tidx, 0) : nullptr);
     return hipGetLastError();
-  }
-  static hipError_t zadj(const DevView& d, const AdjointView& a, bool pi, bool pf, int nv,
-                         int iv0, int iv1) {
-    if (pi && pf) return za<true, true>(d, a, nv, iv0, iv1);
-    if (pi) return za<true, false>(d, a, nv, iv0, iv1);
-    if (pf) return za<false, true>(d, a, nv, iv0, iv1);
-    return za<false, false>(d, a, nv, iv0, iv1);
   }
 
   // Backward sweep: steps nsteps..1, each step's actions in reverse order
@@ -548,59 +513,40 @@ struct Passes {
       DevView d2 = d;  // the stacked state for the y and x passes
       d2.S = 2 * S;
       cx<T>* stk = (cx<T>*)a.stacked;
-      bool zk = false, zopen = false, zpre = false;
-      int zv[2] = {0, 0}, znv = 0;
-      hipError_t e = hipSuccess;
-      auto flush = [&](bool post_fwd) -> hipError_t {
-        hipError_t r = zadj(d, a, zpre, post_fwd, znv, zv[0], zv[1]);
-        zopen = false;
-        znv = 0;
-        zk = post_fwd;
-        return r;
-      };
-      for (int64_t n = nsteps; n >= 1; --n) {
-        for (int i = d.nact - 1; i >= 0; --i) {
-          const int code = d.hprog[i];
-          const int idx = prog_idx(code);
-          if (prog_op(code) == OP_V) {
-            if (zopen && znv == 2) {
-              if ((e = flush(false)) != hipSuccess) return e;
-            }
-            if (!zopen) {
-              zopen = true;
-              zpre = zk;
-              znv = 0;
-              zk = false;
-            }
-            zv[znv++] = idx;
-          } else {
-            if (zopen) {
-              if ((e = flush(true)) != hipSuccess) return e;
-            } else if (!zk) {
-              if ((e = zadj(d, a, false, true, 0, 0, 0)) != hipSuccess) return e;
-              zk = true;
-            }
-            if ((e = ypass<false>(d2, stk)) != hipSuccess) return e;
-            if ((e = xpass<XP_PHASE>(d2, stk, idx, 1)) != hipSuccess) return e;
-            if ((e = ypass<true>(d2, stk)) != hipSuccess) return e;
+      PassMachine m;
+      std::vector<PassDesc> ps;
+      auto run = [&]() -> hipError_t {
+        for (const PassDesc& p : ps) {
+          hipError_t r;
+          switch (p.kind) {
+            case PassDesc::Z:
+              r = p.kz ? za<true>(d, a, p.nv, p.iv0, p.iv1, p.tidx)
+                       : za<false>(d, a, p.nv, p.iv0, p.iv1, 0);
+              break;
+            case PassDesc::Y: r = ypass<AX_KIN>(d2, stk, p.tidx, 1); break;
+            default: r = xpass<AX_KIN>(d2, stk, p.tidx, 1); break;
           }
+          if (r != hipSuccess) return r;
         }
+        ps.clear();
+        return hipSuccess;
+      };
+      hipError_t e = hipSuccess;
+      for (int64_t n = nsteps; n >= 1; --n) {
+        for (int i = d.nact - 1; i >= 0; --i) emit_action(m, d.hprog[i], ps, false);
         if ((n - 1) % K == 0) {
-          if (zopen) {
-            if ((e = flush(false)) != hipSuccess) return e;
-          } else if (zk) {
-            if ((e = zadj(d, a, true, false, 0, 0, 0)) != hipSuccess) return e;
-            zk = false;
-          }
+          emit_flush(m, ps);
+          if ((e = run()) != hipSuccess) return e;
           const size_t bytes = (size_t)S * d.npts * sizeof(cx<T>);
           e = hipMemcpyAsync(a.stacked, (const char*)a.checkpoints + (size_t)((n - 1) / K) * bytes,
                              bytes, hipMemcpyDeviceToDevice, d.stream);
           if (e != hipSuccess) return e;
+        } else if ((e = run()) != hipSuccess) {
+          return e;
         }
       }
-      if (zopen) return flush(false);
-      if (zk) return zadj(d, a, true, false, 0, 0, 0);
-      return hipSuccess;
+      emit_flush(m, ps);
+      return run();
     }
   }
 };

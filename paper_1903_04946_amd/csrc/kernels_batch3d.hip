@@ -4,16 +4,16 @@
 // Each member runs the pruned VTV step program V(a_1) T(b_1) ... T(b_M)
 // V(a_{M+1}) of its own plan (own order, dt, tables and step count).  Its
 // pass sequence is periodic: cycle c (c < cycles = M nsteps) is the z-pass
-// that applies the potential action(s) before kinetic action number c, then
-// the y forward, x (phase) and y inverse passes of that kinetic action; the
-// z-pass of cycle c = cycles applies the closing V(a_{M+1}) and returns z to
-// position space.  At a step boundary the z-pass applies V(a_{M+1}) of the
-// finished step and V(a_1) of the next one (Sec. "Pruning splitting
-// coefficients": the same actions the single-plan executor launches).
-// Launch c of a kind covers every member; a member derives its own pass
-// parameters from c and its program on the device, and members whose run is
-// shorter than c leave at once.  The pass bodies are those of the
-// single-plan kernels, so a member's result equals its single-plan run.
+// that applies the potential action(s) before kinetic action number c and
+// that action's z factor, then the y- and x-passes (or the plane pass) of
+// that kinetic action; the z-pass of cycle c = cycles applies the closing
+// V(a_{M+1}).  At a step boundary the z-pass applies V(a_{M+1}) of the
+// finished step and V(a_1) of the next one (the same actions the
+// single-plan executor launches).  Launch c of a kind covers every member; a
+// member derives its own pass parameters from c and its program on the
+// device, and members whose run is shorter than c leave at once.  The pass
+// bodies are those of the single-plan kernels, so a member's result equals
+// its single-plan run.
 #include "passes_3d.hpp"
 
 namespace sop {
@@ -23,8 +23,15 @@ using namespace s3d;
 
 constexpr int prog_index(int code) { return code & 0xffff; }
 
-// z-pass of cycle c; PI = the state arrives z-transformed (every c > 0).
-template <typename T, class SC, int S, int C, bool PI>
+// kinetic factor set of cycle c (c < cycles), axis a (0 z, 1 y, 2 x)
+template <typename T>
+__device__ __forceinline__ const cx<T>* cycle_kin(const BMember3& m, int64_t c, int a) {
+  const int tidx = prog_index(m.prog[2 * (int)(c % m.M) + 1]);
+  return (const cx<T>*)m.kin + ((size_t)tidx * 3 + a) * m.kin_stride;
+}
+
+// z-pass of cycle c: grid (N / C, N, members)
+template <typename T, class SC, int S, int C>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3b_zpass(const BMember3* __restrict__ mem, int64_t c) {
   extern __shared__ char smem_raw[];
@@ -32,39 +39,29 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const BMember3 m = mem[blockIdx.z];
   if (m.cycles <= 0 || c > m.cycles) return;
   const int M = m.M;
-  int nv = 1, iv0, iv1 = 0;
-  bool pf = true;
-  if (c == m.cycles) {  // closing potential action
-    iv0 = prog_index(m.prog[2 * M]);
-    pf = false;
-  } else {
-    const int i = (int)(c % M);
-    if (c > 0 && i == 0) {  // step boundary: V(a_{M+1}) then V(a_1)
-      nv = 2;
-      iv0 = prog_index(m.prog[2 * M]);
-      iv1 = prog_index(m.prog[0]);
-    } else {
-      iv0 = prog_index(m.prog[2 * i]);
-    }
-  }
   cx<T>* psi = (cx<T>*)m.psi;
   const cx<T>* vexp = (const cx<T>*)m.vexp;
   const cx<T>* tw = (const cx<T>*)m.tw;
-  if constexpr (PI) {
-    if (pf)
-      zpass_body<T, SC, S, C, kTableCols, true, true>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
-                                                      blockIdx.x, blockIdx.y);
-    else
-      zpass_body<T, SC, S, C, kTableCols, true, false>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
-                                                       blockIdx.x, blockIdx.y);
-  } else {
-    zpass_body<T, SC, S, C, kTableCols, false, true>(psi, vexp, nv, iv0, iv1, m.conj, tw, lds,
-                                                     blockIdx.x, blockIdx.y);
+  if (c == m.cycles) {  // closing potential action
+    zpass_body<T, SC, S, C, kTableCols, AX_NONE>(psi, vexp, 1, prog_index(m.prog[2 * M]), 0,
+                                                 m.conj, tw, nullptr, lds, blockIdx.x,
+                                                 blockIdx.y);
+    return;
   }
+  const int i = (int)(c % M);
+  int nv = 1, iv0 = prog_index(m.prog[2 * i]), iv1 = 0;
+  if (c > 0 && i == 0) {  // step boundary: V(a_{M+1}) then V(a_1)
+    nv = 2;
+    iv0 = prog_index(m.prog[2 * M]);
+    iv1 = prog_index(m.prog[0]);
+  }
+  zpass_body<T, SC, S, C, kTableCols, AX_KIN>(psi, vexp, nv, iv0, iv1, m.conj, tw,
+                                              cycle_kin<T>(m, c, 0), lds, blockIdx.x,
+                                              blockIdx.y);
 }
 
 // y-pass of cycle c: grid (N / C, N, S x members).
-template <typename T, class SC, int C, bool INV>
+template <typename T, class SC, int C>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3b_ypass(const BMember3* __restrict__ mem, int S, int64_t c) {
   extern __shared__ char smem_raw[];
@@ -73,11 +70,11 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const BMember3 m = mem[mi];
   if (c >= m.cycles) return;
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  ypass_body<T, SC, C, INV>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + SC::N, lds,
-                            blockIdx.x, blockIdx.y);
+  ypass_body<T, SC, C, AX_KIN>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + SC::N,
+                               cycle_kin<T>(m, c, 1), m.conj, lds, blockIdx.x, blockIdx.y);
 }
 
-// x-pass (forward, kinetic phase of action c mod M, inverse) of cycle c.
+// x-pass of cycle c: grid (N / ROWS, N, S x members).
 template <typename T, class SC, int ROWS>
 __global__ void __launch_bounds__(ROWS * SC::TPC)
     k3b_xpass(const BMember3* __restrict__ mem, int S, int64_t c) {
@@ -86,15 +83,12 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
   const int mi = blockIdx.z / S, s = blockIdx.z % S;
   const BMember3 m = mem[mi];
   if (c >= m.cycles) return;
-  const int tidx = prog_index(m.prog[2 * (int)(c % m.M) + 1]);
-  const cx<T>* kin = (const cx<T>*)m.kin + (size_t)tidx * 3 * m.kin_stride;
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  xpass_body<T, SC, ROWS, XP_PHASE>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + 2 * SC::N,
-                                    kin, m.conj, lds, blockIdx.x, blockIdx.y);
+  xpass_body<T, SC, ROWS, AX_KIN>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + 2 * SC::N,
+                                  cycle_kin<T>(m, c, 2), m.conj, lds, blockIdx.x, blockIdx.y);
 }
 
-// fused xy plane pass (y forward, x phase, y inverse) of cycle c:
-// grid (N planes, S x members).
+// fused xy plane pass of cycle c: grid (N planes, S x members).
 template <typename T, class SC>
 __global__ void __launch_bounds__(SC::N * SC::TPC)
     k3b_plane(const BMember3* __restrict__ mem, int S, int64_t c) {
@@ -103,10 +97,9 @@ __global__ void __launch_bounds__(SC::N * SC::TPC)
   const int mi = blockIdx.y / S, s = blockIdx.y % S;
   const BMember3 m = mem[mi];
   if (c >= m.cycles) return;
-  const int tidx = prog_index(m.prog[2 * (int)(c % m.M) + 1]);
-  const cx<T>* kin = (const cx<T>*)m.kin + (size_t)tidx * 3 * m.kin_stride;
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  plane_body<T, SC>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw, kin, m.conj, lds, blockIdx.x);
+  plane_body<T, SC>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw, cycle_kin<T>(m, c, 0),
+                    m.conj, lds, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- variants
@@ -139,40 +132,25 @@ template <typename T, class SC, int S, int V>
 hipError_t launch_z(const BMember3* mem, int count, int64_t c, hipStream_t st) {
   constexpr int C = zwidth(V);
   const size_t lds = (size_t)C * SC::N * sizeof(cx<T>);
-  const dim3 grid(SC::N / C, SC::N, count), block(C * SC::TPC);
-  if (c == 0) {
-    auto k = k3b_zpass<T, SC, S, C, false>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, block, lds, st, mem, c);
-  } else {
-    auto k = k3b_zpass<T, SC, S, C, true>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, block, lds, st, mem, c);
-  }
+  auto k = k3b_zpass<T, SC, S, C>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(SC::N / C, SC::N, count), dim3(C * SC::TPC), lds, st, mem, c);
   return hipGetLastError();
 }
 
 template <typename T, class SC, int V>
-hipError_t launch_y(bool inv, int S, const BMember3* mem, int count, int64_t c, hipStream_t st) {
+hipError_t launch_y(int S, const BMember3* mem, int count, int64_t c, hipStream_t st) {
   constexpr int C = ywidth<SC, T>(V);
   if constexpr (!valid_width<SC>(C)) {
     return hipErrorInvalidValue;
   } else {
     const size_t lds = (size_t)C * SC::N * sizeof(cx<T>);
-    const dim3 grid(SC::N / C, SC::N, S * count), block(C * SC::TPC);
-    if (inv) {
-      auto k = k3b_ypass<T, SC, C, true>;
-      hipError_t e = set_lds(k, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, block, lds, st, mem, S, c);
-    } else {
-      auto k = k3b_ypass<T, SC, C, false>;
-      hipError_t e = set_lds(k, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, grid, block, lds, st, mem, S, c);
-    }
+    auto k = k3b_ypass<T, SC, C>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(SC::N / C, SC::N, S * count), dim3(C * SC::TPC), lds, st, mem, S,
+                       c);
     return hipGetLastError();
   }
 }
@@ -224,15 +202,12 @@ hipError_t launch_kind(int kind, int S, int v, const BMember3* mem, int count, i
       if (v == 1) return z.template operator()<1>();
       return hipErrorInvalidValue;
     }
-    case B3_YF:
-    case B3_YI: {
-      const bool inv = kind == B3_YI;
-      if (v == 0) return launch_y<T, SC, 0>(inv, S, mem, count, c, st);
-      if (v == 1) return launch_y<T, SC, 1>(inv, S, mem, count, c, st);
-      if (v == 2) return launch_y<T, SC, 2>(inv, S, mem, count, c, st);
+    case B3_Y:
+      if (v == 0) return launch_y<T, SC, 0>(S, mem, count, c, st);
+      if (v == 1) return launch_y<T, SC, 1>(S, mem, count, c, st);
+      if (v == 2) return launch_y<T, SC, 2>(S, mem, count, c, st);
       return hipErrorInvalidValue;
-    }
-    case B3_XP:
+    case B3_X:
       if (v == 0) return launch_x<T, SC, 0>(S, mem, count, c, st);
       if (v == 1) return launch_x<T, SC, 1>(S, mem, count, c, st);
       if (v == 2) return launch_x<T, SC, 2>(S, mem, count, c, st);
@@ -258,7 +233,7 @@ int width_of(int kind, int v) {
   if (kind == B3_XY) return (v == 0 && plane_fits<T, SC>()) ? SC::N : 0;
   if (kind == B3_Z) return (v == 0 || v == 1) ? zwidth(v) : 0;
   if (v < 0 || v > 2) return 0;
-  const int w = (kind == B3_XP) ? scaled(xrows<SC>(), v) : scaled(cols<SC, T>(), v);
+  const int w = (kind == B3_X) ? scaled(xrows<SC>(), v) : scaled(cols<SC, T>(), v);
   const bool ok = w >= 1 && SC::N % w == 0 && w * SC::TPC <= 1024 && w * SC::TPC >= 32;
   return ok ? w : 0;
 }

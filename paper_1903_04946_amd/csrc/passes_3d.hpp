@@ -1,13 +1,25 @@
-// passes_3d.hpp -- pencil schedules and the bodies of the three pass kinds of
-// the 3D executor, as device functions of one workgroup tile.  The kernels
-// of a single plan (kernels_3d.hip) and of a batch of plans
-// (kernels_batch3d.hip) wrap the same bodies, so both compute identical values.
+// passes_3d.hpp -- pencil schedules and the bodies of the pass kinds of the
+// 3D executor, as device functions of one workgroup tile.  The kernels of a
+// single plan (kernels_3d.hip) and of a batch of plans (kernels_batch3d.hip)
+// wrap the same bodies, so both compute identical values.
 //
-// A substep (one potential action followed by one kinetic action, Sec.
-// "Dynamic Fourier method") is four passes over psi[s][z][y][x]:
-//   z-pass : [inverse FFT along z] -> potential unitary(ies) -> [forward FFT z]
-//   y-pass : forward (or inverse) FFT along y;
-//   x-pass : forward FFT along x -> kinetic phase -> inverse FFT along x.
+// The kinetic propagator of a separable T(p) = sum_d p_d^2 / (2 m_d) factors
+// over the axes: exp(-i tau T / hbar) = K_z K_y K_x with the commuting
+// one-dimensional actions K_d = F_d^-1 diag(f_d) F_d along axis d (Sec.
+// "Dynamic Fourier method": the kinetic action is diagonal in the momentum
+// representation, and both it and the FFT factor over the axes).  A substep
+// (one potential action followed by one kinetic action) is therefore three
+// passes over psi[s][z][y][x], each taking the state from and back to the
+// position representation:
+//   z-pass : potential unitary(ies) -> forward FFT z -> f_z -> inverse FFT z
+//            (all S surfaces of a tile of x-columns: the S x S matvec of
+//            Sec. "Molecular Hamiltonian in the diabatic basis" runs in
+//            registers);
+//   y-pass : forward FFT y -> f_y -> inverse FFT y;
+//   x-pass : forward FFT x -> f_x -> inverse FFT x.
+// Where the whole xy plane fits in LDS the y- and x-passes run as one plane
+// pass.  The per-axis factor f_d(k) = exp(-i tau hbar kappa_k^2 / (2 m_d)) / n_d
+// carries the 1/n_d of the unnormalised inverse transform.
 #pragma once
 
 #include "fft_core.hpp"
@@ -59,17 +71,40 @@ constexpr int kTableCols = 16;
 
 }  // namespace s3d
 
+// What a pass does along its axis after its pointwise work:
+//   AX_NONE: nothing (z-pass carrying only potential actions);
+//   AX_KIN : forward FFT -> per-axis kinetic factor -> inverse FFT;
+//   AX_FWD : forward FFT only, output in the momentum representation (the
+//            observables' transform).
+enum { AX_NONE = 0, AX_KIN = 1, AX_FWD = 2 };
+
+// v (forward-transformed, radix-RL ownership) *= f[k] (conjugated factor
+// when conj): the kinetic factor of one axis.
+template <typename T, class SC, int P>
+__device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __restrict__ f,
+                                           T csign, int t) {
+#pragma unroll
+  for (int q = 0; q < SC::E; ++q) {
+    cx<T> w = f[own_idx<SC::N, SC::E, SC::RL>(t, q)];
+    w.im *= csign;
+#pragma unroll
+    for (int p = 0; p < P; ++p) v[p][q] = cmul(v[p][q], w);
+  }
+}
+
 // ---------------------------------------------------------------- z-pass
 // Potential tables are stored per tile of TC x-columns: for table u, tile
 // (y, x / TC) holds [z][entry][x % TC] contiguously, N * NE * TC complex, so
 // a tile reads its table as one contiguous stream.  The pass tile is C
 // columns wide (C divides TC); block (bx, by) owns columns bx*C .. bx*C+C-1
-// of row y = by.  `psi` is one state [S][N^3].
-template <typename T, class SC, int S, int C, int TC, bool PRE_INV, bool POST_FWD>
+// of row y = by.  `psi` is one state [S][N^3]; `fz` the z factor of the
+// kinetic set (AX_KIN only).
+template <typename T, class SC, int S, int C, int TC, int AX>
 __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
                                            const cx<T>* __restrict__ vexp, int nv, int iv0,
                                            int iv1, int conj, const cx<T>* __restrict__ tw,
-                                           cx<T>* lds, int bx, int by) {
+                                           const cx<T>* __restrict__ fz, cx<T>* lds, int bx,
+                                           int by) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
   const int lane = threadIdx.x;
@@ -84,22 +119,11 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
   const size_t tbase = ((size_t)y * (N / TC) + tx) * tile;
   const LayStrided lay{col, 0, C};  // one surface at a time through LDS
   cx<T> v[S][E];
-  constexpr int RIN = PRE_INV ? SC::RL : SC::RF;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, RIN>(t, q) * plane + off0);
-  }
-  if constexpr (PRE_INV) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
-    // normalisation of the z round trip (exact for power-of-two N)
-    constexpr T inv_n = (T)1 / (T)N;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int q = 0; q < E; ++q) v[s][q] = cx<T>{v[s][q].re * inv_n, v[s][q].im * inv_n};
+    for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0);
   }
   const T csign = conj ? (T)-1 : (T)1;
   auto vact = [&](int iv) {
@@ -123,11 +147,16 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
   };
   if (nv >= 1) vact(iv0);
   if (nv >= 2) vact(iv1);
-  if constexpr (POST_FWD) {
+  if constexpr (AX != AX_NONE) {
 #pragma unroll
     for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);
   }
-  constexpr int ROUT = POST_FWD ? SC::RL : SC::RF;
+  if constexpr (AX == AX_KIN) {
+    axis_phase<T, SC, S>(v, fz, csign, t);
+#pragma unroll
+    for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, t);
+  }
+  constexpr int ROUT = AX == AX_FWD ? SC::RL : SC::RF;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
@@ -138,11 +167,12 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
 
 // ---------------------------------------------------------------- y-pass
 // One surface `psi_s` [N^3]; block (bx, z) owns columns bx*C .. bx*C+C-1 of
-// plane z.
-template <typename T, class SC, int C, bool INV>
+// plane z.  AX = AX_KIN (factor fy) or AX_FWD.
+template <typename T, class SC, int C, int AX>
 __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
-                                           const cx<T>* __restrict__ tw, cx<T>* lds, int bx,
-                                           int z) {
+                                           const cx<T>* __restrict__ tw,
+                                           const cx<T>* __restrict__ fy, int conj, cx<T>* lds,
+                                           int bx, int z) {
   constexpr int N = SC::N, E = SC::E;
   const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
@@ -151,28 +181,25 @@ __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
   const LayStrided lay{col, 0, C};
   cx<T> v[1][E];
-  constexpr int RIN = INV ? SC::RL : SC::RF;
-  constexpr int ROUT = INV ? SC::RF : SC::RL;
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) * N + x);
-  if constexpr (INV)
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) * N + x);
+  fft_forward<SC, 1>(v, lds, lay, tw, t);
+  if constexpr (AX == AX_KIN) {
+    axis_phase<T, SC, 1>(v, fy, conj ? (T)-1 : (T)1, t);
     fft_inverse<SC, 1>(v, lds, lay, tw, t);
-  else
-    fft_forward<SC, 1>(v, lds, lay, tw, t);
+  }
+  constexpr int ROUT = AX == AX_FWD ? SC::RL : SC::RF;
 #pragma unroll
   for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) * N + x, v[0][q]);
 }
 
 // ---------------------------------------------------------------- x-pass
-enum { XP_PHASE = 0, XP_FWD = 1, XP_INV = 2 };
-
 // One surface `psi_s`; block (bx, z) owns rows bx*ROWS .. bx*ROWS+ROWS-1 of
-// plane z.  `kin` = the three per-axis factors [f_z | f_y | f_x] of one
-// kinetic coefficient (XP_PHASE only).
-template <typename T, class SC, int ROWS, int MODE>
+// plane z.  AX = AX_KIN (factor fx) or AX_FWD.
+template <typename T, class SC, int ROWS, int AX>
 __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
-                                           const cx<T>* __restrict__ kin, int conj, cx<T>* lds,
+                                           const cx<T>* __restrict__ fx, int conj, cx<T>* lds,
                                            int bx, int z) {
   constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
   const int lane = threadIdx.x;
@@ -183,39 +210,26 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
   const uint32_t yo = (uint32_t)y * N;
   const LayPadded lay{row * (N + N / 16), 0};
   cx<T> v[1][E];
-  constexpr int RIN = MODE == XP_INV ? SC::RL : SC::RF;
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, RIN>(t, q) + yo);
-  if constexpr (MODE == XP_INV) {
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
-  } else {
-    fft_forward<SC, 1>(v, lds, lay, tw, t);
-  }
-  if constexpr (MODE == XP_PHASE) {
-    const T csign = conj ? (T)-1 : (T)1;
-    cx<T> fzy = cmul(kin[z], kin[N + y]);
-    fzy.im *= csign;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(t, q)];
-      fx.im *= csign;
-      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
-    }
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) + yo);
+  fft_forward<SC, 1>(v, lds, lay, tw, t);
+  if constexpr (AX == AX_KIN) {
+    axis_phase<T, SC, 1>(v, fx, conj ? (T)-1 : (T)1, t);
     fft_inverse<SC, 1>(v, lds, lay, tw, t);
   }
-  constexpr int ROUT = MODE == XP_FWD ? SC::RL : SC::RF;
+  constexpr int ROUT = AX == AX_FWD ? SC::RL : SC::RF;
 #pragma unroll
   for (int q = 0; q < E; ++q) st(base, own_idx<N, E, ROUT>(t, q) + yo, v[0][q]);
 }
 
 // ---------------------------------------------------------------- xy plane
-// The y-forward, x (forward, kinetic phase, inverse) and y-inverse passes of
-// one kinetic action fused for grids whose whole xy plane fits in LDS: block
-// = one plane z of one surface, N x TPC threads.  Column layout (lane ->
-// x = lane % N, t = lane / N) for the y transforms, row layout (lane ->
-// t = lane % TPC, y = lane / TPC) for the x transforms, LDS transposes in
-// between.  Every pencil sees the same stages, twiddles and phase products
-// as in the three separate passes, so the values are identical.
+// The y- and x-passes of one kinetic action fused for grids whose whole xy
+// plane fits in LDS: block = one plane z of one surface, N x TPC threads.
+// The y round trip runs in the column layout (lane -> x = lane % N,
+// t = lane / N), one LDS transpose moves the plane to the row layout
+// (lane -> t = lane % TPC, y = lane / TPC), where the x round trip runs and
+// the rows are stored.  Every pencil sees the same stages, twiddles and
+// factors as in the separate passes, so the values are identical.
 template <typename T, class SC>
 constexpr size_t plane_lds_elems() {
   return (size_t)SC::N * (SC::N + SC::N / 16);
@@ -225,6 +239,7 @@ constexpr bool plane_fits() {
   return plane_lds_elems<T, SC>() * sizeof(cx<T>) <= 160 * 1024 && SC::N * SC::TPC <= 1024;
 }
 
+// `kin` = the three per-axis factors [f_z | f_y | f_x] of one kinetic set.
 template <typename T, class SC>
 __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
@@ -241,43 +256,27 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   const cx<T>* twx = tw + 2 * N;
   const LayStrided lcol{col, 0, N};
   const LayPadded lrow{row * P, 0};
+  const T csign = conj ? (T)-1 : (T)1;
   cx<T> v[1][E];
-  // y forward (columns)
+  // y round trip (columns)
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(tc, q) * N + col);
   fft_forward<SC, 1>(v, lds, lcol, twy, tc);
+  axis_phase<T, SC, 1>(v, kin + N, csign, tc);
+  fft_inverse<SC, 1>(v, lds, lcol, twy, tc);
   // columns -> rows
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[own_idx<N, E, SC::RL>(tc, q) * P + col] = v[0][q];
+  for (int q = 0; q < E; ++q) lds[own_idx<N, E, SC::RF>(tc, q) * P + col] = v[0][q];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = lds[row * P + own_idx<N, E, SC::RF>(tr, q)];
   __syncthreads();
-  // x forward, phase, x inverse (rows; row index = k_y, plane index = k_z)
+  // x round trip (rows)
   fft_forward<SC, 1>(v, lds, lrow, twx, tr);
-  {
-    const T csign = conj ? (T)-1 : (T)1;
-    cx<T> fzy = cmul(kin[z], kin[N + row]);
-    fzy.im *= csign;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      cx<T> fx = kin[2 * N + own_idx<N, E, SC::RL>(tr, q)];
-      fx.im *= csign;
-      v[0][q] = cmul(v[0][q], cmul(fzy, fx));
-    }
-  }
+  axis_phase<T, SC, 1>(v, kin + 2 * N, csign, tr);
   fft_inverse<SC, 1>(v, lds, lrow, twx, tr);
-  // rows -> columns
 #pragma unroll
-  for (int q = 0; q < E; ++q) lds[row * P + own_idx<N, E, SC::RF>(tr, q)] = v[0][q];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = lds[own_idx<N, E, SC::RL>(tc, q) * P + col];
-  __syncthreads();
-  // y inverse (columns)
-  fft_inverse<SC, 1>(v, lds, lcol, twy, tc);
-#pragma unroll
-  for (int q = 0; q < E; ++q) st(base, own_idx<N, E, SC::RF>(tc, q) * N + col, v[0][q]);
+  for (int q = 0; q < E; ++q) st(base, row * N + own_idx<N, E, SC::RF>(tr, q), v[0][q]);
 }
 
 }  // namespace sop

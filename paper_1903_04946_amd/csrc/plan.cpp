@@ -222,10 +222,8 @@ void free_plan(sop_plan* p) {
 }
 
 // Kinetic factors of one coefficient set: [ntau][ndim or 3][n] complex,
-// f_d(k) = exp(-i tau hbar kappa_k^2 inv_mass_d / 2) / n_d.  On 3D grids
-// the z axis carries no 1/n_z: the z transforms are not paired with each
-// kinetic action (two adjacent kinetic actions share one z round trip), so
-// the z-pass applies 1/n_z after each inverse z transform instead.
+// f_d(k) = exp(-i tau hbar kappa_k^2 inv_mass_d / 2) / n_d; every axis
+// carries the 1/n_d of its own unnormalised inverse transform.
 std::vector<ld> kinetic_factors(const sop_plan* p, const std::vector<double>& taus) {
   const int nax = p->ndim == 1 ? 1 : 3;
   const int nn = p->n[0];
@@ -237,7 +235,7 @@ std::vector<ld> kinetic_factors(const sop_plan* p, const std::vector<double>& ta
         const ld kap = kTwoPi * (ld)kk / ((ld)p->n[a] * (ld)p->dx[a]);
         const ld ph = -(ld)taus[u] * (ld)p->hbar * kap * kap * (ld)p->inv_mass[a] / 2.0L;
         const size_t o = (((size_t)u * nax + a) * nn + k) * 2;
-        const ld scale = (nax == 3 && a == 0) ? 1.0L : 1.0L / (ld)p->n[a];
+        const ld scale = 1.0L / (ld)p->n[a];
         out[o] = std::cos(ph) * scale;
         out[o + 1] = std::sin(ph) * scale;
       }
