@@ -16,10 +16,12 @@ before timing starts.
 
 One JSON line is printed.  Besides the contract fields it carries
   roofline     -- the dominant kernel's algorithmic bytes per launch over its
-                  average launch duration (HIP events on the plan's stream,
-                  inside this run), against the 8 TB/s HBM peak; `traffic` is
-                  filled from a committed rocprofv3 counter summary when its
-                  kernel source hash matches, else null;
+                  average launch duration (its share, from HIP events on the
+                  plan's stream around every launch of a second run of the
+                  same K steps, of the HIP-event-timed region), against the
+                  8 TB/s HBM peak; `traffic` is filled from a committed
+                  rocprofv3 counter summary when its kernel source hash
+                  matches, else null;
   cpu_baseline -- the FP64 CPU oracle timed on this host on a bounded sample
                   of the same workload (its step loop only).
 """
@@ -39,6 +41,7 @@ if ROOT not in sys.path:
 METRIC = ("grid-pt·surface substeps/s; time-to-error 1e-10 (FP64)/1e-5 (FP32) vs Strang")
 UNIT = "grid-pt·surface substeps/s"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
 
 WORKLOADS = {
     # name: (ndim, n, comp, order, dt, dtype)
@@ -54,7 +57,9 @@ DEFAULT = "lvc3d_128cube_x3_tj6_vtv_c128"
 # batched ensembles: 256 members of uneven grids, orders, dt and step counts
 ENSEMBLES = {"ensemble256_mixed_c128": "c128", "ensemble256_mixed_c64": "c64"}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
+                  "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
+                  "paper_1903_04946_amd/csrc/body_1d.hpp",
                   "paper_1903_04946_amd/csrc/fft_core.hpp"]
 
 
@@ -109,6 +114,25 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
     return {"value": units / sec, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"{steps} step(s) x {substeps_per_step} substeps of the same workload, "
                       f"FP64 oracle step loop ({sec:.2f} s, plan-time eigendecomposition excluded)"}
+
+
+def stream_copy_gbps(torch, nbytes=1 << 30, reps=5):
+    """Context for the roofline: read + write bandwidth of a plain 1 GiB
+    elementwise device copy (torch's vectorized kernel), best of reps."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(src, 1.0, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2.0 * nbytes / (best / 1e3) / 1e9
 
 
 # ---------------------------------------------------------------- time to error
@@ -486,16 +510,26 @@ def main(argv=None) -> int:
     plan.set_timing(False)
     norm = plan.observables(psi)["norm"]
 
+    # The HIP events of the timing run tile its wall time (consecutive
+    # launches share their boundary event), but each interval also carries
+    # one event record and one eager dispatch.  Each kernel's average launch
+    # time is its event share of that run applied to the graph-launched
+    # timed region above (same launches, no events in between).
+    ev_total = sum(v["ms"] for v in kt.values())
+    scale = ms / ev_total if ev_total > 0 else 1.0
     dom = max(kt, key=lambda k: kt[k]["ms"])
     d = kt[dom]
-    avg_ms = d["ms"] / d["count"]
+    avg_ms = scale * d["ms"] / d["count"]
     bytes_per_launch = d["bytes"] / d["count"]
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = traffic_from_profiles(a.workload, dom)
-    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * v["ms"] / v["count"],
-                   "share": v["ms"] / sum(x["ms"] for x in kt.values()),
-                   "alg_GBps": v["bytes"] / (v["ms"] / 1e3) / 1e9} for k, v in kt.items()}
+    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * scale * v["ms"] / v["count"],
+                   "event_avg_us": 1e3 * v["ms"] / v["count"],
+                   "share": v["ms"] / ev_total,
+                   "alg_GBps": v["bytes"] / (scale * v["ms"] / 1e3) / 1e9}
+               for k, v in kt.items()}
 
+    copy_gbps = stream_copy_gbps(torch) if ndim == 3 else None
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(model, comp, order, dt, M)
@@ -522,7 +556,8 @@ def main(argv=None) -> int:
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic,
-                     "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch,
+                     "stream_copy_GBps": copy_gbps},
         "kernels": kernels,
         "cpu_baseline": cpu,
         "time_to_error": tte,
@@ -530,8 +565,19 @@ def main(argv=None) -> int:
         "kernel_source_hash": kernel_source_hash(),
     }
     if ndim == 1:
-        # on-chip workload: report against the FP64 vector peak instead
-        out["roofline"].update({"bound": "alu", "unit": "GB/s (on-chip, informational)"})
+        # On-chip workload (one workgroup per state, psi in registers): the
+        # bound is arithmetic.  Algorithmic flops per unit: two transforms
+        # at 5 log2(N) each (radix-2 count), the S x S complex matvec (8 S
+        # per unit) and the phase (6).  Peak: FP64 vector, 256 CUs x 128
+        # flop/clk x 2.4 GHz = 78.6 TFLOP/s; one workgroup runs on one CU.
+        import math
+        fpu = 10.0 * math.log2(n) + 8.0 * model.nsurf + 6.0
+        peak = FP64_VECTOR_TFLOPS * (1.0 if dts == "c128" else 2.0)
+        tflops = fpu * units_per_step * a.steps / (ms / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": peak,
+                           "unit": "TFLOP/s", "frac": tflops / peak, "traffic": None,
+                           "flops_per_unit": fpu, "one_cu_frac": tflops / (peak / 256.0),
+                           "avg_launch_us": avg_ms * 1e3}
     print(json.dumps(out))
     return 0
 

@@ -230,17 +230,18 @@ sop_status sop_adjoint_backward(sop_plan* plan, int64_t nsteps, int K, const dou
 /* Plan options.  SOP_OPT_GRAPHS (default 1): on 3D grids, runs of 4 or more
  * steps launch the first step, the steady step (replayed) and the final
  * pass as HIP graphs captured once per state pointer, direction and count;
- * 0 launches every pass eagerly.  SOP_OPT_PLANE_PASS (default 1): on 3D
- * grids whose xy plane fits in LDS (n <= 64 in FP64, n <= 128 in FP32) the
- * y-forward, x (phase) and y-inverse passes of a kinetic action run as one
- * plane pass; 0 keeps three passes.  Every setting gives bitwise identical
- * results. */
+ * 0 launches every pass eagerly.  SOP_OPT_PLANE_PASS: on 3D grids whose xy
+ * plane fits in LDS (n <= 64 in FP64, n <= 128 in FP32) the y- and x-passes
+ * of a kinetic action run as one plane pass; default 1 for n <= 64, 0 for
+ * larger grids.  Every setting gives bitwise identical results. */
 enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2 };
 sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
 /* Per-kernel timing (measurement aid).  While enabled, every kernel launch
- * of the plan is bracketed by HIP events on the plan's stream.
- * sop_timing_read synchronises the stream and returns, per kernel kind
+ * of the plan is bracketed by HIP events on the plan's stream, and
+ * consecutive launches within one call share their boundary event (so the
+ * intervals of a propagate call tile its wall time).  Graph capture is off
+ * while timing is on.  sop_timing_read synchronises the stream and returns, per kernel kind
  * (SOP_KIND_*), the summed event time in ms, the launch count and the summed
  * algorithmic bytes (state read + written, tables read), then clears the
  * records.  ms, counts, bytes: host arrays of SOP_KIND_COUNT entries. */
@@ -282,8 +283,8 @@ sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* 
  * Runs longer than 200000 kernel launches are enqueued without a graph.
  *
  * sop_batch_set_option(SOP_OPT_GRAPHS, 0) enqueues the branches directly;
- * SOP_OPT_PLANE_PASS 0 keeps three y/x/y passes in the lockstep groups (same
- * results either way).
+ * SOP_OPT_PLANE_PASS 0 keeps separate y- and x-passes in the lockstep groups
+ * (same results either way).
  *
  * sop_batch_describe writes a NUL-terminated JSON description (families,
  * groups, chosen variants, tuning times in ms, branch count, whether the

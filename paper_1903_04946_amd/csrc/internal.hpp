@@ -25,7 +25,10 @@ enum { KIND_ZPASS = 0, KIND_YPASS = 1, KIND_XPASS = 2, KIND_1D = 3, KIND_OTHER =
        KIND_COUNT = 6 };
 
 // Optional per-launch timing: HIP events recorded on the plan's stream
-// around every kernel launch, resolved after a synchronisation.
+// between kernel launches, resolved after a synchronisation.  Consecutive
+// timed launches share their boundary event (one event record per launch,
+// not two), so the intervals of a run of launches tile its wall time; any
+// untimed work on the stream must break the chain first.
 struct Timer {
   struct Rec {
     int kind;
@@ -35,6 +38,9 @@ struct Timer {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
+  hipEvent_t last = nullptr;  // end event of the previous timed launch
+  hipStream_t last_stream = nullptr;
+  void break_chain() { last = nullptr; }
   hipEvent_t get() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -118,13 +124,27 @@ struct TimedLaunch {
     if (on) {
       rec.kind = kind;
       rec.bytes = bytes;
-      rec.a = d.timer->get();
-      rec.b = d.timer->get();
-      if (!rec.a || !rec.b || hipEventRecord(rec.a, d.stream) != hipSuccess) on = false;
+      Timer& t = *d.timer;
+      if (t.last && t.last_stream == d.stream) {
+        rec.a = t.last;
+      } else {
+        rec.a = t.get();
+        if (!rec.a || hipEventRecord(rec.a, d.stream) != hipSuccess) on = false;
+      }
+      rec.b = on ? t.get() : nullptr;
+      if (!rec.b) on = false;
+      if (!on) t.break_chain();
     }
   }
   ~TimedLaunch() {
-    if (on && hipEventRecord(rec.b, d.stream) == hipSuccess) d.timer->recs.push_back(rec);
+    if (!on) return;
+    if (hipEventRecord(rec.b, d.stream) == hipSuccess) {
+      d.timer->recs.push_back(rec);
+      d.timer->last = rec.b;
+      d.timer->last_stream = d.stream;
+    } else {
+      d.timer->break_chain();
+    }
   }
 };
 

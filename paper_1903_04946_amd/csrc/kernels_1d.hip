@@ -120,12 +120,14 @@ bool k1d_supported(int n, int S) {
 }
 
 hipError_t k1d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj, int count) {
+  if (d.timer) d.timer->break_chain();  // untimed work may precede this call
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
     return launch_prop<T, SC, S>(d, psi, nsteps, conj, count);
   });
 }
 
 hipError_t k1d_fft_forward(const DevView& d, void* psi) {
+  if (d.timer) d.timer->break_chain();  // untimed work may precede this call
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
     return launch_fft<T, SC, S>(d, psi);
   });

@@ -541,6 +541,7 @@ struct Passes {
           e = hipMemcpyAsync(a.stacked, (const char*)a.checkpoints + (size_t)((n - 1) / K) * bytes,
                              bytes, hipMemcpyDeviceToDevice, d.stream);
           if (e != hipSuccess) return e;
+          if (d.timer) d.timer->break_chain();
         } else if ((e = run()) != hipSuccess) {
           return e;
         }
@@ -599,6 +600,7 @@ bool k3d_supported(int n, int S) {
 }
 
 hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) {
+  if (d.timer) d.timer->break_chain();  // untimed work may precede this call
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
     return Passes<T, SC, S>::propagate(d, psi, nsteps, conj);
   });
@@ -609,6 +611,7 @@ bool k3d_adjoint_supported(int n, int S, bool f64) {
 }
 
 hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps, int K) {
+  if (d.timer) d.timer->break_chain();  // untimed work may precede this call
   if (!k3d_adjoint_supported(d.n[0], d.S, d.f64)) return hipErrorInvalidValue;
   switch (d.n[0]) {
     case 32:
@@ -636,6 +639,7 @@ hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t 
 }
 
 hipError_t k3d_fft_forward(const DevView& d, void* psi) {
+  if (d.timer) d.timer->break_chain();  // untimed work may precede this call
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() {
     return Passes<T, SC, S>::fft_forward(d, psi);
   });

@@ -442,6 +442,10 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   d.prog = p->d_prog;
   d.nact = (int)prog.size();
   d.hprog = prog;
+  // the plane pass has one workgroup per plane and surface: it wins on small
+  // grids, where the separate passes cannot fill the chip either, and loses
+  // to them on 128^3 (one 139 KB workgroup per compute unit)
+  d.plane = p->ndim == 3 && p->n[0] <= 64;
 
   p->tile = p->ndim == 3 ? sop::k3d_table_tile(p->n[0], f64) : 0;
   HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));

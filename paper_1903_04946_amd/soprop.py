@@ -320,7 +320,8 @@ class Plan:
         _check(lib().sop_plan_set_option(self._h, 1, int(bool(enable))), "sop_plan_set_option")
 
     def set_plane_pass(self, enable: bool):
-        """Fused xy plane pass on 3D grids whose plane fits in LDS (default on)."""
+        """Fused xy plane pass on 3D grids whose plane fits in LDS (default on
+        for n <= 64)."""
         _check(lib().sop_plan_set_option(self._h, 2, int(bool(enable))), "sop_plan_set_option")
 
     def set_timing(self, enable: bool):
