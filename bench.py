@@ -34,6 +34,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -56,6 +58,9 @@ WORKLOADS = {
 DEFAULT = "lvc3d_128cube_x3_tj6_vtv_c128"
 # batched ensembles: 256 members of uneven grids, orders, dt and step counts
 ENSEMBLES = {"ensemble256_mixed_c128": "c128", "ensemble256_mixed_c64": "c64"}
+# adjoint gradients of the final surface-3 population w.r.t. the three
+# coupling constants (LVC with theta = (0.05, 0.05, 0.2) eV), TJ-6, dt = 10
+ADJOINTS = {"adjoint_lvc3d_128cube_x3_tj6_c128": 128, "adjoint_lvc3d_256cube_x3_tj6_c128": 256}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
@@ -366,6 +371,92 @@ def ensemble_cpu_baseline(models, man, Ms, budget_s=10.0):
                       f"({sec:.2f} s of FP64 oracle step loops)"}
 
 
+def run_adjoint(a, torch, soprop):
+    """Forward sweep (checkpoints every K steps) and backward sweep of the
+    adjoint for d P_3(T) / d theta over `--steps` time steps (default 500 for
+    these workloads); the value is the backward sweep's rate in the metric's
+    unit (it applies every action of the forward run to psi and lambda)."""
+    from paper_1903_04946_amd import synth
+    n = ADJOINTS[a.workload]
+    m = synth.lvc_3d(n=n, dv_params=True)
+    theta0 = np.array([c[3] for c in m.meta["couplings"]])
+    v0 = synth.lvc_vtable_theta(m, np.zeros(3))
+    plan = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, comp="triple_jump", order=6,
+                       dt=10.0, dvtables=m.dvtables)
+    plan.set_params(theta0)
+    M = plan.info.M
+    nsteps = a.steps
+    K = max(1, nsteps // 10)
+    psi0 = torch.from_numpy(m.psi0).cuda()
+    w = [0.0, 0.0, 1.0]
+    # warm-up: a short forward/backward pair (kernels loaded, graphs built)
+    wsw = plan.adjoint_workspace(2, 1)
+    plan.adjoint_forward(psi0, 2, 1, wsw)
+    plan.adjoint_backward(2, 1, w, wsw)
+    del wsw
+    ws = plan.adjoint_workspace(nsteps, K)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    pops = plan.adjoint_forward(psi0, nsteps, K, ws)
+    ev[1].record(stream)
+    grad = plan.adjoint_backward(nsteps, K, w, ws)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    units = m.nsurf * m.npts * M * nsteps
+    # per-kernel split of a second backward sweep (HIP events on the plan's
+    # stream), scaled to the timed sweep as in the propagation workloads
+    plan.adjoint_forward(psi0, nsteps, K, ws)
+    plan.set_timing(True)
+    plan.adjoint_backward(nsteps, K, w, ws)
+    kt = plan.timing_read()
+    plan.set_timing(False)
+    ev_total = sum(v["ms"] for v in kt.values())
+    scale = bwd_ms / ev_total if ev_total > 0 else 1.0
+    kernels = {{"other": "zpass_adjoint"}.get(k, k):
+               {"launches": v["count"], "avg_us": 1e3 * scale * v["ms"] / v["count"],
+                "alg_GBps": v["bytes"] / (scale * v["ms"] / 1e3) / 1e9} for k, v in kt.items()}
+    dom = max(kt, key=lambda k: kt[k]["ms"])
+    d = kt[dom]
+    avg_ms = scale * d["ms"] / d["count"]
+    achieved = (d["bytes"] / d["count"]) / (avg_ms / 1e3) / 1e9
+    fd = None
+    if a.fd_check:
+        h = 1e-5
+        fdv = np.zeros(3)
+        for k in range(3):
+            vals = []
+            for sgn in (1, -1):
+                th = theta0.copy()
+                th[k] += sgn * h
+                plan.set_params(th)
+                vals.append(plan.adjoint_forward(psi0, nsteps, K, ws)[2])
+            fdv[k] = (vals[0] - vals[1]) / (2 * h)
+        plan.set_params(theta0)
+        fd = {"h_eV": h, "fd": fdv.tolist(),
+              "max_abs_diff": float(np.max(np.abs(fdv - grad))),
+              "max_rel_diff": float(np.max(np.abs(fdv - grad)) / max(1e-300, np.max(np.abs(fdv))))}
+    return {
+        "metric": METRIC, "value": units / (bwd_ms / 1e3), "unit": UNIT, "n_gpus": 1,
+        "steps": nsteps, "warmup": 1, "ms_per_step": bwd_ms / nsteps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "grid": [n] * 3, "nsurf": 3, "composition": "triple_jump",
+                   "order": 6, "substeps_per_step": M, "dt": 10.0, "nsteps": nsteps,
+                   "checkpoint_every": K, "theta_eV": theta0.tolist(), "loss": "P_3(T)"},
+        "roofline": {"bound": "hbm", "kernel": {"other": "zpass_adjoint"}.get(dom, dom),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": d["bytes"] / d["count"]},
+        "kernels": kernels,
+        "adjoint": {"forward_ms": fwd_ms, "backward_ms": bwd_ms, "pops": pops.tolist(),
+                    "grad_P3": grad.tolist(), "fd_check": fd,
+                    "workspace_bytes": int(ws.numel())},
+        "cpu_baseline": None,
+    }
+
+
 def run_ensemble(a, torch, soprop):
     """One step = one batch propagate call advancing all 256 members of the
     ensemble to t_final (uneven step counts), as one graph launch."""
@@ -400,7 +491,9 @@ def run_ensemble(a, torch, soprop):
                                     for i in idx)}
         sub.close()
     # algorithmic HBM bytes of the 3D lockstep passes: every pass reads and
-    # writes the state; each potential action reads one table
+    # writes the state (a z-pass and a plane pass per cycle, or a z-, y- and
+    # x-pass, plus the closing z-pass); each potential action reads one table
+    plane = {g["n"]: g.get("plane", False) for g in desc["groups"]}
     b3 = 0.0
     for i, e in enumerate(man):
         if e["kind"] != "3d":
@@ -408,7 +501,8 @@ def run_ensemble(a, torch, soprop):
         m = models[i]
         ne = m.nsurf * (m.nsurf + 1) // 2
         cyc = Ms[i] * ns[i]
-        b3 += ((4 * cyc + 1) * 2 * m.nsurf + (Ms[i] + 1) * ns[i] * ne) * m.npts * cs
+        per = 2 if plane.get(e["n"], False) else 3
+        b3 += ((per * cyc + 1) * 2 * m.nsurf + (Ms[i] + 1) * ns[i] * ne) * m.npts * cs
     ach3 = b3 / (parts["3d"]["ms"] / 1e3) / 1e9
     norms = [p.observables(x)["norm"] for p, x in zip(plans, psis)]
     cpu = None if a.no_cpu_baseline else ensemble_cpu_baseline(models, man, Ms)
@@ -447,7 +541,10 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(ENSEMBLES))
+    ap.add_argument("--workload", default=DEFAULT,
+                    choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS))
+    ap.add_argument("--fd-check", action="store_true",
+                    help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-to-error", action="store_true",
                     help="also run the time-to-error sweeps (about two minutes)")
@@ -474,6 +571,9 @@ def main(argv=None) -> int:
         del src, dst
     if a.workload in ENSEMBLES:
         print(json.dumps(run_ensemble(a, torch, soprop)))
+        return 0
+    if a.workload in ADJOINTS:
+        print(json.dumps(run_adjoint(a, torch, soprop)))
         return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64

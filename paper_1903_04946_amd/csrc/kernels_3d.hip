@@ -47,10 +47,12 @@ struct AdjSched<Z256> {
   using type = Sched<256, 4, RList<4, 4, 4, 4>, RList<4, 4, 4, 4>, 4, 4>;
 };
 
-// Columns per tile of the z-pass: the table tile width.
+// Columns per tile of the z-pass: the table tile width, or half of it on
+// 64^3, where 16-column tiles give one workgroup per compute unit (smaller
+// grids keep 16 columns: half a tile would be half a wave).
 template <class SC, typename T>
 constexpr int zcols() {
-  return kTableCols;
+  return (SC::N == 64 && SC::TPC * kTableCols / 2 >= 64) ? kTableCols / 2 : kTableCols;
 }
 
 // ---------------------------------------------------------------- z-pass
@@ -62,8 +64,8 @@ __global__ void __launch_bounds__(C * SC::TPC)
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   psi += (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member of a batch
-  zpass_body<T, SC, S, C, C, AX>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds, blockIdx.x,
-                                 blockIdx.y);
+  zpass_body<T, SC, S, C, kTableCols, AX>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds,
+                                          blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- adjoint z-pass
@@ -485,8 +487,9 @@ struct Passes {
   static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1,
                        int tidx) {
     using SA = typename AdjSched<SC>::type;
-    auto k = k3d_zpass_adj<SA, S, CZ, KZ>;
-    const size_t lds = (size_t)CZ * N * sizeof(cx<double>);
+    constexpr int CA = kTableCols;  // the adjoint pass reads whole table tiles
+    auto k = k3d_zpass_adj<SA, S, CA, KZ>;
+    const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     // psi, lambda read + written; per action a table, the eigen table and the
@@ -494,7 +497,7 @@ struct Passes {
     const double bytes = (4.0 * S + nv * (2.0 * S * (S + 1) / 2.0 + S * (S + 1))) *
                          (double)d.npts * sizeof(cx<double>) / 1.0;
     TimedLaunch tl(d, KIND_OTHER, bytes);
-    hipLaunchKernelGGL(k, dim3(N / CZ, N), dim3(CZ * SA::TPC), lds, d.stream,
+    hipLaunchKernelGGL(k, dim3(N / CA, N), dim3(CA * SA::TPC), lds, d.stream,
                        (cx<double>*)a.stacked, (const cx<double>*)d.vexp,
                        (const cx<double>*)a.eig, a.qacc, a.taus, nv, iv0, iv1,
                        (const cx<double>*)d.tw[0],
@@ -582,7 +585,8 @@ hipError_t dispatch(int n, int S, bool f64, F&& f) {
 
 int k3d_table_tile(int n, bool f64) {
   (void)n;
-  return f64 ? zcols<Z128, double>() : zcols<Z128, float>();
+  (void)f64;
+  return kTableCols;
 }
 
 bool k3d_plane(int n, bool f64) {
