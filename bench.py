@@ -438,6 +438,7 @@ def run_adjoint(a, torch, soprop):
         fd = {"h_eV": h, "fd": fdv.tolist(),
               "max_abs_diff": float(np.max(np.abs(fdv - grad))),
               "max_rel_diff": float(np.max(np.abs(fdv - grad)) / max(1e-300, np.max(np.abs(fdv))))}
+    cpu = None if a.no_cpu_baseline else adjoint_cpu_baseline(M)
     return {
         "metric": METRIC, "value": units / (bwd_ms / 1e3), "unit": UNIT, "n_gpus": 1,
         "steps": nsteps, "warmup": 1, "ms_per_step": bwd_ms / nsteps, "higher_is_better": True,
@@ -453,8 +454,29 @@ def run_adjoint(a, torch, soprop):
         "adjoint": {"forward_ms": fwd_ms, "backward_ms": bwd_ms, "pops": pops.tolist(),
                     "grad_P3": grad.tolist(), "fd_check": fd,
                     "workspace_bytes": int(ws.numel())},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
+
+
+def adjoint_cpu_baseline(M):
+    """The oracle's gradient (tangent mode, FP64) for one TJ-6 step of the
+    same model on a 32^3 grid: one step at 128^3 takes the oracle about ten
+    minutes, and its rate per unit does not depend on the grid size beyond
+    the FFT's log factor."""
+    from oracle import oracle as O
+    from paper_1903_04946_amd import synth
+    m = synth.lvc_3d(n=32, dv_params=True)
+    theta0 = np.array([c[3] for c in m.meta["couplings"]])
+    P = O.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, synth.lvc_vtable_theta(m, theta0),
+                  m.hbar)
+    t0 = time.perf_counter()
+    O.gradient(P, m.dvtables, m.psi0, O.VTV, O.TRIPLE_JUMP, 6, 10.0, 1, [0.0, 0.0, 1.0])
+    sec = time.perf_counter() - t0
+    return {"value": m.nsurf * m.npts * M / sec, "unit": UNIT, "cores": int(O.lib().orc_threads()),
+            "kind": "oracle",
+            "sample": f"tangent-mode gradient of P_3 w.r.t. the 3 couplings, one TJ-6 step "
+                      f"({M} substeps) of the same model on a 32^3 grid ({sec:.1f} s, "
+                      f"table formation included)"}
 
 
 def run_ensemble(a, torch, soprop):

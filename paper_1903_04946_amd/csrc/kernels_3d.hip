@@ -84,12 +84,14 @@ __global__ void __launch_bounds__(C * SC::TPC)
 // packed (Q_ii; Q_ij + Q_ji for i < j) in qacc[entry][point].  With KZ the
 // pass then applies the adjoint z factor K_z^dag (conjugated f_z) to all 2S
 // pencils.
-template <class SC, int S, int C, bool KZ>
+// The pass tile is C columns of the TC-column table tiles (C divides TC).
+template <class SC, int S, int C, int TC, bool KZ>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ vexp,
                   const cx<double>* __restrict__ eig, double* __restrict__ qacc,
                   const double* __restrict__ taus, int nv, int iv0, int iv1,
                   const cx<double>* __restrict__ tw, const cx<double>* __restrict__ fz) {
+  static_assert(TC % C == 0, "pass tile must divide the table tile");
   extern __shared__ char smem_raw[];
   cx<double>* lds = reinterpret_cast<cx<double>*>(smem_raw);
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2, P = 2 * S;
@@ -98,9 +100,10 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const int x = blockIdx.x * C + col, y = blockIdx.y;
   constexpr uint32_t plane = (uint32_t)N * N;
   constexpr int64_t npts = (int64_t)plane * N;
-  constexpr uint32_t tile = (uint32_t)N * NE * C;
+  constexpr uint32_t tile = (uint32_t)N * NE * TC;
   const uint32_t off0 = (uint32_t)y * N + x;
-  const size_t tbase = ((size_t)y * (N / C) + blockIdx.x) * tile;
+  const int tcol = (blockIdx.x * C) % TC + col;  // column within the table tile
+  const size_t tbase = ((size_t)y * (N / TC) + (blockIdx.x * C) / TC) * tile;
   const LayStrided lay{col, 0, C};
   cx<double> v[P][E];
 #pragma unroll
@@ -116,18 +119,18 @@ __global__ void __launch_bounds__(C * SC::TPC)
     const double tau = taus[iv];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * C) + col;
+      const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
       const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * plane + off0;
       cx<double> u[NE];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        u[e] = ld<double>(ru, tp + e * C);
+        u[e] = ld<double>(ru, tp + e * TC);
         u[e].im = -u[e].im;  // U^dag = conj(U) for complex-symmetric U
       }
       double ev[2 * NE];  // R (row-major S x S) then lam (S)
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        const cx<double> w = ld<double>(rg, tp + e * C);
+        const cx<double> w = ld<double>(rg, tp + e * TC);
         ev[2 * e] = w.re;
         ev[2 * e + 1] = w.im;
       }
@@ -152,22 +155,52 @@ __global__ void __launch_bounds__(C * SC::TPC)
         }
       }
       const double* lam = ev + S * S;
+      // c_a = exp(-i tau lam_a / 2): three sincos per point instead of one per
+      // (a, b) pair.  exp(-i tau (lam_a + lam_b)/2) = c_a c_b and
+      // exp(i h_ab) = c_b conj(c_a) with h_ab = tau (lam_a - lam_b)/2, so
+      // sin(h_ab) = Im(c_b conj(c_a)); below |h| = 1e-2 the sinc comes from its
+      // series (the product form would lose relative accuracy there).
+      cx<double> c[S];
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        double sn, cs;
+        sincos(0.5 * tau * lam[a], &sn, &cs);
+        c[a] = cx<double>{cs, -sn};
+      }
       double rm[S][S];  // Re(M)
 #pragma unroll
       for (int a = 0; a < S; ++a)
 #pragma unroll
         for (int b = 0; b < S; ++b) {
           // F_ab = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2)
-          const double h = 0.5 * tau * (lam[a] - lam[b]);
-          const double sc = (fabs(h) < 1e-8) ? 1.0 - h * h / 6.0 : sin(h) / h;
-          double sn, cs;
-          sincos(-0.5 * tau * (lam[a] + lam[b]), &sn, &cs);
-          // -i tau (cs + i sn) sc = tau sc (sn - i cs)
-          const cx<double> F = {tau * sc * sn, -tau * sc * cs};
+          double sc = 1.0;
+          if (a != b) {
+            const double h = 0.5 * tau * (lam[a] - lam[b]);
+            if (fabs(h) < 1e-2) {
+              const double h2 = h * h;
+              sc = 1.0 - h2 * (1.0 / 6.0 - h2 * (1.0 / 120.0 - h2 * (1.0 / 5040.0)));
+            } else {
+              const double sh = c[b].im * c[a].re - c[b].re * c[a].im;  // Im(c_b conj(c_a))
+              sc = sh / h;
+            }
+          }
+          const cx<double> e2 = cmul(c[a], c[b]);
+          // -i tau sc e2
+          const cx<double> F = {tau * sc * e2.im, -tau * sc * e2.re};
           const cx<double> fb = cmul(F, be[b]);
           rm[a][b] = al[a].re * fb.re + al[a].im * fb.im;  // Re(conj(alpha_a) F_ab beta_b)
         }
-      // Q = R Re(M) R^T, accumulated packed
+      // Q = R Re(M) R^T (T = R Re(M) first), accumulated packed
+      double tq[S][S];
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+          double acc = 0.0;
+#pragma unroll
+          for (int a = 0; a < S; ++a) acc += ev[i * S + a] * rm[a][b];
+          tq[i][b] = acc;
+        }
       int e = 0;
 #pragma unroll
       for (int i = 0; i < S; ++i)
@@ -175,12 +208,10 @@ __global__ void __launch_bounds__(C * SC::TPC)
         for (int j = i; j < S; ++j) {
           double qij = 0.0, qji = 0.0;
 #pragma unroll
-          for (int a = 0; a < S; ++a)
-#pragma unroll
-            for (int b = 0; b < S; ++b) {
-              qij += ev[i * S + a] * rm[a][b] * ev[j * S + b];
-              qji += ev[j * S + a] * rm[a][b] * ev[i * S + b];
-            }
+          for (int b = 0; b < S; ++b) {
+            qij += tq[i][b] * ev[j * S + b];
+            qji += tq[j][b] * ev[i * S + b];
+          }
           double* qp = qacc + (size_t)e * npts + pt;
           *qp += (i == j) ? qij : qij + qji;
           ++e;
@@ -320,9 +351,10 @@ struct Passes {
   static constexpr int ROWS = xrows<XS>();
   static_assert(N % C == 0 && N % CZ == 0 && N % ROWS == 0, "tiles must cover the grid");
 
-  // algorithmic bytes of one pass: psi read + written, plus tables read
+  // algorithmic bytes of one pass: psi read + written (d.S pencil sets: the
+  // adjoint's y- and x-passes run on the stacked 2S), plus tables read
   static double pass_bytes(const DevView& d, int ntables) {
-    return (2.0 * S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>) * d.count;
+    return (2.0 * d.S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>) * d.count;
   }
   // axis factor a (0 z, 1 y, 2 x) of kinetic set tidx
   static const cx<T>* kfac(const DevView& d, int tidx, int a) {
@@ -487,15 +519,18 @@ struct Passes {
   static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1,
                        int tidx) {
     using SA = typename AdjSched<SC>::type;
-    constexpr int CA = kTableCols;  // the adjoint pass reads whole table tiles
-    auto k = k3d_zpass_adj<SA, S, CA, KZ>;
+    // at most 256 threads per block (four waves: each may hold 512 registers)
+    constexpr int CA = (256 / SA::TPC < kTableCols) ? 256 / SA::TPC : kTableCols;
+    auto k = k3d_zpass_adj<SA, S, CA, kTableCols, KZ>;
     const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
-    // psi, lambda read + written; per action a table, the eigen table and the
-    // gradient accumulator (read + written)
-    const double bytes = (4.0 * S + nv * (2.0 * S * (S + 1) / 2.0 + S * (S + 1))) *
-                         (double)d.npts * sizeof(cx<double>) / 1.0;
+    // psi, lambda read + written; per action a table and the eigen table
+    // (S(S+1)/2 complex each) and the gradient accumulator (S(S+1)/2 doubles,
+    // read + written)
+    constexpr double NE = S * (S + 1) / 2.0;
+    const double bytes = ((4.0 * S + nv * 2.0 * NE) * sizeof(cx<double>) +
+                          nv * 2.0 * NE * sizeof(double)) * (double)d.npts;
     TimedLaunch tl(d, KIND_OTHER, bytes);
     hipLaunchKernelGGL(k, dim3(N / CA, N), dim3(CA * SA::TPC), lds, d.stream,
                        (cx<double>*)a.stacked, (const cx<double>*)d.vexp,

@@ -114,6 +114,36 @@ def test_adjoint_vs_finite_differences_128(torch_cuda):
     assert np.max(np.abs(grad - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd)))
 
 
+def test_adjoint_256_bench_shape(torch_cuda):
+    """256^3 x 3, TJ-6, dt = 10 (the largest adjoint configuration, at the
+    bench's launch shape): gradient of P_3 vs central differences (h = 1e-5
+    eV) and the conservation of the total norm (sum_s dP_s/dtheta = 0)."""
+    torch = torch_cuda
+    m, theta0, v0 = base_model(256)
+    nsteps, K = 3, 2
+    plan = make_plan(torch, m, v0, "triple_jump", 6, 10.0)
+    psi0 = torch.from_numpy(m.psi0).cuda()
+    plan.set_params(theta0)
+    ws = plan.adjoint_workspace(nsteps, K)
+    plan.adjoint_forward(psi0, nsteps, K, ws)
+    grad = plan.adjoint_backward(nsteps, K, [0, 0, 1.0], ws)
+    plan.adjoint_forward(psi0, nsteps, K, ws)
+    gn = plan.adjoint_backward(nsteps, K, [1.0, 1.0, 1.0], ws)
+    assert np.max(np.abs(gn)) < 1e-11
+    h = 1e-5
+    fd = np.zeros(3)
+    for k in range(3):
+        vals = []
+        for sgn in (1, -1):
+            th = theta0.copy()
+            th[k] += sgn * h
+            plan.set_params(th)
+            vals.append(plan.adjoint_forward(psi0, nsteps, K, ws)[2])
+        fd[k] = (vals[0] - vals[1]) / (2 * h)
+    print(f"[adjoint 256^3] grad {grad} fd {fd}")
+    assert np.max(np.abs(grad - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
 def test_populations_autograd(torch_cuda):
     torch = torch_cuda
     from paper_1903_04946_amd import soprop
