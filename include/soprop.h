@@ -112,7 +112,7 @@ typedef struct {
   int n_b;        /* B actions per step                                     */
   int n_a_unq;    /* unique A coefficients                                  */
   int n_b_unq;    /* unique B coefficients                                  */
-  int n_v_tables; /* stored potential tables  (= n_a_unq if A = V)          */
+  int n_v_tables; /* stored potential tables (= n_a_unq if A = V; 1 for the eigen form) */
   int n_t_tables; /* stored kinetic factor sets                             */
   int64_t npts;
   size_t table_bytes;   /* device bytes of stored evolution operators      */
@@ -149,8 +149,14 @@ sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int ca
 /* Builds a plan: validates, computes the sequence on the host, uploads the
  * V-table and forms the unique potential tables exp(-i c dt V/hbar) on the
  * device (FP64 formation, rounded once to complex64 for SOP_C64 plans), plus
- * per-axis kinetic factors and FFT twiddles.  hip_stream: a hipStream_t or
- * NULL.  Synchronises the stream.  *out receives the plan. */
+ * per-axis kinetic factors and FFT twiddles.  3D FP64 plans of two or three
+ * surfaces store instead one compact eigen form of V per point (the rotation
+ * of its Jacobi diagonalisation and its eigenvalues, 32 or 64 bytes), from
+ * which each potential action forms exp(-i tau lam) in FP64; they do so when
+ * every phase |tau lam| (bounded by the Gershgorin row sums of the V-table)
+ * stays within 1e6, and keep the per-coefficient tables otherwise.
+ * hip_stream: a hipStream_t or NULL.  Synchronises the stream.  *out
+ * receives the plan. */
 sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out);
 
 /* Frees the plan's device memory.  NULL is accepted. */
@@ -193,7 +199,9 @@ sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
 
 /* Sets the parameters: V <- vtable + sum_k theta[k] dvtables[k], and forms the
  * potential tables again on the device (theta: host, [nparams]).
- * Synchronises.  SOP_ERR_STATE if the plan has no parameters. */
+ * Synchronises.  SOP_ERR_STATE if the plan has no parameters;
+ * SOP_ERR_UNSUPPORTED if the plan holds the eigen form and theta could take
+ * a phase |tau lam| beyond its range (then nothing changes). */
 sop_status sop_plan_set_params(sop_plan* plan, const double* theta);
 
 /* Adjoint (reverse-mode) derivatives of the final surface populations

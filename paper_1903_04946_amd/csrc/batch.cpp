@@ -270,6 +270,7 @@ sop_status tune_group(sop_batch* b, Group3& g) {
     std::memset(&m, 0, sizeof(m));
     m.psi = (char*)scratch + one * i;
     m.vexp = d.vexp;
+    m.vtaus = d.vtaus;
     m.kin = d.kin;
     m.tw = d.tw[0];
     m.prog = d.prog;
@@ -437,7 +438,8 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
         b->fams.push_back(f);
       }
       b->fams[it->second].members.push_back(i);
-    } else if (sop::k3b_supported(d.n[0], d.S) && vtv_m(d) > 0) {
+    } else if (sop::k3b_supported(d.n[0], d.S) && vtv_m(d) > 0 &&
+               d.eig == sop::eig_form(3, d.S, d.f64)) {
       const std::string k = std::to_string(d.n[0]) + "/" + std::to_string(d.S) + "/" +
                             dtype_name(d.f64);
       auto it = gidx.find(k);
@@ -604,6 +606,7 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
         std::memset(&m, 0, sizeof(m));
         m.psi = psi[mi];
         m.vexp = d.vexp;
+        m.vtaus = d.vtaus;
         m.kin = d.kin;
         m.tw = d.tw[0];
         m.prog = d.prog;

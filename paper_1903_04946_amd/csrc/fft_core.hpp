@@ -308,6 +308,54 @@ __device__ __forceinline__ void fft_inverse(cx<T> (*v)[SC::E], cx<T>* lds, const
   run_stages<T, SC::N, SC::E, true, 1, P, Lay>(v, lds, lay, tw, t, typename SC::Inv{});
 }
 
+// ----------------------------------------------------------------- phases
+// Largest |x| that sincos_phase accepts (the quadrant count stays below 2^22,
+// so its products with the 30-bit parts of pi/2 are exact).
+constexpr double kPhaseMax = 1.0e6;
+
+// sin x and cos x in FP64 for |x| <= kPhaseMax: Cody-Waite reduction
+// x = k pi/2 + r with pi/2 = C1 + C2 + C3 (C1, C2 of 30 significant bits,
+// together about 115 bits, computed from Machin's formula
+// pi = 16 atan(1/5) - 4 atan(1/239)), then the Taylor series of sin and cos
+// on |r| <= pi/4 through r^17 and r^18 (the first omitted terms are below
+// 1e-19).  Short and branch-free, unlike the general library routine with its
+// large-argument reduction.
+__host__ __device__ __forceinline__ void sincos_phase(double x, double* sn, double* cs) {
+  const double k = rint(x * 0.63661977236758138);  // 2/pi
+  double r = fma(-k, 1.5707963276654482, x);      // C1 = 0x1.921fb548p+0
+  r = fma(-k, -8.705515692000731e-10, r);         // C2 = -0x1.de973dc8p-31
+  r = fma(-k, -3.50343439808993e-19, r);          // C3
+  const double u = r * r;
+  // sin r = r sum_{n<=8} (-u)^n / (2n+1)!, Horner from the top term
+  double ps = 1.0 / 355687428096000.0;   // 1/17!
+  ps = fma(ps, u, -1.0 / 1307674368000.0);  // 1/15!
+  ps = fma(ps, u, 1.0 / 6227020800.0);      // 1/13!
+  ps = fma(ps, u, -1.0 / 39916800.0);       // 1/11!
+  ps = fma(ps, u, 1.0 / 362880.0);          // 1/9!
+  ps = fma(ps, u, -1.0 / 5040.0);           // 1/7!
+  ps = fma(ps, u, 1.0 / 120.0);             // 1/5!
+  ps = fma(ps, u, -1.0 / 6.0);              // 1/3!
+  ps = fma(ps, u, 1.0);
+  // cos r = sum_{n<=9} (-u)^n / (2n)!
+  double pc = -1.0 / 6402373705728000.0;  // 1/18!
+  pc = fma(pc, u, 1.0 / 20922789888000.0);  // 1/16!
+  pc = fma(pc, u, -1.0 / 87178291200.0);    // 1/14!
+  pc = fma(pc, u, 1.0 / 479001600.0);       // 1/12!
+  pc = fma(pc, u, -1.0 / 3628800.0);        // 1/10!
+  pc = fma(pc, u, 1.0 / 40320.0);           // 1/8!
+  pc = fma(pc, u, -1.0 / 720.0);            // 1/6!
+  pc = fma(pc, u, 1.0 / 24.0);              // 1/4!
+  pc = fma(pc, u, -0.5);
+  pc = fma(pc, u, 1.0);
+  const double s0 = r * ps, c0 = pc;
+  // x = k pi/2 + r: rotate (s0, c0) by the quadrant k mod 4
+  const int q = (int)((long long)k & 3);
+  const double a = (q & 1) ? c0 : s0;
+  const double b = (q & 1) ? s0 : c0;
+  *sn = (q & 2) ? -a : a;
+  *cs = ((q + 1) & 2) ? -b : b;
+}
+
 // ----------------------------------------------------------------- potential
 // w = U v for the complex-symmetric U given by its packed upper triangle
 // (S(S+1)/2 entries, row-major); conj = 1 applies conj(U) = U(-tau).

@@ -102,7 +102,11 @@ struct DevView {
   int64_t npts = 1;
   bool f64 = true;
   hipStream_t stream = nullptr;
-  const void* vexp = nullptr;  // [n_vtab][S(S+1)/2][npts] complex
+  // [n_vtab][S(S+1)/2][npts] complex; when `eig`, the one compact
+  // eigen-form table instead
+  const void* vexp = nullptr;
+  bool eig = false;
+  const double* vtaus = nullptr;  // device c dt / hbar of each potential coefficient
   const void* kin = nullptr;   // 1D: [n_ttab][n0]; 3D: [n_ttab][3][kin_stride]
   int kin_stride = 0;          // complex entries per axis block (3D)
   const void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis twiddles exp(-2 pi i k/n)
@@ -174,6 +178,13 @@ hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
 bool k3d_plane(int n, bool f64);  // the xy plane of an n^3 grid fits in LDS
 hipError_t k3d_fft_forward(const DevView& d, void* psi);
 
+// Complex slots per point of the compact eigen form (3D FP64, S = 2, 3).
+constexpr int eig_slots(int S) { return S == 3 ? 4 : 2; }
+// Whether a plan of this kind can store the eigen form instead of
+// per-coefficient tables (it does when every phase tau lam stays within
+// kPhaseMax).
+constexpr bool eig_form(int ndim, int S, bool f64) { return ndim == 3 && f64 && S >= 2; }
+
 // kernels_aux.hip
 // tile = 0: [u][entry][point] (1D); tile = C: the z-pass tile layout (3D).
 hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
@@ -184,6 +195,8 @@ hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
 hipError_t overlap_reduce(const DevView& d, const void* psi, const void* phi,
                           double* partials_dev, double* out_dev);
 hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* out);
+// compact eigen form, eig_slots(S) slots per point in the z-pass tile layout
+hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out);
 hipError_t set_vparams(const DevView& d, double* vraw, const double* vbase, const double* dv,
                        const double* delta_dev, int nparams);
 hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const double* w_dev,
@@ -212,7 +225,8 @@ struct BMember1 {
 // c = cycles its closing potential action.
 struct BMember3 {
   void* psi;          // [S][n^3]
-  const void* vexp;   // tile-layout potential tables
+  const void* vexp;   // tile-layout potential tables (or the eigen form, FP64 S >= 2)
+  const double* vtaus;  // c dt / hbar of each potential coefficient (eigen form)
   const void* kin;    // [n_ttab][3][kin_stride]
   const void* tw;     // [3][n] twiddles (z, y, x blocks)
   const int* prog;

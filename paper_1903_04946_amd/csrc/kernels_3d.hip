@@ -57,26 +57,30 @@ constexpr int zcols() {
 
 // ---------------------------------------------------------------- z-pass
 // grid (N / C, N, states); fz = the z factor of the kinetic set (AX_KIN)
-template <typename T, class SC, int S, int C, int AX>
+// EQ: the potential comes from the compact eigen form (FP64, S >= 2).
+template <typename T, class SC, int S, int C, int AX, bool EQ>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
-              int conj, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fz) {
+              int conj, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fz,
+              const double* __restrict__ taus) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   psi += (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member of a batch
-  zpass_body<T, SC, S, C, kTableCols, AX>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds,
-                                          blockIdx.x, blockIdx.y);
+  zpass_body<T, SC, S, C, kTableCols, AX, EQ>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds,
+                                              blockIdx.x, blockIdx.y, taus);
 }
 
 // ---------------------------------------------------------------- adjoint z-pass
 // Backward sweep of the adjoint method over the stacked state [psi; lambda]
 // (2S pencils, FP64).  For each potential action j, walked in reverse, the
 // kernel holds psi_j (the state after the action) and lambda_j (the adjoint
-// after it) and computes
-//   psi_{j-1} = U_j^dag psi_j,   lambda_{j-1} = U_j^dag lambda_j,
+// after it) and, with V(x) = R diag(lam) R^T read from the eigen table and
+// D = diag(exp(-i tau lam)), computes in eigen coordinates
+//   psi_{j-1} = U_j^dag psi_j = R conj(D) R^T psi_j,
+//   lambda_{j-1} = U_j^dag lambda_j = R conj(D) R^T lambda_j,
 //   Q(x) += R Re(M) R^T,  M_ab = conj(alpha_a) F_ab beta_b,
-// with alpha = R^T lambda_j, beta = R^T psi_{j-1}, V(x) = R diag(lam) R^T and
-// the divided differences of f(v) = exp(-i tau v):
+// with alpha = R^T lambda_j, beta = R^T psi_{j-1} and the divided
+// differences of f(v) = exp(-i tau v):
 //   F_ab = (f(lam_a) - f(lam_b)) / (lam_a - lam_b)
 //        = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2),
 // so that d P / d theta_k = 2 dV sum_x sum_ij Q_ij(x) D_k,ij(x) (Daleckii-
@@ -87,8 +91,8 @@ __global__ void __launch_bounds__(C * SC::TPC)
 // The pass tile is C columns of the TC-column table tiles (C divides TC).
 template <class SC, int S, int C, int TC, bool KZ>
 __global__ void __launch_bounds__(C * SC::TPC)
-    k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ vexp,
-                  const cx<double>* __restrict__ eig, double* __restrict__ qacc,
+    k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ eig,
+                  double* __restrict__ qacc,
                   const double* __restrict__ taus, int nv, int iv0, int iv1,
                   const cx<double>* __restrict__ tw, const cx<double>* __restrict__ fz) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
@@ -114,19 +118,12 @@ __global__ void __launch_bounds__(C * SC::TPC)
       v[s][q] = ld<double>(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0);
   }
   auto vact = [&](int iv) {
-    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
     const auto rg = rsrc(eig + tbase, tile);
     const double tau = taus[iv];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
       const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * plane + off0;
-      cx<double> u[NE];
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        u[e] = ld<double>(ru, tp + e * TC);
-        u[e].im = -u[e].im;  // U^dag = conj(U) for complex-symmetric U
-      }
       double ev[2 * NE];  // R (row-major S x S) then lam (S)
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -134,24 +131,17 @@ __global__ void __launch_bounds__(C * SC::TPC)
         ev[2 * e] = w.re;
         ev[2 * e + 1] = w.im;
       }
-      cx<double> ps[S], la[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        ps[s] = v[s][q];
-        la[s] = v[S + s][q];
-      }
-      apply_u<double, S>(ps, u);  // psi_{j-1}
-      // alpha = R^T lambda_j, beta = R^T psi_{j-1}
-      cx<double> al[S], be[S];
+      // eigen coordinates: gamma = R^T psi_j, alpha = R^T lambda_j
+      cx<double> ga[S], al[S];
 #pragma unroll
       for (int a = 0; a < S; ++a) {
+        ga[a] = cx<double>{0.0, 0.0};
         al[a] = cx<double>{0.0, 0.0};
-        be[a] = cx<double>{0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < S; ++i) {
           const double r = ev[i * S + a];
-          al[a] = cx<double>{al[a].re + r * la[i].re, al[a].im + r * la[i].im};
-          be[a] = cx<double>{be[a].re + r * ps[i].re, be[a].im + r * ps[i].im};
+          ga[a] = cx<double>{ga[a].re + r * v[i][q].re, ga[a].im + r * v[i][q].im};
+          al[a] = cx<double>{al[a].re + r * v[S + i][q].re, al[a].im + r * v[S + i][q].im};
         }
       }
       const double* lam = ev + S * S;
@@ -164,8 +154,17 @@ __global__ void __launch_bounds__(C * SC::TPC)
 #pragma unroll
       for (int a = 0; a < S; ++a) {
         double sn, cs;
-        sincos(0.5 * tau * lam[a], &sn, &cs);
+        sincos_phase(0.5 * tau * lam[a], &sn, &cs);
         c[a] = cx<double>{cs, -sn};
+      }
+      // U_j^dag = R conj(D) R^T with D_a = exp(-i tau lam_a) = c_a^2:
+      // beta = R^T psi_{j-1} = conj(D) gamma, and R^T lambda_{j-1} = conj(D) alpha
+      cx<double> be[S], al1[S];
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const cx<double> dc = cconj(cmul(c[a], c[a]));
+        be[a] = cmul(dc, ga[a]);
+        al1[a] = cmul(dc, al[a]);
       }
       double rm[S][S];  // Re(M)
 #pragma unroll
@@ -216,11 +215,18 @@ __global__ void __launch_bounds__(C * SC::TPC)
           *qp += (i == j) ? qij : qij + qji;
           ++e;
         }
-      apply_u<double, S>(la, u);  // lambda_{j-1}
+      // psi_{j-1} = R beta, lambda_{j-1} = R conj(D) alpha
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        v[s][q] = ps[s];
-        v[S + s][q] = la[s];
+      for (int i = 0; i < S; ++i) {
+        cx<double> p = {0.0, 0.0}, l = {0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+          const double r = ev[i * S + a];
+          p = cx<double>{p.re + r * be[a].re, p.im + r * be[a].im};
+          l = cx<double>{l.re + r * al1[a].re, l.im + r * al1[a].im};
+        }
+        v[i][q] = p;
+        v[S + i][q] = l;
       }
     }
   };
@@ -351,10 +357,17 @@ struct Passes {
   static constexpr int ROWS = xrows<XS>();
   static_assert(N % C == 0 && N % CZ == 0 && N % ROWS == 0, "tiles must cover the grid");
 
+  // the potential may come from the compact eigen form (one table for every
+  // coefficient; plans whose phases stay within kPhaseMax)
+  static constexpr bool EQ = eig_form(3, S, std::is_same<T, double>::value);
+
   // algorithmic bytes of one pass: psi read + written (d.S pencil sets: the
-  // adjoint's y- and x-passes run on the stacked 2S), plus tables read
+  // adjoint's y- and x-passes run on the stacked 2S), plus tables read (the
+  // eigen form is read once for up to two actions)
   static double pass_bytes(const DevView& d, int ntables) {
-    return (2.0 * d.S + ntables * S * (S + 1) / 2.0) * (double)d.npts * sizeof(cx<T>) * d.count;
+    const double tab = (EQ && d.eig) ? (ntables > 0 ? eig_slots(S) : 0)
+                                     : ntables * S * (S + 1) / 2.0;
+    return (2.0 * d.S + tab) * (double)d.npts * sizeof(cx<T>) * d.count;
   }
   // axis factor a (0 z, 1 y, 2 x) of kinetic set tidx
   static const cx<T>* kfac(const DevView& d, int tidx, int a) {
@@ -364,14 +377,22 @@ struct Passes {
   template <int AX>
   static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int tidx,
                       int conj) {
-    auto k = k3d_zpass<T, SC, S, CZ, AX>;
+    if constexpr (EQ) {
+      if (d.eig) return zk<AX, true>(d, psi, nv, iv0, iv1, tidx, conj);
+    }
+    return zk<AX, false>(d, psi, nv, iv0, iv1, tidx, conj);
+  }
+  template <int AX, bool Q>
+  static hipError_t zk(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int tidx,
+                       int conj) {
+    auto k = k3d_zpass<T, SC, S, CZ, AX, Q>;
     const size_t lds = (size_t)CZ * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
     hipLaunchKernelGGL(k, dim3(N / CZ, N, d.count), dim3(CZ * SC::TPC), lds, d.stream, psi,
                        (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0],
-                       AX == AX_KIN ? kfac(d, tidx, 0) : nullptr);
+                       AX == AX_KIN ? kfac(d, tidx, 0) : nullptr, d.vtaus);
     return hipGetLastError();
   }
   template <int AX>
@@ -525,16 +546,15 @@ struct Passes {
     const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
-    // psi, lambda read + written; per action a table and the eigen table
-    // (S(S+1)/2 complex each) and the gradient accumulator (S(S+1)/2 doubles,
-    // read + written)
+    // psi, lambda read + written; per action the eigen table (S(S+1)/2
+    // complex) and the gradient accumulator (S(S+1)/2 doubles, read + written)
     constexpr double NE = S * (S + 1) / 2.0;
-    const double bytes = ((4.0 * S + nv * 2.0 * NE) * sizeof(cx<double>) +
+    const double bytes = ((4.0 * S + nv * NE) * sizeof(cx<double>) +
                           nv * 2.0 * NE * sizeof(double)) * (double)d.npts;
     TimedLaunch tl(d, KIND_OTHER, bytes);
     hipLaunchKernelGGL(k, dim3(N / CA, N), dim3(CA * SA::TPC), lds, d.stream,
-                       (cx<double>*)a.stacked, (const cx<double>*)d.vexp,
-                       (const cx<double>*)a.eig, a.qacc, a.taus, nv, iv0, iv1,
+                       (cx<double>*)a.stacked, (const cx<double>*)a.eig, a.qacc, a.taus, nv,
+                       iv0, iv1,
                        (const cx<double>*)d.tw[0],
                        KZ ? (const cx<double>*)kfac(d, tidx, 0) : nullptr);
     return hipGetLastError();

@@ -247,6 +247,82 @@ __global__ void __launch_bounds__(kReduceThreads)
   }
 }
 
+// Compact eigen form of V(q) for the FP64 3D z-pass (S = 2, 3): per point
+// the rotation R of V = R diag(lam) R^T (det R = +1, a product of Jacobi
+// rotations) and the eigenvalues, in eig_slots(S) complex slots of the
+// z-pass tile layout: S = 3 as the unit quaternion (w, x) (y, z) of R and
+// (lam_0, lam_1) (lam_2, 0); S = 2 as (cos, sin) of the rotation angle and
+// (lam_0, lam_1).  One table serves every coefficient: each potential
+// action forms exp(-i tau lam) itself.  The quaternion comes from the
+// largest of w^2, x^2, y^2, z^2 (each = (1 +- R_00 +- R_11 +- R_22)/4), so
+// the division is always by a number >= 1/2.
+template <int S>
+__global__ void __launch_bounds__(256)
+    k_form_eigq(const double* __restrict__ vraw, int64_t npts, int tile, int n,
+                cx<double>* __restrict__ out) {
+  constexpr int NE = S * (S + 1) / 2;
+  constexpr int NQ = eig_slots(S);
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    double A[S][S], R[S][S];
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = i; j < S; ++j) {
+        const double vij = vraw[(int64_t)e * npts + x];
+        A[i][j] = vij;
+        A[j][i] = vij;
+        ++e;
+      }
+    jacobi_sym<S>(A, R);
+    cx<double> slot[NQ];
+    if constexpr (S == 2) {
+      slot[0] = cx<double>{R[0][0], R[1][0]};
+      slot[1] = cx<double>{A[0][0], A[1][1]};
+    } else {
+      const double t0 = 1.0 + R[0][0] + R[1][1] + R[2][2];  // 4 w^2
+      const double t1 = 1.0 + R[0][0] - R[1][1] - R[2][2];  // 4 x^2
+      const double t2 = 1.0 - R[0][0] + R[1][1] - R[2][2];  // 4 y^2
+      const double t3 = 1.0 - R[0][0] - R[1][1] + R[2][2];  // 4 z^2
+      double w, qx, qy, qz;
+      if (t0 >= t1 && t0 >= t2 && t0 >= t3) {
+        const double r = 2.0 * sqrt(t0);  // 4 w
+        w = 0.25 * r;
+        qx = (R[2][1] - R[1][2]) / r;
+        qy = (R[0][2] - R[2][0]) / r;
+        qz = (R[1][0] - R[0][1]) / r;
+      } else if (t1 >= t2 && t1 >= t3) {
+        const double r = 2.0 * sqrt(t1);  // 4 x
+        w = (R[2][1] - R[1][2]) / r;
+        qx = 0.25 * r;
+        qy = (R[0][1] + R[1][0]) / r;
+        qz = (R[0][2] + R[2][0]) / r;
+      } else if (t2 >= t3) {
+        const double r = 2.0 * sqrt(t2);  // 4 y
+        w = (R[0][2] - R[2][0]) / r;
+        qx = (R[0][1] + R[1][0]) / r;
+        qy = 0.25 * r;
+        qz = (R[1][2] + R[2][1]) / r;
+      } else {
+        const double r = 2.0 * sqrt(t3);  // 4 z
+        w = (R[1][0] - R[0][1]) / r;
+        qx = (R[0][2] + R[2][0]) / r;
+        qy = (R[1][2] + R[2][1]) / r;
+        qz = 0.25 * r;
+      }
+      const double nrm = 1.0 / sqrt(w * w + qx * qx + qy * qy + qz * qz);
+      slot[0] = cx<double>{w * nrm, qx * nrm};
+      slot[1] = cx<double>{qy * nrm, qz * nrm};
+      slot[2] = cx<double>{A[0][0], A[1][1]};
+      slot[3] = cx<double>{A[2][2], 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[table_index(npts, NQ, tile, n, 0, q, x)] = slot[q];
+    (void)NE;
+  }
+}
+
 // Eigen-decomposition table for the adjoint: per point R (row-major S x S)
 // then the eigenvalues, as S(S+1)/2 pairs of doubles in the z-pass tile
 // layout (the pair of entry e is stored where a table stores its entry e).
@@ -362,6 +438,17 @@ hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* tau
                          : form_impl<3, float>(d, vraw_dev, taus, ntau, tile, out);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out) {
+  int blocks = (int)((d.npts + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  switch (d.S) {
+    case 2: hipLaunchKernelGGL(k_form_eigq<2>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    case 3: hipLaunchKernelGGL(k_form_eigq<3>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // partials layout: [kReduceBlocks][S+1] for the pointwise sums, then

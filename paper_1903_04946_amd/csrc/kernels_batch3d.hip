@@ -42,10 +42,11 @@ __global__ void __launch_bounds__(C * SC::TPC)
   cx<T>* psi = (cx<T>*)m.psi;
   const cx<T>* vexp = (const cx<T>*)m.vexp;
   const cx<T>* tw = (const cx<T>*)m.tw;
+  constexpr bool EQ = eig_form(3, S, sizeof(T) == 8);
   if (c == m.cycles) {  // closing potential action
-    zpass_body<T, SC, S, C, kTableCols, AX_NONE>(psi, vexp, 1, prog_index(m.prog[2 * M]), 0,
-                                                 m.conj, tw, nullptr, lds, blockIdx.x,
-                                                 blockIdx.y);
+    zpass_body<T, SC, S, C, kTableCols, AX_NONE, EQ>(psi, vexp, 1, prog_index(m.prog[2 * M]),
+                                                     0, m.conj, tw, nullptr, lds, blockIdx.x,
+                                                     blockIdx.y, m.vtaus);
     return;
   }
   const int i = (int)(c % M);
@@ -55,9 +56,9 @@ __global__ void __launch_bounds__(C * SC::TPC)
     iv0 = prog_index(m.prog[2 * M]);
     iv1 = prog_index(m.prog[0]);
   }
-  zpass_body<T, SC, S, C, kTableCols, AX_KIN>(psi, vexp, nv, iv0, iv1, m.conj, tw,
-                                              cycle_kin<T>(m, c, 0), lds, blockIdx.x,
-                                              blockIdx.y);
+  zpass_body<T, SC, S, C, kTableCols, AX_KIN, EQ>(psi, vexp, nv, iv0, iv1, m.conj, tw,
+                                                  cycle_kin<T>(m, c, 0), lds, blockIdx.x,
+                                                  blockIdx.y, m.vtaus);
 }
 
 // y-pass of cycle c: grid (N / C, N, S x members).

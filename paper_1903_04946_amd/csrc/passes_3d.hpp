@@ -99,14 +99,44 @@ __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __res
 // columns wide (C divides TC); block (bx, by) owns columns bx*C .. bx*C+C-1
 // of row y = by.  `psi` is one state [S][N^3]; `fz` the z factor of the
 // kinetic set (AX_KIN only).
-template <typename T, class SC, int S, int C, int TC, int AX>
+//
+// EQ (FP64, S = 2, 3): `vexp` is instead the one compact eigen-form table
+// (eig_slots(S) slots per point, same tile layout) and `taus` the tau of
+// each coefficient; a potential action is psi <- R exp(-i tau lam) R^T psi
+// in registers, and the two actions at a step boundary share one load, one
+// pair of rotations and one phase (psi <- R exp(-i (tau_1 + tau_2) lam) R^T
+// psi: the same operator, rounded once).
+template <typename T, int S>
+__device__ __forceinline__ void rotation_from_slots(const cx<T>* q, T (&R)[S][S]) {
+  if constexpr (S == 2) {
+    const T c = q[0].re, s = q[0].im;
+    R[0][0] = c;
+    R[0][1] = -s;
+    R[1][0] = s;
+    R[1][1] = c;
+  } else {
+    const T w = q[0].re, x = q[0].im, y = q[1].re, z = q[1].im;
+    R[0][0] = (T)1 - (T)2 * (y * y + z * z);
+    R[0][1] = (T)2 * (x * y - z * w);
+    R[0][2] = (T)2 * (x * z + y * w);
+    R[1][0] = (T)2 * (x * y + z * w);
+    R[1][1] = (T)1 - (T)2 * (x * x + z * z);
+    R[1][2] = (T)2 * (y * z - x * w);
+    R[2][0] = (T)2 * (x * z - y * w);
+    R[2][1] = (T)2 * (y * z + x * w);
+    R[2][2] = (T)1 - (T)2 * (x * x + y * y);
+  }
+}
+
+template <typename T, class SC, int S, int C, int TC, int AX, bool EQ = false>
 __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
                                            const cx<T>* __restrict__ vexp, int nv, int iv0,
                                            int iv1, int conj, const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fz, cx<T>* lds, int bx,
-                                           int by) {
+                                           int by, const double* __restrict__ taus = nullptr) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
-  constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2;
+  static_assert(!EQ || (sizeof(T) == 8 && S >= 2), "eigen form: FP64, two or three surfaces");
+  constexpr int N = SC::N, E = SC::E, NE = EQ ? eig_slots(S) : S * (S + 1) / 2;
   const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
   const int x = bx * C + col, y = by;
@@ -126,27 +156,66 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
     for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0);
   }
   const T csign = conj ? (T)-1 : (T)1;
-  auto vact = [&](int iv) {
-    const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
+  if constexpr (EQ) {
+    if (nv >= 1) {
+      const auto rq = rsrc(vexp + tbase, tile);
+      // two actions at a step boundary: exp(-i tau_2 lam) exp(-i tau_1 lam)
+      // = exp(-i (tau_1 + tau_2) lam), one phase per eigenvalue
+      const double tab = csign * (taus[iv0] + (nv >= 2 ? taus[iv1] : 0.0));
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
-      cx<T> u[NE];
+      for (int q = 0; q < E; ++q) {
+        const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
+        cx<T> sl[NE];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        u[e] = ld<T>(ru, pt + e * TC);
-        u[e].im *= csign;
+        for (int e = 0; e < NE; ++e) sl[e] = ld<T>(rq, pt + e * TC);
+        T R[S][S];
+        rotation_from_slots<T, S>(sl, R);
+        const T lam[3] = {sl[S == 3 ? 2 : 1].re, sl[S == 3 ? 2 : 1].im,
+                          S == 3 ? sl[NE - 1].re : (T)0};
+        // gamma = R^T psi, gamma_k *= exp(-i tau lam_k) per action, psi = R gamma
+        cx<T> g[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          g[k] = cx<T>{(T)0, (T)0};
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            g[k] = cx<T>{g[k].re + R[i][k] * v[i][q].re, g[k].im + R[i][k] * v[i][q].im};
+          double sn, cs;
+          sincos_phase(tab * lam[k], &sn, &cs);
+          g[k] = cmul(g[k], cx<T>{cs, -sn});
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          cx<T> a = {(T)0, (T)0};
+#pragma unroll
+          for (int k = 0; k < S; ++k) a = cx<T>{a.re + R[i][k] * g[k].re, a.im + R[i][k] * g[k].im};
+          v[i][q] = a;
+        }
       }
-      cx<T> w[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) w[s] = v[s][q];
-      apply_u<T, S>(w, u);
-#pragma unroll
-      for (int s = 0; s < S; ++s) v[s][q] = w[s];
     }
-  };
-  if (nv >= 1) vact(iv0);
-  if (nv >= 2) vact(iv1);
+  } else {
+    auto vact = [&](int iv) {
+      const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
+        cx<T> u[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          u[e] = ld<T>(ru, pt + e * TC);
+          u[e].im *= csign;
+        }
+        cx<T> w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) w[s] = v[s][q];
+        apply_u<T, S>(w, u);
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s][q] = w[s];
+      }
+    };
+    if (nv >= 1) vact(iv0);
+    if (nv >= 2) vact(iv1);
+  }
   if constexpr (AX != AX_NONE) {
 #pragma unroll
     for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, t);

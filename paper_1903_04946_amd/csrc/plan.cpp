@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/soprop.h"
+#include "fft_core.hpp"
 #include "internal.hpp"
 
 using sop::DevView;
@@ -190,6 +191,9 @@ struct sop_plan {
   double* d_part = nullptr;
   double* d_out = nullptr;
   size_t table_bytes = 0;
+  bool eig_form = false;  // d_vexp holds the compact eigen form (3D FP64, S >= 2)
+  double vbound = 0;      // max over points of max_i sum_j |V_ij| (bounds |lam|)
+  std::vector<double> dvbound;  // the same for each dvtables[k]
   int tile = 0;  // potential-table layout (0 = [u][entry][point])
   sop::Timer* timer = nullptr;
   int nparams = 0;
@@ -240,6 +244,43 @@ std::vector<ld> kinetic_factors(const sop_plan* p, const std::vector<double>& ta
         out[o + 1] = std::sin(ph) * scale;
       }
   return out;
+}
+
+// Largest Gershgorin row sum of a packed [S(S+1)/2][npts] symmetric table: a
+// bound on every |eigenvalue| at every point.
+double gershgorin_bound(const double* v, int S, int64_t npts) {
+  std::vector<int> idx((size_t)S * S);
+  int e = 0;
+  for (int i = 0; i < S; ++i)
+    for (int j = i; j < S; ++j) {
+      idx[(size_t)i * S + j] = e;
+      idx[(size_t)j * S + i] = e;
+      ++e;
+    }
+  double b = 0.0;
+  for (int64_t x = 0; x < npts; ++x)
+    for (int i = 0; i < S; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < S; ++j) r += std::fabs(v[(int64_t)idx[(size_t)i * S + j] * npts + x]);
+      b = std::max(b, r);
+    }
+  return b;
+}
+
+// Whether every phase the eigen-form z-pass forms, tau lam with tau up to
+// twice the largest coefficient (two merged actions) or `extra_tau`, stays
+// within the range of its phase routine.
+bool phases_fit(const sop_plan* p, double vbound, double extra_tau = 0.0) {
+  double tmax = std::fabs(extra_tau);
+  for (double t : p->vtaus) tmax = std::max(tmax, 2.0 * std::fabs(t));
+  return tmax * vbound <= sop::kPhaseMax;
+}
+
+// Forms the potential tables of the plan from its raw V-table on the device:
+// the compact eigen form, or one exp(-i tau V) table per unique coefficient.
+hipError_t form_tables(sop_plan* p) {
+  if (p->eig_form) return sop::form_eigq(p->dv, p->d_vraw, p->tile, p->d_vexp);
+  return sop::form_vexp(p->dv, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp);
 }
 
 // Rounds interleaved extended-precision values to the plan precision.
@@ -392,7 +433,17 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
 
   // device buffers
   const size_t vbytes = (size_t)NE * p->npts * sizeof(double);
-  const size_t tbytes = vc.size() * NE * p->npts * p->csize;
+  // 3D FP64 plans of two or three surfaces store the compact eigen form of
+  // V (one table for every coefficient) instead of one exp(-i tau V) table
+  // per unique coefficient
+  if (sop::eig_form(p->ndim, S, f64)) {
+    p->vbound = gershgorin_bound(desc->vtable, S, p->npts);
+    for (int k = 0; k < desc->nparams; ++k)
+      p->dvbound.push_back(gershgorin_bound(desc->dvtables + (size_t)k * NE * p->npts, S, p->npts));
+    p->eig_form = phases_fit(p, p->vbound);
+  }
+  const size_t tbytes = p->eig_form ? (size_t)sop::eig_slots(S) * p->npts * 2 * sizeof(double)
+                                    : vc.size() * NE * p->npts * p->csize;
   const int nax = p->ndim == 1 ? 1 : 3;
   const size_t kbytes = tc.size() * nax * p->n[0] * p->csize;
   const size_t wbytes = (size_t)nax * p->n[0] * p->csize;
@@ -448,7 +499,9 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   d.plane = p->ndim == 3 && p->n[0] <= 64;
 
   p->tile = p->ndim == 3 ? sop::k3d_table_tile(p->n[0], f64) : 0;
-  HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
+  d.vtaus = p->d_taus;
+  d.eig = p->eig_form;
+  HIPTRY(form_tables(p));
   if (p->ndim == 3) {
     p->graphs = new (std::nothrow) sop::GraphCache();
     if (!p->graphs) return fail(SOP_ERR_NOMEM, "host allocation failed");
@@ -498,7 +551,7 @@ sop_status sop_plan_info_get(const sop_plan* p, sop_plan_info* out) {
   i.n_b = (int)p->seq.b.size();
   i.n_a_unq = (int)p->seq.au.size();
   i.n_b_unq = (int)p->seq.bu.size();
-  i.n_v_tables = (int)p->vtaus.size();
+  i.n_v_tables = p->eig_form ? 1 : (int)p->vtaus.size();
   i.n_t_tables = (int)p->ttaus.size();
   i.npts = p->npts;
   i.table_bytes = p->table_bytes;
@@ -594,14 +647,20 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
   DevView d = p->dv;
   if (op == 0) {
     const int NE = p->S * (p->S + 1) / 2;
-    if (!p->d_atab) HIPTRY(hipMalloc(&p->d_atab, (size_t)NE * p->npts * p->csize));
     const double tau = (double)((ld)coef * (ld)p->dt / (ld)p->hbar);
     HIPTRY(hipMemcpyAsync(p->d_taus + p->vtaus.size(), &tau, sizeof(double),
                           hipMemcpyHostToDevice, d.stream));
-    HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->tile, p->d_atab));
-    d.vexp = p->d_atab;
-    d.prog = p->d_prog1;
-    d.hprog = {sop::prog_entry(sop::OP_V, 0)};
+    if (p->eig_form && std::fabs(tau) * p->vbound <= sop::kPhaseMax) {
+      // the eigen form serves any tau within range: index the spare slot
+      d.hprog = {sop::prog_entry(sop::OP_V, (int)p->vtaus.size())};
+    } else {
+      d.eig = false;
+      if (!p->d_atab) HIPTRY(hipMalloc(&p->d_atab, (size_t)NE * p->npts * p->csize));
+      HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->tile, p->d_atab));
+      d.vexp = p->d_atab;
+      d.prog = p->d_prog1;
+      d.hprog = {sop::prog_entry(sop::OP_V, 0)};
+    }
   } else {
     const int nax = p->ndim == 1 ? 1 : 3;
     const size_t kb = (size_t)nax * p->n[0] * p->csize;
@@ -627,10 +686,17 @@ sop_status sop_plan_set_params(sop_plan* p, const double* theta) {
   if (p->nparams == 0) return fail(SOP_ERR_STATE, "plan has no parameters");
   for (int k = 0; k < p->nparams; ++k)
     if (!std::isfinite(theta[k])) return fail(SOP_ERR_INVALID, "theta must be finite");
+  if (p->eig_form) {  // |lam(theta)| <= bound(V0) + sum_k |theta_k| bound(D_k)
+    double b = p->vbound;
+    for (int k = 0; k < p->nparams; ++k) b += std::fabs(theta[k]) * p->dvbound[k];
+    if (!phases_fit(p, b))
+      return fail(SOP_ERR_UNSUPPORTED,
+                  "these parameters take the phases tau*lambda beyond the eigen form's range");
+  }
   hipStream_t st = p->dv.stream;
   HIPTRY(hipMemcpyAsync(p->d_theta, theta, p->nparams * sizeof(double), hipMemcpyHostToDevice, st));
   HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
-  HIPTRY(sop::form_vexp(p->dv, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp));
+  HIPTRY(form_tables(p));
   if (p->d_eig) HIPTRY(sop::form_eig(p->dv, p->d_vraw, p->tile, p->d_eig));
   HIPTRY(hipStreamSynchronize(st));
   return SOP_OK;

@@ -71,22 +71,26 @@ def normalise(psi: np.ndarray, dV: float) -> np.ndarray:
 # ----------------------------------------------------------------- 1D model
 def two_surface_1d(n: int = 1024, lo: float = -10.0, hi: float = 10.0,
                    x0: float = -2.0, p0: float = 0.0,
-                   sigma: float = 1.0 / np.sqrt(2.0)) -> Model:
+                   sigma: float = 1.0 / np.sqrt(2.0), v22_cap: float | None = None) -> Model:
     """1D two-surface diabatic model with a Gaussian on surface 1.
 
     V11 = 0.5 (x+1)^2, V22 = 0.1 (1 - exp(-0.8 (x-1.5)))^2 + 0.3,
-    V12 = 0.05 exp(-x^2/2); mass 1.
+    V12 = 0.05 exp(-x^2/2); mass 1.  V22 reaches about 1e7 Ha at x = -10;
+    v22_cap, if given, clips it there (min(V22, v22_cap)).
     """
     x = lo + np.arange(n) * ((hi - lo) / n)
     v11 = 0.5 * (x + 1.0) ** 2
     v22 = 0.1 * (1.0 - np.exp(-0.8 * (x - 1.5))) ** 2 + 0.3
+    if v22_cap is not None:
+        v22 = np.minimum(v22, v22_cap)
     v12 = 0.05 * np.exp(-x**2 / 2.0)
     vt = np.stack([v11, v12, v22]).astype(np.float64)
     psi = np.zeros((2, n), dtype=np.complex128)
     psi[0] = gaussian_1d(x, x0, p0, sigma)
     psi = normalise(psi, (hi - lo) / n)
     return Model([n], [lo], [hi], 2, [1.0], vt, psi,
-                 meta={"name": "two_surface_1d", "x0": x0, "p0": p0, "sigma": sigma})
+                 meta={"name": "two_surface_1d", "x0": x0, "p0": p0, "sigma": sigma,
+                       "v22_cap": v22_cap})
 
 
 # ----------------------------------------------------------------- 3D LVC
