@@ -440,3 +440,57 @@ def test_3d_plane_pass_equals_three_passes(torch_cuda, n, c64):
     kinds = a.timing_read()
     a.set_timing(False)
     assert "plane" in kinds and "ypass" not in kinds and "xpass" not in kinds
+
+
+# ------------------------------------------------------------------ eigen form
+def test_3d_eigen_form_and_table_fallback(torch_cuda, orc):
+    """3D FP64 plans of three surfaces hold the compact eigen form of V (one
+    table); a plan whose phases |tau lam| would leave the range of the phase
+    routine (1e6) keeps per-coefficient tables instead.  Both match the
+    oracle; the tolerance of the large-phase case is 1e-14 + 8 eps times the
+    summed phase magnitude, since each side rounds every phase argument."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32)
+    plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=10.0)
+    assert plan.info.n_v_tables == 1
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate(psi, 3)
+    ref = oracle_run(orc, m, "VTV", "triple_jump", 4, 10.0, 3)
+    assert rel_l2(psi.cpu().numpy(), ref) < FP64_TOL
+    # the same model with V scaled up: 2 max|tau| max|lam| > 1e6
+    big = synth.Model(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable * 3.0e5, m.psi0, meta={})
+    dt = 10.0
+    pb = soprop.Plan.from_model(big, comp="triple_jump", order=4, dt=dt)
+    assert pb.info.n_v_tables > 1  # per-coefficient tables
+    psi = torch.from_numpy(big.psi0.copy()).cuda()
+    pb.propagate(psi, 1)
+    refb = oracle_run(orc, big, "VTV", "triple_jump", 4, dt, 1)
+    lam = np.abs(big.vtable).reshape(6, -1).sum(axis=0).max()
+    gam = np.abs(orc.gammas(orc.TRIPLE_JUMP, 4)).sum()
+    tol = 1e-14 + 8 * EPS * gam * dt * lam
+    err = rel_l2(psi.cpu().numpy(), refb)
+    print(f"[eigen fallback] err {err:.3e} tol {tol:.3e}")
+    assert err < tol
+
+
+def test_set_params_beyond_phase_range_is_refused(torch_cuda):
+    """An eigen-form plan refuses parameters that could take a phase beyond
+    the routine's range, and keeps its state."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32, dv_params=True)
+    v0 = synth.lvc_vtable_theta(m, np.zeros(3))
+    plan = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, comp="strang", order=2,
+                       dt=10.0, dvtables=m.dvtables)
+    assert plan.info.n_v_tables == 1
+    theta = np.array([c[3] for c in m.meta["couplings"]])
+    plan.set_params(theta)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate(psi, 2)
+    a = psi.cpu().numpy()
+    with pytest.raises(soprop.SopError):
+        plan.set_params(np.array([1.0e9, 0.0, 0.0]))
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate(psi, 2)
+    np.testing.assert_array_equal(psi.cpu().numpy(), a)
