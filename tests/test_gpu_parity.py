@@ -305,8 +305,8 @@ def test_3d_parity(torch_cuda, orc, n, S, comp, order, nsteps):
 @pytest.mark.parametrize("split,comp,order", [("TVT", "triple_jump", 4), ("TVT", "strang", 2),
                                               ("VT", "strang", 1), ("TV", "strang", 1)])
 def test_3d_other_splittings(torch_cuda, orc, split, comp, order):
-    """TVT steps end and begin with a kinetic action: two adjacent kinetic
-    actions share one z round trip."""
+    """TVT steps end and begin with a kinetic action (two kinetic actions in a
+    row at every step boundary); VT and TV are the first-order splittings."""
     torch = torch_cuda
     m = synth.lvc_3d(n=32)
     got, _ = gpu_run(torch, m, split, comp, order, 10.0, 3)
