@@ -47,12 +47,17 @@ struct AdjSched<Z256> {
   using type = Sched<256, 4, RList<4, 4, 4, 4>, RList<4, 4, 4, 4>, 4, 4>;
 };
 
-// Columns per tile of the z-pass: the table tile width, or half of it on
-// 64^3, where 16-column tiles give one workgroup per compute unit (smaller
-// grids keep 16 columns: half a tile would be half a wave).
+// Columns per tile of the z-pass: the table tile width, or half of it
+//   on 64^3, where 16-column tiles give one workgroup per compute unit
+//   (smaller grids keep 16 columns: half a tile would be half a wave);
+//   on 256^3, where 16 columns make 512-thread workgroups of ~200 VGPRs
+//   (two per SIMD); 256-thread ones schedule better (556 vs 586 us a pass
+//   for 256^3 x 3 FP64).
 template <class SC, typename T>
 constexpr int zcols() {
-  return (SC::N == 64 && SC::TPC * kTableCols / 2 >= 64) ? kTableCols / 2 : kTableCols;
+  if (SC::N == 64 && SC::TPC * kTableCols / 2 >= 64) return kTableCols / 2;
+  if (SC::N == 256) return kTableCols / 2;
+  return kTableCols;
 }
 
 // ---------------------------------------------------------------- z-pass
