@@ -98,13 +98,12 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
 #pragma unroll
           for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, guard<GUARD>(t0));
         }
-        const cx<T>* F = kin + (size_t)idx * N;
+        const cx<T>* F = kin + (size_t)idx * N * Split<T>::rep;
 #pragma unroll
         for (int q = 0; q < E; ++q) {
-          cx<T> f = F[own_idx<N, E, SC::RL>(t, q)];
-          f.im *= csign;
+          const Fac<T> f = load_fac(F, own_idx<N, E, SC::RL>(t, q), csign);
 #pragma unroll
-          for (int s = 0; s < S; ++s) v[s][q] = cmul(v[s][q], f);
+          for (int s = 0; s < S; ++s) v[s][q] = fmul(v[s][q], f);
         }
         if constexpr (PL == S) {
           fft_inverse<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));

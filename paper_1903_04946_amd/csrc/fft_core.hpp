@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace sop {
 
 template <typename T>
@@ -45,7 +47,68 @@ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
   return {a.im, -a.re};
 }
 
+// ----------------------------------------------------------------- FP32 products
+// In FP32 every fixed unit-modulus factor -- a twiddle, a radix constant such
+// as cos(pi/4), a kinetic factor -- rounds to a value whose modulus is off 1
+// by the same amount at every application.  Within one transform that is
+// harmless, but the time step applies the same factors thousands of times,
+// and the deterministic bias compounds into a norm drift linear in the number
+// of substeps (about 1e-7 a substep at 32^3, mostly loss: the rounded twiddles
+// of small transforms all lie inside the unit circle), far above the
+// random-walk growth of ordinary roundings.  FP32 products with such factors
+// therefore carry the rounding residue lo = value - rounded: x (w + lo) is
+// formed with fused multiply-adds, so the only roundings are those of the
+// sums, which have no preferred sign.  FP32 plans store every twiddle and
+// kinetic factor as the pair (rounded, residue), 16 bytes read by one load:
+// a block of n factors holds Split<float>::rep * n complex values.
+template <typename T>
+struct Split {
+  static constexpr int rep = 1;
+};
+template <>
+struct Split<float> {
+  static constexpr int rep = 2;
+};
+
+// A factor read from a (split) table, conjugated when csign = -1.
+template <typename T>
+struct Fac {
+  cx<T> w;
+};
+template <>
+struct Fac<float> {
+  cx<float> w, lo;
+};
+typedef float sop_f32x4 __attribute__((ext_vector_type(4)));
+// Entry i of a factor block.
+template <typename T>
+__device__ __forceinline__ Fac<T> load_fac(const cx<T>* __restrict__ f, int i, T csign) {
+  Fac<T> F;
+  if constexpr (std::is_same<T, float>::value) {
+    const sop_f32x4 q = *reinterpret_cast<const sop_f32x4*>(f + 2 * i);
+    F.w = {q.x, csign * q.y};
+    F.lo = {q.z, csign * q.w};
+  } else {
+    F.w = f[i];
+    F.w.im *= csign;
+  }
+  return F;
+}
+// a (w + lo): the residue terms enter below the rounded products.
+__device__ __forceinline__ cx<float> cmul_lo(cx<float> a, cx<float> w, cx<float> lo) {
+  const float cr = __builtin_fmaf(a.re, lo.re, -a.im * lo.im);
+  const float ci = __builtin_fmaf(a.re, lo.im, a.im * lo.re);
+  return {__builtin_fmaf(a.re, w.re, __builtin_fmaf(-a.im, w.im, cr)),
+          __builtin_fmaf(a.re, w.im, __builtin_fmaf(a.im, w.re, ci))};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> fmul(cx<T> a, const Fac<T>& F) {
+  if constexpr (std::is_same<T, float>::value) return cmul_lo(a, F.w, F.lo);
+  else return cmul(a, F.w);
+}
+
 // ----------------------------------------------------------------- radix DFTs
+// Radix constants; in FP32 with their rounding residues (K<float>::*_lo).
 template <typename T>
 struct K {
   static constexpr T r2 = (T)0.70710678118654752440084436210484903928;   // cos(pi/4)
@@ -53,6 +116,35 @@ struct K {
   static constexpr T s8 = (T)0.38268343236508977172845998403039886676;   // sin(pi/8)
   static constexpr T s3 = (T)0.86602540378443864676372317075293618347;   // sin(pi/3)
 };
+template <>
+struct K<float> {
+  static constexpr double R2 = 0.70710678118654752440084436210484903928;
+  static constexpr double C8 = 0.92387953251128675612818318939678828682;
+  static constexpr double S8 = 0.38268343236508977172845998403039886676;
+  static constexpr double S3 = 0.86602540378443864676372317075293618347;
+  static constexpr float r2 = (float)R2, r2_lo = (float)(R2 - (double)r2);
+  static constexpr float c8 = (float)C8, c8_lo = (float)(C8 - (double)c8);
+  static constexpr float s8 = (float)S8, s8_lo = (float)(S8 - (double)s8);
+  static constexpr float s3 = (float)S3, s3_lo = (float)(S3 - (double)s3);
+};
+template <typename T> __device__ __forceinline__ constexpr T lo_r2() {
+  if constexpr (std::is_same<T, float>::value) return K<float>::r2_lo; else return (T)0;
+}
+template <typename T> __device__ __forceinline__ constexpr T lo_c8() {
+  if constexpr (std::is_same<T, float>::value) return K<float>::c8_lo; else return (T)0;
+}
+template <typename T> __device__ __forceinline__ constexpr T lo_s8() {
+  if constexpr (std::is_same<T, float>::value) return K<float>::s8_lo; else return (T)0;
+}
+template <typename T> __device__ __forceinline__ constexpr T lo_s3() {
+  if constexpr (std::is_same<T, float>::value) return K<float>::s3_lo; else return (T)0;
+}
+// x * constant (hi + lo in FP32)
+template <typename T>
+__device__ __forceinline__ T mulk(T x, T hi, T lo) {
+  if constexpr (std::is_same<T, float>::value) return __builtin_fmaf(x, hi, x * lo);
+  else return x * hi;
+}
 
 template <bool INV, typename T>
 __device__ __forceinline__ void dft2(cx<T>* v) {
@@ -67,7 +159,8 @@ __device__ __forceinline__ void dft3(cx<T>* v) {
   cx<T> s = cadd(v[1], v[2]);
   cx<T> d = csub(v[1], v[2]);
   cx<T> h = {v[0].re - (T)0.5 * s.re, v[0].im - (T)0.5 * s.im};
-  cx<T> e = mul_mi<INV>(cx<T>{d.re * K<T>::s3, d.im * K<T>::s3});
+  const T k3 = K<T>::s3, k3l = lo_s3<T>();
+  cx<T> e = mul_mi<INV>(cx<T>{mulk(d.re, k3, k3l), mulk(d.im, k3, k3l)});
   v[0] = cadd(v[0], s);
   v[1] = cadd(h, e);
   v[2] = csub(h, e);
@@ -86,16 +179,22 @@ __device__ __forceinline__ void dft4(cx<T>* v) {
 // x * exp(-+ i pi/4)
 template <bool INV, typename T>
 __device__ __forceinline__ cx<T> w8_1(cx<T> a) {
-  const T r = K<T>::r2;
-  if (INV) return {(a.re - a.im) * r, (a.re + a.im) * r};
-  return {(a.re + a.im) * r, (a.im - a.re) * r};
+  const T r = K<T>::r2, rl = lo_r2<T>();
+  if (INV) return {mulk(a.re - a.im, r, rl), mulk(a.re + a.im, r, rl)};
+  return {mulk(a.re + a.im, r, rl), mulk(a.im - a.re, r, rl)};
 }
 // x * exp(-+ 3 i pi/4)
 template <bool INV, typename T>
 __device__ __forceinline__ cx<T> w8_3(cx<T> a) {
-  const T r = K<T>::r2;
-  if (INV) return {-(a.re + a.im) * r, (a.re - a.im) * r};
-  return {(a.im - a.re) * r, -(a.re + a.im) * r};
+  const T r = K<T>::r2, rl = lo_r2<T>();
+  if (INV) return {-mulk(a.re + a.im, r, rl), mulk(a.re - a.im, r, rl)};
+  return {mulk(a.im - a.re, r, rl), -mulk(a.re + a.im, r, rl)};
+}
+// x * (c + i s) for a radix constant pair
+template <typename T>
+__device__ __forceinline__ cx<T> cmulk(cx<T> a, T c, T s, T cl, T sl) {
+  if constexpr (std::is_same<T, float>::value) return cmul_lo(a, {c, s}, {cl, sl});
+  else return cmul(a, cx<T>{c, s});
 }
 
 template <bool INV, typename T>
@@ -124,16 +223,16 @@ __device__ __forceinline__ void dft16(cx<T>* v) {
   }
   dft8<INV>(e);
   dft8<INV>(o);
-  const T c = K<T>::c8, s = K<T>::s8;
+  const T c = K<T>::c8, s = K<T>::s8, cl = lo_c8<T>(), sl = lo_s8<T>();
   const T sg = INV ? (T)1 : (T)-1;  // sign of the imaginary part of the twiddle
   // o[k] *= exp(sg * i * 2 pi k / 16), k = 1..7
-  o[1] = cmul(o[1], cx<T>{c, sg * s});
+  o[1] = cmulk(o[1], c, sg * s, cl, sg * sl);
   o[2] = w8_1<INV>(o[2]);
-  o[3] = cmul(o[3], cx<T>{s, sg * c});
+  o[3] = cmulk(o[3], s, sg * c, sl, sg * cl);
   o[4] = mul_mi<INV>(o[4]);
-  o[5] = cmul(o[5], cx<T>{-s, sg * c});
+  o[5] = cmulk(o[5], -s, sg * c, -sl, sg * cl);
   o[6] = w8_3<INV>(o[6]);
-  o[7] = cmul(o[7], cx<T>{-c, sg * s});
+  o[7] = cmulk(o[7], -c, sg * s, -cl, sg * sl);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     v[k] = cadd(e[k], o[k]);
@@ -246,9 +345,8 @@ __device__ __forceinline__ void stage(cx<T> (&v)[E], int t, const cx<T>* __restr
       const int k = j % L;
 #pragma unroll
       for (int m = 1; m < R; ++m) {
-        cx<T> w = tw[(k * m) * (N / (L * R))];
-        if (INV) w.im = -w.im;
-        v[b * R + m] = cmul(v[b * R + m], w);
+        const Fac<T> w = load_fac(tw, (k * m) * (N / (L * R)), INV ? (T)-1 : (T)1);
+        v[b * R + m] = fmul(v[b * R + m], w);
       }
     }
     dft<R, INV>(&v[b * R]);

@@ -71,8 +71,9 @@ __global__ void __launch_bounds__(C * SC::TPC)
   const BMember3 m = mem[mi];
   if (c >= m.cycles) return;
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  ypass_body<T, SC, C, AX_KIN>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + SC::N,
-                               cycle_kin<T>(m, c, 1), m.conj, lds, blockIdx.x, blockIdx.y);
+  const cx<T>* tw = (const cx<T>*)m.tw + SC::N * Split<T>::rep;  // the y block
+  ypass_body<T, SC, C, AX_KIN>((cx<T>*)m.psi + s * npts, tw, cycle_kin<T>(m, c, 1), m.conj, lds,
+                               blockIdx.x, blockIdx.y);
 }
 
 // x-pass of cycle c: grid (N / ROWS, N, S x members).
@@ -85,8 +86,9 @@ __global__ void __launch_bounds__(ROWS * SC::TPC)
   const BMember3 m = mem[mi];
   if (c >= m.cycles) return;
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  xpass_body<T, SC, ROWS, AX_KIN>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw + 2 * SC::N,
-                                  cycle_kin<T>(m, c, 2), m.conj, lds, blockIdx.x, blockIdx.y);
+  const cx<T>* tw = (const cx<T>*)m.tw + 2 * SC::N * Split<T>::rep;  // the x block
+  xpass_body<T, SC, ROWS, AX_KIN>((cx<T>*)m.psi + s * npts, tw, cycle_kin<T>(m, c, 2), m.conj,
+                                  lds, blockIdx.x, blockIdx.y);
 }
 
 // fused xy plane pass of cycle c: grid (N planes, S x members).

@@ -79,16 +79,15 @@ constexpr int kTableCols = 16;
 enum { AX_NONE = 0, AX_KIN = 1, AX_FWD = 2 };
 
 // v (forward-transformed, radix-RL ownership) *= f[k] (conjugated factor
-// when conj): the kinetic factor of one axis.
+// when conj): the kinetic factor of one axis (a split block in FP32).
 template <typename T, class SC, int P>
 __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __restrict__ f,
                                            T csign, int t) {
 #pragma unroll
   for (int q = 0; q < SC::E; ++q) {
-    cx<T> w = f[own_idx<SC::N, SC::E, SC::RL>(t, q)];
-    w.im *= csign;
+    const Fac<T> w = load_fac(f, own_idx<SC::N, SC::E, SC::RL>(t, q), csign);
 #pragma unroll
-    for (int p = 0; p < P; ++p) v[p][q] = cmul(v[p][q], w);
+    for (int p = 0; p < P; ++p) v[p][q] = fmul(v[p][q], w);
   }
 }
 
@@ -321,8 +320,9 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   const int tr = lane % TPC, row = lane / TPC;  // row layout
   constexpr int64_t plane = (int64_t)N * N;
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
-  const cx<T>* twy = tw + N;
-  const cx<T>* twx = tw + 2 * N;
+  constexpr int AS = N * Split<T>::rep;  // axis stride of the twiddle and factor blocks
+  const cx<T>* twy = tw + AS;
+  const cx<T>* twx = tw + 2 * AS;
   const LayStrided lcol{col, 0, N};
   const LayPadded lrow{row * P, 0};
   const T csign = conj ? (T)-1 : (T)1;
@@ -331,7 +331,7 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(tc, q) * N + col);
   fft_forward<SC, 1>(v, lds, lcol, twy, tc);
-  axis_phase<T, SC, 1>(v, kin + N, csign, tc);
+  axis_phase<T, SC, 1>(v, kin + AS, csign, tc);
   fft_inverse<SC, 1>(v, lds, lcol, twy, tc);
   // columns -> rows
 #pragma unroll
@@ -342,7 +342,7 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   __syncthreads();
   // x round trip (rows)
   fft_forward<SC, 1>(v, lds, lrow, twx, tr);
-  axis_phase<T, SC, 1>(v, kin + 2 * N, csign, tr);
+  axis_phase<T, SC, 1>(v, kin + 2 * AS, csign, tr);
   fft_inverse<SC, 1>(v, lds, lrow, twx, tr);
 #pragma unroll
   for (int q = 0; q < E; ++q) st(base, row * N + own_idx<N, E, SC::RF>(tr, q), v[0][q]);

@@ -283,16 +283,28 @@ hipError_t form_tables(sop_plan* p) {
   return sop::form_vexp(p->dv, p->d_vraw, p->d_taus, (int)p->vtaus.size(), p->tile, p->d_vexp);
 }
 
-// Rounds interleaved extended-precision values to the plan precision.
-std::vector<char> pack(const std::vector<ld>& v, bool f64) {
-  std::vector<char> out(v.size() * (f64 ? 8 : 4));
+// Rounds blocks of n interleaved extended-precision complex values to the
+// plan precision.  In FP32 each value becomes the pair (rounded, residue =
+// value - rounded), which the FP32 kernels fold into their products with
+// these factors.
+std::vector<char> pack_split(const std::vector<ld>& v, bool f64, int n) {
   if (f64) {
+    std::vector<char> out(v.size() * sizeof(double));
     double* d = reinterpret_cast<double*>(out.data());
     for (size_t i = 0; i < v.size(); ++i) d[i] = (double)v[i];
-  } else {
-    float* f = reinterpret_cast<float*>(out.data());
-    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)(double)v[i];
+    return out;
   }
+  const size_t nb = v.size() / (2 * (size_t)n);
+  std::vector<char> out(nb * (size_t)n * 4 * sizeof(float));
+  float* f = reinterpret_cast<float*>(out.data());
+  for (size_t b = 0; b < nb; ++b)
+    for (int k = 0; k < n; ++k)
+      for (int c = 0; c < 2; ++c) {
+        const ld x = v[(b * n + k) * 2 + c];
+        const float hi = (float)(double)x;
+        f[((b * n + k) * 2) * 2 + c] = hi;
+        f[((b * n + k) * 2 + 1) * 2 + c] = (float)(double)(x - (ld)hi);
+      }
   return out;
 }
 
@@ -445,8 +457,9 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   const size_t tbytes = p->eig_form ? (size_t)sop::eig_slots(S) * p->npts * 2 * sizeof(double)
                                     : vc.size() * NE * p->npts * p->csize;
   const int nax = p->ndim == 1 ? 1 : 3;
-  const size_t kbytes = tc.size() * nax * p->n[0] * p->csize;
-  const size_t wbytes = (size_t)nax * p->n[0] * p->csize;
+  const int rep = f64 ? 1 : 2;  // FP32 factor blocks carry their residues
+  const size_t kbytes = tc.size() * nax * p->n[0] * p->csize * rep;
+  const size_t wbytes = (size_t)nax * p->n[0] * p->csize * rep;
   if (hipMalloc(&p->d_vraw, vbytes) != hipSuccess || hipMalloc(&p->d_vexp, tbytes) != hipSuccess ||
       hipMalloc(&p->d_kin, kbytes) != hipSuccess || hipMalloc(&p->d_tw, wbytes) != hipSuccess ||
       hipMalloc((void**)&p->d_prog, prog.size() * sizeof(int)) != hipSuccess ||
@@ -467,7 +480,8 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
       tw[((size_t)a * p->n[0] + k) * 2] = std::cos(ang);
       tw[((size_t)a * p->n[0] + k) * 2 + 1] = std::sin(ang);
     }
-  std::vector<char> twp = pack(tw, f64), kinp = pack(kinetic_factors(p, p->ttaus), f64);
+  std::vector<char> twp = pack_split(tw, f64, p->n[0]);
+  std::vector<char> kinp = pack_split(kinetic_factors(p, p->ttaus), f64, p->n[0]);
   const int prog1[2] = {sop::prog_entry(sop::OP_V, 0), sop::prog_entry(sop::OP_T, 0)};
   HIPTRY(hipMemcpyAsync(p->d_vraw, desc->vtable, vbytes, hipMemcpyHostToDevice, stream));
   HIPTRY(hipMemcpyAsync(p->d_tw, twp.data(), wbytes, hipMemcpyHostToDevice, stream));
@@ -487,9 +501,9 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   d.stream = stream;
   d.vexp = p->d_vexp;
   d.kin = p->d_kin;
-  d.kin_stride = p->n[0];
+  d.kin_stride = p->n[0] * rep;
   for (int a = 0; a < 3; ++a)
-    d.tw[a] = (const char*)p->d_tw + (size_t)(a < nax ? a : 0) * p->n[0] * p->csize;
+    d.tw[a] = (const char*)p->d_tw + (size_t)(a < nax ? a : 0) * p->n[0] * p->csize * rep;
   d.prog = p->d_prog;
   d.nact = (int)prog.size();
   d.hprog = prog;
@@ -663,9 +677,10 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
     }
   } else {
     const int nax = p->ndim == 1 ? 1 : 3;
-    const size_t kb = (size_t)nax * p->n[0] * p->csize;
+    const size_t kb = (size_t)nax * p->n[0] * p->csize * (d.f64 ? 1 : 2);
     if (!p->d_akin) HIPTRY(hipMalloc(&p->d_akin, kb));
-    std::vector<char> kp = pack(kinetic_factors(p, {(double)((ld)coef * (ld)p->dt)}), d.f64);
+    std::vector<char> kp =
+        pack_split(kinetic_factors(p, {(double)((ld)coef * (ld)p->dt)}), d.f64, p->n[0]);
     HIPTRY(hipMemcpyAsync(p->d_akin, kp.data(), kb, hipMemcpyHostToDevice, d.stream));
     d.kin = p->d_akin;
     d.prog = p->d_prog1 + 1;

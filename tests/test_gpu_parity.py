@@ -339,6 +339,26 @@ def test_3d_64_fp32(torch_cuda, orc):
     assert err < 1e-5
 
 
+def test_fp32_error_growth_32cube_sf4(torch_cuda, orc):
+    """FP32 round-off over many substeps: 32^3 x 3 LVC, SF-4 at dt = 500/128,
+    128 steps (640 substeps), against the FP64 oracle at the same scheme and
+    dt, so the splitting error cancels.  The FP32 products with twiddles,
+    radix constants and kinetic factors carry those factors' rounding
+    residues, so no fixed modulus bias compounds from substep to substep:
+    the error grows like a random walk.  Stated bounds: 1e-5 relative L2 and
+    a norm change below 1e-6 (plain rounded factors drift about 1e-7 a
+    substep, 6e-5 here)."""
+    torch = torch_cuda
+    m = synth.lvc_3d(n=32)
+    got, plan = gpu_run(torch, m, "VTV", "suzuki", 4, 500.0 / 128, 128, dtype=torch.complex64)
+    ref = oracle_run(orc, m, "VTV", "suzuki", 4, 500.0 / 128, 128)
+    err = rel_l2(got, ref)
+    drift = np.linalg.norm(got) / np.linalg.norm(ref) - 1
+    print(f"[fp32] 32^3 SF-4, 640 substeps: error {err:.3e}, norm change {drift:.3e}")
+    assert err < 1e-5
+    assert abs(drift) < 1e-6
+
+
 def test_3d_reversibility(torch_cuda):
     torch = torch_cuda
     from paper_1903_04946_amd import soprop
