@@ -155,6 +155,10 @@ sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int ca
  * which each potential action forms exp(-i tau lam) in FP64; they do so when
  * every phase |tau lam| (bounded by the Gershgorin row sums of the V-table)
  * stays within 1e6, and keep the per-coefficient tables otherwise.
+ * SOP_C64 plans keep each twiddle and kinetic factor as its FP32 rounding
+ * plus the rounding residue, which their products fold in: a fixed rounded
+ * unit-modulus factor would otherwise bias the norm the same way at every
+ * substep.
  * hip_stream: a hipStream_t or NULL.  Synchronises the stream.  *out
  * receives the plan. */
 sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out);
