@@ -201,6 +201,19 @@ sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev,
  * The table for coef is formed on the fly into the plan's scratch. */
 sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
 
+/* Replaces the plan's V-table (host FP64, [S(S+1)/2][npts], the layout of
+ * sop_plan_desc.vtable) and forms the potential tables again on the device,
+ * in the same buffers, so captured graphs and batches that hold the plan stay
+ * valid.  For a plan with parameters the new table is V at theta = 0 and the
+ * current theta applies on top of it.  The unitaries exp(-i tau V) of the
+ * sequence are tables of V (Sec. "Pruning splitting coefficients": formed
+ * once, reused by every step); this forms them for another V of the same
+ * grid and surfaces.  Synchronises.  SOP_ERR_INVALID for a NULL or
+ * non-finite table; SOP_ERR_UNSUPPORTED if the plan holds the eigen form and
+ * the new V could take a phase |tau lam| beyond its range (then nothing
+ * changes). */
+sop_status sop_plan_update_v(sop_plan* plan, const double* vtable);
+
 /* Sets the parameters: V <- vtable + sum_k theta[k] dvtables[k], and forms the
  * potential tables again on the device (theta: host, [nparams]).
  * Synchronises.  SOP_ERR_STATE if the plan has no parameters;

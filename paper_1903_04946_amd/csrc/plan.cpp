@@ -200,6 +200,7 @@ struct sop_plan {
   double* d_vbase = nullptr;  // V at theta = 0
   double* d_dv = nullptr;     // [nparams][NE][npts]
   double* d_theta = nullptr;  // [nparams]
+  std::vector<double> theta;  // host copy of the current parameters
   void* d_eig = nullptr;      // adjoint eigen table (FP64, tile layout)
   double* d_w = nullptr;      // [S] adjoint weights
   sop::GraphCache* graphs = nullptr;
@@ -274,6 +275,13 @@ bool phases_fit(const sop_plan* p, double vbound, double extra_tau = 0.0) {
   double tmax = std::fabs(extra_tau);
   for (double t : p->vtaus) tmax = std::max(tmax, 2.0 * std::fabs(t));
   return tmax * vbound <= sop::kPhaseMax;
+}
+
+// Bound on |lam| of V = V0 + sum_k theta_k D_k from the bound of V0.
+double param_bound(const sop_plan* p, double v0bound, const double* theta) {
+  double b = v0bound;
+  for (int k = 0; k < p->nparams; ++k) b += std::fabs(theta[k]) * p->dvbound[k];
+  return b;
 }
 
 // Forms the potential tables of the plan from its raw V-table on the device:
@@ -534,6 +542,9 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
     }
     HIPTRY(hipMemcpyAsync(p->d_vbase, p->d_vraw, vbytes, hipMemcpyDeviceToDevice, stream));
     HIPTRY(hipMemcpyAsync(p->d_dv, desc->dvtables, dvb, hipMemcpyHostToDevice, stream));
+    p->theta.assign(p->nparams, 0.0);  // the V-table is V at theta = 0
+    HIPTRY(hipMemcpyAsync(p->d_theta, p->theta.data(), p->nparams * sizeof(double),
+                          hipMemcpyHostToDevice, stream));
     if (p->ndim == 3 && f64 && sop::k3d_adjoint_supported(p->n[0], S, f64)) {
       if (hipMalloc(&p->d_eig, (size_t)NE * p->npts * sizeof(double) * 2) != hipSuccess) {
         (void)hipGetLastError();
@@ -701,19 +712,41 @@ sop_status sop_plan_set_params(sop_plan* p, const double* theta) {
   if (p->nparams == 0) return fail(SOP_ERR_STATE, "plan has no parameters");
   for (int k = 0; k < p->nparams; ++k)
     if (!std::isfinite(theta[k])) return fail(SOP_ERR_INVALID, "theta must be finite");
-  if (p->eig_form) {  // |lam(theta)| <= bound(V0) + sum_k |theta_k| bound(D_k)
-    double b = p->vbound;
-    for (int k = 0; k < p->nparams; ++k) b += std::fabs(theta[k]) * p->dvbound[k];
-    if (!phases_fit(p, b))
-      return fail(SOP_ERR_UNSUPPORTED,
-                  "these parameters take the phases tau*lambda beyond the eigen form's range");
-  }
+  if (p->eig_form && !phases_fit(p, param_bound(p, p->vbound, theta)))
+    return fail(SOP_ERR_UNSUPPORTED,
+                "these parameters take the phases tau*lambda beyond the eigen form's range");
   hipStream_t st = p->dv.stream;
   HIPTRY(hipMemcpyAsync(p->d_theta, theta, p->nparams * sizeof(double), hipMemcpyHostToDevice, st));
   HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
   HIPTRY(form_tables(p));
   if (p->d_eig) HIPTRY(sop::form_eig(p->dv, p->d_vraw, p->tile, p->d_eig));
   HIPTRY(hipStreamSynchronize(st));
+  p->theta.assign(theta, theta + p->nparams);
+  return SOP_OK;
+}
+
+sop_status sop_plan_update_v(sop_plan* p, const double* vtable) {
+  if (!p || !vtable) return fail(SOP_ERR_INVALID, "NULL argument");
+  const int NE = p->S * (p->S + 1) / 2;
+  const size_t nv = (size_t)NE * p->npts;
+  for (size_t i = 0; i < nv; ++i)
+    if (!std::isfinite(vtable[i])) return fail(SOP_ERR_INVALID, "vtable must be finite");
+  const double vb = p->eig_form ? gershgorin_bound(vtable, p->S, p->npts) : 0.0;
+  if (p->eig_form && !phases_fit(p, param_bound(p, vb, p->theta.data())))
+    return fail(SOP_ERR_UNSUPPORTED,
+                "this V-table takes the phases tau*lambda beyond the eigen form's range");
+  hipStream_t st = p->dv.stream;
+  const size_t vbytes = nv * sizeof(double);
+  if (p->nparams > 0) {
+    HIPTRY(hipMemcpyAsync(p->d_vbase, vtable, vbytes, hipMemcpyHostToDevice, st));
+    HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
+  } else {
+    HIPTRY(hipMemcpyAsync(p->d_vraw, vtable, vbytes, hipMemcpyHostToDevice, st));
+  }
+  HIPTRY(form_tables(p));
+  if (p->d_eig) HIPTRY(sop::form_eig(p->dv, p->d_vraw, p->tile, p->d_eig));
+  HIPTRY(hipStreamSynchronize(st));
+  if (p->eig_form) p->vbound = vb;
   return SOP_OK;
 }
 

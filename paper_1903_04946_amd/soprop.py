@@ -51,6 +51,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
+           "sop_plan_update_v",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
            "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
@@ -86,6 +87,7 @@ def lib():
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
+    L.sop_plan_update_v.argtypes = [vp, dp]
     L.sop_propagate_many.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
     L.sop_plan_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sop_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int,
@@ -103,7 +105,7 @@ def lib():
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
               "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
-              "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
+              "sop_plan_update_v", "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
               "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
               "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
               "sop_batch_describe"):
@@ -229,6 +231,15 @@ class Plan:
         """V <- vtable + sum_k theta_k dvtables[k]; tables formed again."""
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.nparams)
         _check(lib().sop_plan_set_params(self._h, _dp(th)), "sop_plan_set_params")
+
+    def update_v(self, vtable):
+        """Replaces the V-table ([S(S+1)/2][npts] FP64) and forms the tables again."""
+        vt = np.ascontiguousarray(vtable, dtype=np.float64)
+        if vt.size != self._vt.size:
+            raise ValueError("vtable must hold S(S+1)/2 x npts values")
+        vt = vt.reshape(self._vt.shape)
+        _check(lib().sop_plan_update_v(self._h, _dp(vt)), "sop_plan_update_v")
+        self._vt = vt
 
     def adjoint_workspace_bytes(self, nsteps: int, K: int) -> int:
         b = ctypes.c_size_t()

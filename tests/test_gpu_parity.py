@@ -494,6 +494,54 @@ def test_3d_eigen_form_and_table_fallback(torch_cuda, orc):
     assert err < tol
 
 
+@pytest.mark.parametrize("kind", ["3d_eigen", "3d_fp32", "1d", "3d_params"])
+def test_update_v(torch_cuda, orc, kind):
+    """sop_plan_update_v: a plan built for one V-table and given another
+    propagates like a plan built for the second (oracle parity at the FP64
+    bar, 1e-5 for FP32); with parameters, the new table is V at theta = 0
+    and the current theta still applies; a table whose phases leave the
+    eigen form's range is refused and changes nothing."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    dtype, tol, nsteps = torch.complex128, FP64_TOL, 2
+    if kind == "1d":
+        a = synth.random_small([256], 2, seed=11, lo=-6, hi=6)
+        b = synth.random_small([256], 2, seed=12, lo=-6, hi=6)
+        kw = dict(comp="suzuki", order=4, dt=0.05)
+    else:
+        a = synth.lvc_3d(n=32, dv_params=(kind == "3d_params"))
+        b = synth.lvc_3d(n=32, couplings=[(0, 1, 0, 0.1), (0, 2, 1, 0.07), (1, 2, 2, 0.3)])
+        kw = dict(comp="triple_jump", order=4, dt=10.0)
+        if kind == "3d_fp32":
+            dtype, tol = torch.complex64, 1e-5
+    if kind == "3d_params":
+        theta = np.array([0.02, -0.03, 0.1])
+        v0 = synth.lvc_vtable_theta(a, np.zeros(3))
+        plan = soprop.Plan(a.n, a.lo, a.hi, a.nsurf, a.inv_mass, v0, dvtables=a.dvtables, **kw)
+        plan.set_params(theta)
+        plan.update_v(b.vtable)
+        vt = b.vtable + np.tensordot(theta, a.dvtables, axes=1)
+    else:
+        plan = soprop.Plan.from_model(a, dtype=dtype, **kw)
+        plan.update_v(b.vtable)
+        vt = b.vtable
+    # the plan keeps its grid and masses (a's); only V changes
+    target = synth.Model(a.n, a.lo, a.hi, a.nsurf, a.inv_mass, vt, b.psi0, meta={})
+    psi = torch.from_numpy(b.psi0.copy()).to(dtype).cuda()
+    plan.propagate(psi, nsteps)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref = oracle_run(orc, target, "VTV", kw["comp"], kw["order"], kw["dt"], nsteps,
+                     psi0=b.psi0)
+    assert rel_l2(got, ref) < tol
+    if kind == "3d_eigen":
+        assert plan.info.n_v_tables == 1
+        with pytest.raises(soprop.SopError):
+            plan.update_v(b.vtable * 1.0e9)
+        psi2 = torch.from_numpy(b.psi0.copy()).cuda()
+        plan.propagate(psi2, nsteps)
+        np.testing.assert_array_equal(psi2.cpu().numpy(), got)
+
+
 def test_set_params_beyond_phase_range_is_refused(torch_cuda):
     """An eigen-form plan refuses parameters that could take a phase beyond
     the routine's range, and keeps its state."""
