@@ -94,8 +94,10 @@ __global__ void __launch_bounds__(C * SC::TPC)
 // pass then applies the adjoint z factor K_z^dag (conjugated f_z) to all 2S
 // pencils.
 // The pass tile is C columns of the TC-column table tiles (C divides TC).
+// Two waves per SIMD: with six pencils of state the three-surface pass needs
+// about 200-250 VGPRs, and a one-wave budget let the compiler take more.
 template <class SC, int S, int C, int TC, bool KZ>
-__global__ void __launch_bounds__(C * SC::TPC)
+__global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_eu(2)))
     k3d_zpass_adj(cx<double>* __restrict__ stk, const cx<double>* __restrict__ eig,
                   double* __restrict__ qacc,
                   const double* __restrict__ taus, int nv, int iv0, int iv1,
@@ -163,48 +165,48 @@ __global__ void __launch_bounds__(C * SC::TPC)
         c[a] = cx<double>{cs, -sn};
       }
       // U_j^dag = R conj(D) R^T with D_a = exp(-i tau lam_a) = c_a^2:
-      // beta = R^T psi_{j-1} = conj(D) gamma, and R^T lambda_{j-1} = conj(D) alpha
-      cx<double> be[S], al1[S];
+      // beta = R^T psi_{j-1} = conj(D) gamma, formed in place of gamma (the
+      // temporaries of one point are kept few: with the six pencils of the
+      // stacked state they decide how many waves a SIMD holds)
+#pragma unroll
+      for (int a = 0; a < S; ++a) ga[a] = cmul(cconj(cmul(c[a], c[a])), ga[a]);
+      // T = R Re(M) with M_ab = conj(alpha_a) F_ab beta_b, accumulated entry by
+      // entry (F_ab = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2))
+      // sinc(h_ab) is symmetric in (a, b): one value per pair a < b, chosen
+      // without a branch between the series and the quotient
+      double sinc[S][S];
 #pragma unroll
       for (int a = 0; a < S; ++a) {
-        const cx<double> dc = cconj(cmul(c[a], c[a]));
-        be[a] = cmul(dc, ga[a]);
-        al1[a] = cmul(dc, al[a]);
-      }
-      double rm[S][S];  // Re(M)
+        sinc[a][a] = 1.0;
 #pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S; ++b) {
-          // F_ab = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2)
-          double sc = 1.0;
-          if (a != b) {
-            const double h = 0.5 * tau * (lam[a] - lam[b]);
-            if (fabs(h) < 1e-2) {
-              const double h2 = h * h;
-              sc = 1.0 - h2 * (1.0 / 6.0 - h2 * (1.0 / 120.0 - h2 * (1.0 / 5040.0)));
-            } else {
-              const double sh = c[b].im * c[a].re - c[b].re * c[a].im;  // Im(c_b conj(c_a))
-              sc = sh / h;
-            }
-          }
-          const cx<double> e2 = cmul(c[a], c[b]);
-          // -i tau sc e2
-          const cx<double> F = {tau * sc * e2.im, -tau * sc * e2.re};
-          const cx<double> fb = cmul(F, be[b]);
-          rm[a][b] = al[a].re * fb.re + al[a].im * fb.im;  // Re(conj(alpha_a) F_ab beta_b)
+        for (int b = a + 1; b < S; ++b) {
+          const double h = 0.5 * tau * (lam[a] - lam[b]);
+          const double h2 = h * h;
+          const double ser = 1.0 - h2 * (1.0 / 6.0 - h2 * (1.0 / 120.0 - h2 * (1.0 / 5040.0)));
+          const double sh = c[b].im * c[a].re - c[b].re * c[a].im;  // Im(c_b conj(c_a))
+          const double quo = sh / h;
+          sinc[a][b] = sinc[b][a] = fabs(h) < 1e-2 ? ser : quo;
         }
-      // Q = R Re(M) R^T (T = R Re(M) first), accumulated packed
+      }
       double tq[S][S];
 #pragma unroll
       for (int i = 0; i < S; ++i)
 #pragma unroll
-        for (int b = 0; b < S; ++b) {
-          double acc = 0.0;
+        for (int b = 0; b < S; ++b) tq[i][b] = 0.0;
 #pragma unroll
-          for (int a = 0; a < S; ++a) acc += ev[i * S + a] * rm[a][b];
-          tq[i][b] = acc;
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+          const double sc = sinc[a][b];
+          const cx<double> e2 = cmul(c[a], c[b]);
+          // -i tau sc e2
+          const cx<double> F = {tau * sc * e2.im, -tau * sc * e2.re};
+          const cx<double> fb = cmul(F, ga[b]);
+          const double rm = al[a].re * fb.re + al[a].im * fb.im;  // Re(M_ab)
+#pragma unroll
+          for (int i = 0; i < S; ++i) tq[i][b] += ev[i * S + a] * rm;
         }
+      // Q = T R^T, accumulated packed
       int e = 0;
 #pragma unroll
       for (int i = 0; i < S; ++i)
@@ -222,13 +224,15 @@ __global__ void __launch_bounds__(C * SC::TPC)
         }
       // psi_{j-1} = R beta, lambda_{j-1} = R conj(D) alpha
 #pragma unroll
+      for (int a = 0; a < S; ++a) al[a] = cmul(cconj(cmul(c[a], c[a])), al[a]);
+#pragma unroll
       for (int i = 0; i < S; ++i) {
         cx<double> p = {0.0, 0.0}, l = {0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < S; ++a) {
           const double r = ev[i * S + a];
-          p = cx<double>{p.re + r * be[a].re, p.im + r * be[a].im};
-          l = cx<double>{l.re + r * al1[a].re, l.im + r * al1[a].im};
+          p = cx<double>{p.re + r * ga[a].re, p.im + r * ga[a].im};
+          l = cx<double>{l.re + r * al[a].re, l.im + r * al[a].im};
         }
         v[i][q] = p;
         v[S + i][q] = l;
@@ -545,8 +549,10 @@ struct Passes {
   static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1,
                        int tidx) {
     using SA = typename AdjSched<SC>::type;
-    // at most 256 threads per block (four waves: each may hold 512 registers)
-    constexpr int CA = (256 / SA::TPC < kTableCols) ? 256 / SA::TPC : kTableCols;
+    // 256 threads per block, but at least 8 columns (128-byte row segments;
+    // 512 threads at 256^3, two waves per SIMD as the register budget allows)
+    constexpr int CA0 = (256 / SA::TPC < kTableCols) ? 256 / SA::TPC : kTableCols;
+    constexpr int CA = CA0 < 8 ? 8 : CA0;
     auto k = k3d_zpass_adj<SA, S, CA, kTableCols, KZ>;
     const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
