@@ -519,6 +519,12 @@ def adjoint_cpu_baseline(M):
                       f"table formation included)"}
 
 
+def _rel_l2_dev(torch, a, b):
+    """||a - b|| / ||b|| on the device, in FP64."""
+    a64 = a.to(torch.complex128)
+    return float(torch.linalg.vector_norm(a64 - b) / torch.linalg.vector_norm(b))
+
+
 def run_ensemble(a, torch, soprop):
     """One step = one batch propagate call advancing all 256 members of the
     ensemble to t_final (uneven step counts), as one graph launch."""
@@ -571,6 +577,23 @@ def run_ensemble(a, torch, soprop):
         b3 += ((per * cyc + 1) * 2 * m.nsurf + tab) * m.npts * cs
     ach3 = b3 / (parts["3d"]["ms"] / 1e3) / 1e9
     norms = [p.observables(x)["norm"] for p, x in zip(plans, psis)]
+    fp32 = None
+    if dtype == torch.complex64:
+        # every member's FP32 error after one call, against the same call in FP64
+        p64 = [soprop.Plan.from_model(m, comp=e["scheme"], order=e["order"], dt=e["dt"],
+                                      dtype=torch.complex128) for e, m in zip(man, models)]
+        b64 = soprop.Batch(p64)
+        r64 = [torch.from_numpy(m.psi0).cuda() for m in models]
+        r32 = [torch.from_numpy(m.psi0).to(dtype).cuda() for m in models]
+        b64.propagate(r64, ns)
+        batch.propagate(r32, ns)
+        torch.cuda.synchronize()
+        errs = [_rel_l2_dev(torch, x, y) for x, y in zip(r32, r64)]
+        fp32 = {"calls": 1, "max_rel_l2_vs_fp64": max(errs),
+                "median_rel_l2_vs_fp64": float(sorted(errs)[len(errs) // 2])}
+        b64.close()
+        for p in p64:
+            p.close()
     cpu = None if a.no_cpu_baseline else ensemble_cpu_baseline(models, man, Ms)
     counts = {}
     for e in man:
@@ -598,7 +621,8 @@ def run_ensemble(a, torch, soprop):
                                                 "tuned_ms", "max_cycles", "chains")}
                              | {"members": len(g["members"])} for g in desc["groups"]]},
         "cpu_baseline": cpu,
-        "checks": {"norm_max_dev": max(abs(x - 1) for x in norms), "wall_s_timed": wall},
+        "checks": {"norm_max_dev": max(abs(x - 1) for x in norms), "wall_s_timed": wall}
+        | ({} if fp32 is None else {"fp32_error": fp32}),
     }
 
 
@@ -695,6 +719,22 @@ def main(argv=None) -> int:
                    "alg_GBps": v["bytes"] / (scale * v["ms"] / 1e3) / 1e9}
                for k, v in kt.items()}
 
+    fp32 = None
+    if dtype == torch.complex64:
+        # The FP32 form's error, stated with the result: the same K steps from
+        # psi0 in FP32 and in FP64 (the FP64 path is held to the FP64 oracle
+        # within 1e-12 by the parity tests).
+        p64 = soprop.Plan.from_model(model, comp=comp, order=order, dt=dt,
+                                     dtype=torch.complex128)
+        r64 = torch.from_numpy(model.psi0).cuda()
+        p64.propagate(r64, a.steps)
+        r32 = torch.from_numpy(model.psi0).to(dtype).cuda()
+        plan.propagate(r32, a.steps)
+        torch.cuda.synchronize()
+        fp32 = {"steps": a.steps, "rel_l2_vs_fp64": _rel_l2_dev(torch, r32, r64)}
+        p64.close()
+        del r64, r32
+
     copy_gbps = stream_copy_gbps(torch) if ndim == 3 else None
     cpu = None
     if not a.no_cpu_baseline:
@@ -727,7 +767,8 @@ def main(argv=None) -> int:
         "kernels": kernels,
         "cpu_baseline": cpu,
         "time_to_error": tte,
-        "checks": {"norm_after": norm, "wall_s_timed": wall},
+        "checks": {"norm_after": norm, "wall_s_timed": wall}
+        | ({} if fp32 is None else {"fp32_error": fp32}),
         "kernel_source_hash": kernel_source_hash(),
     }
     if ndim == 1:
