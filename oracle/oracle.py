@@ -80,9 +80,11 @@ def lib():
                                    ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp, dp]
         L.orc_observables.argtypes = [pp, dp, dp]
         L.orc_overlap.argtypes = [pp, dp, dp, dp]
+        L.orc_distance.argtypes = [pp, dp, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
+                  "orc_distance",
                   "orc_exact", "orc_propagate_timed", "orc_threads", "orc_expm_frechet",
                   "orc_gradient"):
             getattr(L, f).restype = ctypes.c_int
@@ -264,6 +266,18 @@ def overlap(prob: Problem, psi: np.ndarray, phi: np.ndarray) -> complex:
     out = np.zeros(2)
     lib().orc_overlap(prob.ptr(), _dp(a.view(np.float64)), _dp(b.view(np.float64)), _dp(out))
     return complex(out[0], out[1])
+
+
+def distance(prob: Problem, psi: np.ndarray, phi: np.ndarray) -> float:
+    """||psi - phi|| with the volume element (the error norm of the paper's
+    convergence studies)."""
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape)
+    b = np.ascontiguousarray(phi, dtype=np.complex128).reshape(prob.shape)
+    out = np.zeros(1)
+    if lib().orc_distance(prob.ptr(), _dp(a.view(np.float64)), _dp(b.view(np.float64)),
+                          _dp(out)) != 0:
+        raise ValueError("oracle distance rejected its arguments")
+    return float(out[0])
 
 
 def exact(prob: Problem, psi: np.ndarray, t: float) -> np.ndarray:

@@ -732,6 +732,22 @@ int orc_overlap(const orc_problem* prob, const double* psi_in, const double* phi
   return 0;
 }
 
+// L2 distance ||psi - phi|| = sqrt(sum |psi - phi|^2 dV), the error norm of
+// the convergence studies (Sec. "Numerical examples"), from the difference
+// itself: the expansion ||psi||^2 + ||phi||^2 - 2 Re<psi|phi> cancels
+// catastrophically when the two states agree closely.
+int orc_distance(const orc_problem* prob, const double* psi_in, const double* phi_in,
+                 double* out) {
+  Grid g;
+  if (!make_grid(prob, g)) return -1;
+  const cd* psi = reinterpret_cast<const cd*>(psi_in);
+  const cd* phi = reinterpret_cast<const cd*>(phi_in);
+  ld d2 = 0;
+  for (int64_t i = 0; i < (int64_t)g.S * g.npts; ++i) d2 += (ld)std::norm(psi[i] - phi[i]);
+  out[0] = (double)std::sqrt(d2 * (ld)g.dV);
+  return 0;
+}
+
 // ---------------------------------------------------------------- brute force
 // Exact evolution exp(-i H t / hbar) psi for the discrete Hamiltonian on
 // tiny grids (Eq. exact_evol_op): H = K (x) 1_S + blockdiag V(x), where the

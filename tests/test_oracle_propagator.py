@@ -241,6 +241,28 @@ def test_overlap_matches_numpy(orc):
     assert abs(orc.overlap(P, m.psi0, phi) - ref) < 1e-14
 
 
+def test_distance_pins(orc):
+    """||psi - phi|| from the difference: a global phase e^{i t} gives
+    |1 - e^{i t}| ||psi|| = 2 |sin(t/2)| ||psi|| (closed form); a state and a
+    copy perturbed by 1e-12 give the perturbation's norm (up to the rounding
+    of the perturbed copy), where the expansion through the overlap
+    (||psi||^2 + ||phi||^2 - 2 Re<psi|phi>) cancels to round-off; the
+    distance is symmetric and zero for equal states."""
+    m = synth.random_small([8, 8], 2, seed=4)
+    P = problem(orc, m)
+    nrm = np.sqrt(np.vdot(m.psi0.ravel(), m.psi0.ravel()).real * m.dV)
+    for t in (1e-9, 0.3, np.pi):
+        d = orc.distance(P, m.psi0, np.exp(1j * t) * m.psi0)
+        assert abs(d - 2 * abs(np.sin(t / 2)) * nrm) < 1e-15 * max(1.0, 1 / t) * nrm * 8
+    dpsi = 1e-12 * synth.random_state(m.psi0.shape, 7, m.dV)
+    d = orc.distance(P, m.psi0 + dpsi, m.psi0)
+    ref = np.sqrt(np.vdot(dpsi.ravel(), dpsi.ravel()).real * m.dV)
+    assert abs(d - ref) < 4e-16 * nrm  # the rounding of psi + dpsi itself
+    assert orc.distance(P, m.psi0, m.psi0) == 0.0
+    phi = synth.random_state(m.psi0.shape, 6, m.dV)
+    assert orc.distance(P, m.psi0, phi) == orc.distance(P, phi, m.psi0)
+
+
 # ------------------------------------------------------------------ invariants
 def test_geometric_invariants_1d(orc):
     """Norm, symplectic form and time reversibility (Fig. 8 analogue)."""
