@@ -196,6 +196,14 @@ sop_status sop_observables(sop_plan* plan, const void* psi_dev, double* out);
  * The symplectic two-form is -2 hbar Im<psi|phi>.  Synchronises. */
 sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev, double* out);
 
+/* L2 distance between two states of the plan's shape and dtype:
+ * out[0] = ||psi - phi|| = sqrt(sum |psi - phi|^2 dV), out[1] = ||psi - phi|| /
+ * ||phi|| (0 when phi = 0); host, [2].  The error norm of the convergence
+ * studies (Sec. "Numerical examples"), formed from the difference in FP64
+ * (the expansion through sop_overlap would cancel when the states agree
+ * closely).  Fixed-order reduction; synchronises. */
+sop_status sop_distance(sop_plan* plan, const void* psi_dev, const void* phi_dev, double* out);
+
 /* Applies one action to psi (testing aid; asynchronous): op = 0 potential
  * exp(-i tau V/hbar) with tau = coef * dt, op = 1 kinetic exp(-i tau T/hbar).
  * The table for coef is formed on the fly into the plan's scratch. */

@@ -194,6 +194,8 @@ hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
                       double hbar, double* partials_dev, double* out_dev);
 hipError_t overlap_reduce(const DevView& d, const void* psi, const void* phi,
                           double* partials_dev, double* out_dev);
+hipError_t distance_reduce(const DevView& d, const void* psi, const void* phi,
+                          double* partials_dev, double* out_dev);
 hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* out);
 // compact eigen form, eig_slots(S) slots per point in the z-pass tile layout
 hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out);

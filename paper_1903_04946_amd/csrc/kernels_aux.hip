@@ -229,6 +229,23 @@ __global__ void __launch_bounds__(kReduceThreads)
   block_sum<2>(acc, partials + (size_t)blockIdx.x * 2);
 }
 
+// sum |a - b|^2 and sum |b|^2, the difference taken in FP64 from the
+// stored values.
+template <typename T>
+__global__ void __launch_bounds__(kReduceThreads)
+    k_distance(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, int64_t n,
+               double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kReduceThreads) {
+    const cx<T> p = a[i], q = b[i];
+    const double dr = (double)p.re - (double)q.re, di = (double)p.im - (double)q.im;
+    acc[0] += dr * dr + di * di;
+    acc[1] += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
+  }
+  block_sum<2>(acc, partials + (size_t)blockIdx.x * 2);
+}
+
 // Sums nblocks rows of nv partials in a fixed order into out[nv].
 __global__ void __launch_bounds__(kReduceThreads)
     k_final(const double* __restrict__ partials, int nblocks, int nv, double* __restrict__ out) {
@@ -567,6 +584,22 @@ hipError_t pops_reduce(const DevView& d, const void* psi, const double* vraw_dev
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials, kReduceBlocks,
                      d.S + 1, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t distance_reduce(const DevView& d, const void* psi, const void* phi, double* partials,
+                           double* out_dev) {
+  const int64_t n = d.npts * d.S;
+  if (d.f64)
+    hipLaunchKernelGGL(k_distance<double>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                       d.stream, (const cx<double>*)psi, (const cx<double>*)phi, n, partials);
+  else
+    hipLaunchKernelGGL(k_distance<float>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                       d.stream, (const cx<float>*)psi, (const cx<float>*)phi, n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kReduceThreads), 0, d.stream, partials, kReduceBlocks,
+                     2, out_dev);
   return hipGetLastError();
 }
 

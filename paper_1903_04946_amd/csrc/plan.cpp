@@ -665,6 +665,17 @@ sop_status sop_overlap(sop_plan* p, const void* psi, const void* phi, double* ou
   return SOP_OK;
 }
 
+sop_status sop_distance(sop_plan* p, const void* psi, const void* phi, double* out) {
+  if (!p || !psi || !phi || !out) return fail(SOP_ERR_INVALID, "NULL argument");
+  HIPTRY(sop::distance_reduce(p->dv, psi, phi, p->d_part, p->d_out));
+  double raw[2];
+  HIPTRY(hipMemcpyAsync(raw, p->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, p->dv.stream));
+  HIPTRY(hipStreamSynchronize(p->dv.stream));
+  out[0] = std::sqrt(raw[0] * p->dV);
+  out[1] = raw[1] > 0.0 ? std::sqrt(raw[0] / raw[1]) : 0.0;
+  return SOP_OK;
+}
+
 sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
   if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
   if (op != 0 && op != 1) return fail(SOP_ERR_INVALID, "op must be 0 (V) or 1 (T)");

@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
            "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
+           "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+           "sop_plan_set_params",
            "sop_plan_update_v",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
@@ -84,6 +85,7 @@ def lib():
     L.sop_propagate.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int]
     L.sop_observables.argtypes = [vp, vp, dp]
     L.sop_overlap.argtypes = [vp, vp, vp, dp]
+    L.sop_distance.argtypes = [vp, vp, vp, dp]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
@@ -104,7 +106,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_size_t)]
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_apply_action", "sop_plan_set_timing", "sop_timing_read", "sop_plan_set_params",
+              "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+              "sop_plan_set_params",
               "sop_plan_update_v", "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
               "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
               "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
@@ -366,6 +369,15 @@ class Plan:
         _check(lib().sop_overlap(self._h, ctypes.c_void_p(psi.data_ptr()),
                                  ctypes.c_void_p(phi.data_ptr()), _dp(out)), "sop_overlap")
         return complex(out[0], out[1])
+
+    def distance(self, psi, phi) -> tuple:
+        """(||psi - phi||, ||psi - phi|| / ||phi||) with the volume element."""
+        self._check_psi(psi)
+        self._check_psi(phi)
+        out = np.zeros(2)
+        _check(lib().sop_distance(self._h, ctypes.c_void_p(psi.data_ptr()),
+                                  ctypes.c_void_p(phi.data_ptr()), _dp(out)), "sop_distance")
+        return float(out[0]), float(out[1])
 
 
 class Batch:

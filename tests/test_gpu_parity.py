@@ -542,6 +542,35 @@ def test_update_v(torch_cuda, orc, kind):
         np.testing.assert_array_equal(psi2.cpu().numpy(), got)
 
 
+@pytest.mark.parametrize("c64", [False, True])
+def test_distance(torch_cuda, orc, c64):
+    """sop_distance against the oracle's distance on the same stored values:
+    a propagated state against the initial one, and a state against a copy
+    perturbed by 1e-12 relative (where the overlap expansion would cancel).
+    The relative output is the absolute one over ||phi||."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    dtype = torch.complex64 if c64 else torch.complex128
+    m = synth.lvc_3d(n=32)
+    plan = soprop.Plan.from_model(m, comp="strang", order=2, dt=10.0, dtype=dtype)
+    P = oracle_problem(orc, m)
+    psi0 = torch.from_numpy(m.psi0.copy()).to(dtype).cuda()
+    psi = psi0.clone()
+    plan.propagate(psi, 3)
+    pert = 1e-12 if not c64 else 1e-5
+    noise = torch.from_numpy(synth.random_state(m.psi0.shape, 3, m.dV)).to(dtype).cuda()
+    noisy = psi0 + pert * noise
+    for a, b in ((psi, psi0), (noisy, psi0)):
+        got, rel = plan.distance(a, b)
+        an = a.cpu().numpy().astype(np.complex128)
+        bn = b.cpu().numpy().astype(np.complex128)
+        ref = orc.distance(P, an, bn)
+        assert abs(got - ref) < 1e-13 * ref + 1e-300
+        nb = np.sqrt(np.vdot(bn.ravel(), bn.ravel()).real * m.dV)
+        assert abs(rel - ref / nb) < 1e-13 * rel
+    assert plan.distance(psi0, psi0) == (0.0, 0.0)
+
+
 def test_set_params_beyond_phase_range_is_refused(torch_cuda):
     """An eigen-form plan refuses parameters that could take a phase beyond
     the routine's range, and keeps its state."""
