@@ -735,6 +735,27 @@ def main(argv=None) -> int:
         p64.close()
         del r64, r32
 
+    # Whole-step byte accounting (3D): the passes' algorithmic bytes per unit
+    # and the lower bound of one z-pencil round trip carrying the potential
+    # plus one xy-plane round trip (the state read and written twice per
+    # substep, the potential tables once), each as a fraction of the HBM peak
+    # at the measured step time.
+    step_bytes = None
+    if ndim == 3:
+        units = units_per_step * a.steps
+        cs = 16 if dts == "c128" else 8
+        total = sum(v["bytes"] for v in kt.values())
+        zk = kt.get("zpass")
+        tables = 0.0
+        if zk is not None:  # z-pass bytes beyond its state round trips
+            tables = zk["bytes"] - zk["count"] * 2.0 * model.nsurf * model.npts * cs
+        lb = 4.0 * cs * units + tables
+        sec = ms / 1e3
+        step_bytes = {"design_bytes_per_unit": total / units,
+                      "design_frac": total / sec / 1e9 / HBM_PEAK_GBS,
+                      "lower_bound_bytes_per_unit": lb / units,
+                      "lower_bound_frac": lb / sec / 1e9 / HBM_PEAK_GBS}
+
     copy_gbps = stream_copy_gbps(torch) if ndim == 3 else None
     cpu = None
     if not a.no_cpu_baseline:
@@ -765,6 +786,7 @@ def main(argv=None) -> int:
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch,
                      "stream_copy_GBps": copy_gbps},
         "kernels": kernels,
+        "step_bytes": step_bytes,
         "cpu_baseline": cpu,
         "time_to_error": tte,
         "checks": {"norm_after": norm, "wall_s_timed": wall}
