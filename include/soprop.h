@@ -36,7 +36,8 @@
  * Streams and synchronisation
  *   All device work is enqueued on the HIP stream given at plan creation
  *   (NULL = the default stream).  sop_propagate is asynchronous.
- *   sop_plan_create, sop_observables and sop_overlap synchronise the stream
+ *   sop_plan_create, sop_plan_update_v, sop_plan_set_params,
+ *   sop_observables, sop_overlap and sop_distance synchronise the stream
  *   before returning.
  *
  * Errors
