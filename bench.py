@@ -116,9 +116,19 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
     else:
         sec = sec1
     units = model.nsurf * model.npts * substeps_per_step * steps
+    # the same step loop on one thread (one step: the single-thread rate is
+    # the all-core rate over roughly the thread count)
+    all_threads = threads
+    O.set_threads(1)
+    try:
+        _, sec_1t, _ = O.propagate_timed(P, model.psi0, O.VTV, comp_id, order, dt, 1)
+    finally:
+        O.set_threads(all_threads)
+    units_1t = model.nsurf * model.npts * substeps_per_step
     return {"value": units / sec, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"{steps} step(s) x {substeps_per_step} substeps of the same workload, "
-                      f"FP64 oracle step loop ({sec:.2f} s, plan-time eigendecomposition excluded)"}
+                      f"FP64 oracle step loop ({sec:.2f} s, plan-time eigendecomposition excluded)",
+            "single_thread": {"value": units_1t / sec_1t, "sample": f"1 step ({sec_1t:.2f} s)"}}
 
 
 def stream_copy_gbps(torch, nbytes=1 << 30, reps=5):

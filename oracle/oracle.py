@@ -74,6 +74,7 @@ def lib():
         L.orc_propagate_timed.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_expm_frechet.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double,
                                        dp, dp]
         L.orc_gradient.argtypes = [pp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
@@ -85,7 +86,8 @@ def lib():
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
                   "orc_distance",
-                  "orc_exact", "orc_propagate_timed", "orc_threads", "orc_expm_frechet",
+                  "orc_exact", "orc_propagate_timed", "orc_threads", "orc_set_threads",
+                  "orc_expm_frechet",
                   "orc_gradient"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -200,6 +202,13 @@ def propagate(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: in
     if rc != 0:
         raise ValueError("oracle propagate rejected its arguments")
     return a
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops; returns the count now in use."""
+    if lib().orc_set_threads(int(n)) != 0:
+        raise ValueError("thread count must be >= 1")
+    return int(lib().orc_threads())
 
 
 def propagate_timed(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: int,

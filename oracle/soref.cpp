@@ -638,6 +638,16 @@ int orc_propagate_timed(const orc_problem* prob, int split, int scheme, int orde
   return 0;
 }
 
+// Sets the number of threads of the OpenMP loops (n >= 1; no effect without
+// OpenMP).  For timing the oracle single-threaded and on all cores.
+int orc_set_threads(int n) {
+  if (n < 1) return -1;
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#endif
+  return 0;
+}
+
 // Number of threads the OpenMP loops use (1 without OpenMP).
 int orc_threads(void) {
 #ifdef _OPENMP
