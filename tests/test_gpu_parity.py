@@ -379,6 +379,17 @@ def test_3d_256_strang(torch_cuda, orc):
     assert rel_l2(got, ref) < FP64_TOL
 
 
+def test_3d_256_tj6_bench_shape(torch_cuda, orc):
+    """256^3 x 3, TJ-6 VTV, dt = 10, two steps (the step-boundary z-pass
+    carries two potential actions): the launch configuration of the 256^3
+    benchmark, against the oracle at the FP64 bar."""
+    torch = torch_cuda
+    m = synth.lvc_3d(n=256)
+    got, _ = gpu_run(torch, m, "VTV", "triple_jump", 6, 10.0, 2)
+    ref = oracle_run(orc, m, "VTV", "triple_jump", 6, 10.0, 2)
+    assert rel_l2(got, ref) < FP64_TOL
+
+
 def test_propagate_many_equals_single_runs(torch_cuda):
     """Several states of one plan in one launch: each equals its single run."""
     torch = torch_cuda
