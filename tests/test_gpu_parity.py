@@ -553,6 +553,35 @@ def test_update_v(torch_cuda, orc, kind):
         np.testing.assert_array_equal(psi2.cpu().numpy(), got)
 
 
+def test_update_v_keeps_graphs_and_batches_valid(torch_cuda):
+    """Tables are formed again in place: a plan whose steps were captured in
+    HIP graphs, and a batch that holds it, propagate with the new V at the
+    next call (bitwise equal to a plan built for the new V)."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    a = synth.lvc_3d(n=32)
+    b = synth.lvc_3d(n=32, couplings=[(0, 1, 0, 0.1), (1, 2, 2, 0.3)])
+    kw = dict(comp="suzuki", order=4, dt=10.0)
+    plan = soprop.Plan.from_model(a, **kw)
+    other = soprop.Plan.from_model(synth.lvc_3d(n=32, q0=(0.5, 0.0, 0.0)), **kw)
+    batch = soprop.Batch([plan, other])
+    warm = [torch.from_numpy(a.psi0.copy()).cuda(), torch.from_numpy(a.psi0.copy()).cuda()]
+    plan.propagate(warm[0], 6)           # graph-captured segments
+    batch.propagate(warm, [6, 6])        # the batch graph
+    plan.update_v(b.vtable)
+    fresh = soprop.Plan.from_model(b, **kw)
+    ref = torch.from_numpy(b.psi0.copy()).cuda()
+    fresh.propagate(ref, 6)
+    got = torch.from_numpy(b.psi0.copy()).cuda()
+    plan.propagate(got, 6)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy())
+    pair = [torch.from_numpy(b.psi0.copy()).cuda(), torch.from_numpy(a.psi0.copy()).cuda()]
+    batch.propagate(pair, [6, 6])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pair[0].cpu().numpy(), ref.cpu().numpy())
+
+
 @pytest.mark.parametrize("c64", [False, True])
 def test_distance(torch_cuda, orc, c64):
     """sop_distance against the oracle's distance on the same stored values:
