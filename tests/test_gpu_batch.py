@@ -284,9 +284,11 @@ def test_batch_every_variant_matches_oracle(torch_cuda, orc):
             os.environ["SOPROP_TUNE_CACHE"] = old
 
 
-def test_ensemble_manifest_bench_shape(torch_cuda):
+def test_ensemble_manifest_bench_shape(torch_cuda, orc):
     """The 256-member ensemble the benchmark times (FP64): sampled members
-    equal their single-plan runs, every member keeps its norm."""
+    equal their single-plan runs, the cheapest 3D member and the most and
+    least expensive 1D members match the oracle, every member keeps its
+    norm."""
     torch = torch_cuda
     from paper_1903_04946_amd import soprop
     man = synth.batch_manifest()
@@ -316,6 +318,19 @@ def test_ensemble_manifest_bench_shape(torch_cuda):
             assert rel_l2(a, b) < FP64_TOL, f"member {i}"
     for i, (p, x) in enumerate(zip(plans, psis)):
         assert abs(p.observables(x)["norm"] - 1.0) < 1e-10, f"member {i}"
+    kinds = [e["kind"] for e in man]
+    c1 = [c if k == "1d" else np.inf for c, k in zip(cost, kinds)]
+    c3 = [c if k == "3d" else np.inf for c, k in zip(cost, kinds)]
+    c1max = [c if k == "1d" else -1 for c, k in zip(cost, kinds)]
+    for i in sorted({int(np.argmin(c3)), int(np.argmin(c1)), int(np.argmax(c1max))}):
+        m, e = models[i], man[i]
+        P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
+        ref = orc.propagate(P, m.psi0, SPLIT_ID["VTV"], COMP_ID[e["scheme"]], e["order"],
+                            e["dt"], ns[i])
+        err = rel_l2(psis[i].cpu().numpy(), ref)
+        print(f"[ensemble] member {i} {e['kind']} n={e['n']} {e['scheme']}-{e['order']} "
+              f"nsteps={ns[i]}: {err:.2e} vs oracle", flush=True)
+        assert err < FP64_TOL, f"member {i}"
 
 
 def test_batch_plane_pass_equals_three_passes(torch_cuda):
