@@ -652,7 +652,7 @@ def main(argv=None) -> int:
                     help="first run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path "
               f"(asked for --gpus {a.gpus}).", file=sys.stderr)
         return 2
 
