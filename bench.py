@@ -101,6 +101,20 @@ def traffic_from_profiles(workload: str, kernel_kind: str):
         return None
 
 
+def _host_cpu():
+    """CPU model and logical CPU count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
     """Times the FP64 oracle's step loop on this host (all OpenMP threads)."""
     from oracle import oracle as O
@@ -126,6 +140,7 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
         O.set_threads(all_threads)
     units_1t = model.nsurf * model.npts * substeps_per_step
     return {"value": units / sec, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "host": _host_cpu(),
             "sample": f"{steps} step(s) x {substeps_per_step} substeps of the same workload, "
                       f"FP64 oracle step loop ({sec:.2f} s, plan-time eigendecomposition excluded)",
             "single_thread": {"value": units_1t / sec_1t, "sample": f"1 step ({sec_1t:.2f} s)"}}
@@ -417,6 +432,7 @@ def ensemble_cpu_baseline(models, man, Ms, budget_s=10.0):
         if sec > budget_s:
             break
     return {"value": units / sec, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "host": _host_cpu(),
             "sample": f"one step of each of the first {used} ensemble members "
                       f"({sec:.2f} s of FP64 oracle step loops)"}
 
@@ -522,7 +538,8 @@ def adjoint_cpu_baseline(M):
     t0 = time.perf_counter()
     O.gradient(P, m.dvtables, m.psi0, O.VTV, O.TRIPLE_JUMP, 6, 10.0, 1, [0.0, 0.0, 1.0])
     sec = time.perf_counter() - t0
-    return {"value": m.nsurf * m.npts * M / sec, "unit": UNIT, "cores": int(O.lib().orc_threads()),
+    return {"value": m.nsurf * m.npts * M / sec, "unit": UNIT, "host": _host_cpu(),
+            "cores": int(O.lib().orc_threads()),
             "kind": "oracle",
             "sample": f"tangent-mode gradient of P_3 w.r.t. the 3 couplings, one TJ-6 step "
                       f"({M} substeps) of the same model on a 32^3 grid ({sec:.1f} s, "
