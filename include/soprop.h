@@ -164,6 +164,27 @@ sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int ca
  * receives the plan. */
 sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out);
 
+/* Device memory hooks for a plan: alloc(ctx, bytes, stream) returns device
+ * memory usable on `stream` (NULL on failure), free(ctx, ptr, stream) takes
+ * it back; `stream` is the hip_stream given at creation.  With hooks, every
+ * device buffer the plan owns -- tables, factors, programs, reduction and
+ * scratch space -- comes from alloc and goes back through free when the
+ * plan is destroyed (after sop_plan_destroy has synchronised the plan's
+ * stream), so that a framework's caching allocator (PyTorch's) owns the
+ * memory.  Batches and HIP graph objects keep their own small allocations. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} sop_allocator;
+
+/* sop_plan_create with device memory from `allocator` (NULL: hipMalloc, the
+ * same as sop_plan_create).  SOP_ERR_INVALID if only one hook is set;
+ * SOP_ERR_NOMEM if alloc returns NULL.  The hooks must stay callable until
+ * sop_plan_destroy returns. */
+sop_status sop_plan_create_with_allocator(const sop_plan_desc* desc, void* hip_stream,
+                                          const sop_allocator* allocator, sop_plan** out);
+
 /* Frees the plan's device memory.  NULL is accepted. */
 sop_status sop_plan_destroy(sop_plan* plan);
 

@@ -205,6 +205,8 @@ struct sop_plan {
   double* d_w = nullptr;      // [S] adjoint weights
   sop::GraphCache* graphs = nullptr;
   bool use_graphs = true;
+  sop_allocator hook{};  // device memory hooks (alloc == NULL: hipMalloc/hipFree)
+  hipStream_t home = nullptr;  // the creation stream, handed to the hooks
 };
 
 namespace sop {
@@ -214,14 +216,35 @@ void set_last_error(const std::string& msg) { g_err = msg; }
 
 namespace {
 
+// Device buffers of a plan: through the caller's hooks when given.
+hipError_t dalloc(sop_plan* p, void** ptr, size_t bytes) {
+  if (p->hook.alloc) {
+    *ptr = p->hook.alloc(p->hook.ctx, bytes, (void*)p->home);
+    return *ptr ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(ptr, bytes);
+}
+template <typename T>
+hipError_t dalloc(sop_plan* p, T** ptr, size_t bytes) {
+  void* v = nullptr;
+  const hipError_t e = dalloc(p, &v, bytes);
+  *ptr = (T*)v;
+  return e;
+}
+
 void free_plan(sop_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
                   p->d_dv, p->d_theta, p->d_eig, p->d_w};
   delete p->graphs;
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  for (void* b : bufs) {
+    if (!b) continue;
+    if (p->hook.free)
+      p->hook.free(p->hook.ctx, b, (void*)p->home);
+    else
+      (void)hipFree(b);
+  }
   delete p->timer;
   delete p;
 }
@@ -345,7 +368,7 @@ sop_status validate(const sop_plan_desc* d) {
 }
 
 sop_status ensure_scratch(sop_plan* p) {
-  if (!p->d_scratch) HIPTRY(hipMalloc(&p->d_scratch, (size_t)p->S * p->npts * p->csize));
+  if (!p->d_scratch) HIPTRY(dalloc(p, &p->d_scratch, (size_t)p->S * p->npts * p->csize));
   return SOP_OK;
 }
 
@@ -399,11 +422,20 @@ sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int ca
 }
 
 sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out) {
+  return sop_plan_create_with_allocator(desc, hip_stream, nullptr, out);
+}
+
+sop_status sop_plan_create_with_allocator(const sop_plan_desc* desc, void* hip_stream,
+                                          const sop_allocator* allocator, sop_plan** out) {
   if (!out) return fail(SOP_ERR_INVALID, "out is NULL");
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return fail(SOP_ERR_INVALID, "an allocator needs both alloc and free");
   sop_status st = validate(desc);
   if (st != SOP_OK) return st;
   sop_plan* p = new (std::nothrow) sop_plan();
   if (!p) return fail(SOP_ERR_NOMEM, "host allocation failed");
+  if (allocator) p->hook = *allocator;
+  p->home = (hipStream_t)hip_stream;
   struct Guard {
     sop_plan* p;
     bool keep = false;
@@ -468,13 +500,15 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   const int rep = f64 ? 1 : 2;  // FP32 factor blocks carry their residues
   const size_t kbytes = tc.size() * nax * p->n[0] * p->csize * rep;
   const size_t wbytes = (size_t)nax * p->n[0] * p->csize * rep;
-  if (hipMalloc(&p->d_vraw, vbytes) != hipSuccess || hipMalloc(&p->d_vexp, tbytes) != hipSuccess ||
-      hipMalloc(&p->d_kin, kbytes) != hipSuccess || hipMalloc(&p->d_tw, wbytes) != hipSuccess ||
-      hipMalloc((void**)&p->d_prog, prog.size() * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&p->d_prog1, 2 * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&p->d_taus, (vc.size() + 1) * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&p->d_part, (size_t)sop::kReduceBlocks * (S + 2 + sop::kMaxParams) * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&p->d_out, 8 * sizeof(double)) != hipSuccess) {
+  if (dalloc(p, &p->d_vraw, vbytes) != hipSuccess || dalloc(p, &p->d_vexp, tbytes) != hipSuccess ||
+      dalloc(p, &p->d_kin, kbytes) != hipSuccess || dalloc(p, &p->d_tw, wbytes) != hipSuccess ||
+      dalloc(p, &p->d_prog, prog.size() * sizeof(int)) != hipSuccess ||
+      dalloc(p, &p->d_prog1, 2 * sizeof(int)) != hipSuccess ||
+      dalloc(p, &p->d_taus, (vc.size() + 1) * sizeof(double)) != hipSuccess ||
+      dalloc(p, &p->d_part,
+             (size_t)sop::kReduceBlocks * (S + 2 + sop::kMaxParams) * sizeof(double)) !=
+          hipSuccess ||
+      dalloc(p, &p->d_out, 8 * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SOP_ERR_NOMEM, "device allocation failed for the plan tables");
   }
@@ -533,10 +567,9 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
   p->nparams = desc->nparams;
   if (p->nparams > 0) {
     const size_t dvb = (size_t)p->nparams * vbytes;
-    if (hipMalloc((void**)&p->d_vbase, vbytes) != hipSuccess ||
-        hipMalloc((void**)&p->d_dv, dvb) != hipSuccess ||
-        hipMalloc((void**)&p->d_theta, sop::kMaxParams * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&p->d_w, 8 * sizeof(double)) != hipSuccess) {
+    if (dalloc(p, &p->d_vbase, vbytes) != hipSuccess || dalloc(p, &p->d_dv, dvb) != hipSuccess ||
+        dalloc(p, &p->d_theta, sop::kMaxParams * sizeof(double)) != hipSuccess ||
+        dalloc(p, &p->d_w, 8 * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SOP_ERR_NOMEM, "device allocation failed for the parameter tables");
     }
@@ -546,7 +579,7 @@ sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan
     HIPTRY(hipMemcpyAsync(p->d_theta, p->theta.data(), p->nparams * sizeof(double),
                           hipMemcpyHostToDevice, stream));
     if (p->ndim == 3 && f64 && sop::k3d_adjoint_supported(p->n[0], S, f64)) {
-      if (hipMalloc(&p->d_eig, (size_t)NE * p->npts * sizeof(double) * 2) != hipSuccess) {
+      if (dalloc(p, &p->d_eig, (size_t)NE * p->npts * sizeof(double) * 2) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SOP_ERR_NOMEM, "device allocation failed for the eigen table");
       }
@@ -691,7 +724,7 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
       d.hprog = {sop::prog_entry(sop::OP_V, (int)p->vtaus.size())};
     } else {
       d.eig = false;
-      if (!p->d_atab) HIPTRY(hipMalloc(&p->d_atab, (size_t)NE * p->npts * p->csize));
+      if (!p->d_atab) HIPTRY(dalloc(p, &p->d_atab, (size_t)NE * p->npts * p->csize));
       HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->tile, p->d_atab));
       d.vexp = p->d_atab;
       d.prog = p->d_prog1;
@@ -700,7 +733,7 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
   } else {
     const int nax = p->ndim == 1 ? 1 : 3;
     const size_t kb = (size_t)nax * p->n[0] * p->csize * (d.f64 ? 1 : 2);
-    if (!p->d_akin) HIPTRY(hipMalloc(&p->d_akin, kb));
+    if (!p->d_akin) HIPTRY(dalloc(p, &p->d_akin, kb));
     std::vector<char> kp =
         pack_split(kinetic_factors(p, {(double)((ld)coef * (ld)p->dt)}), d.f64, p->n[0]);
     HIPTRY(hipMemcpyAsync(p->d_akin, kp.data(), kb, hipMemcpyHostToDevice, d.stream));

@@ -39,6 +39,36 @@ class _Desc(ctypes.Structure):
                 ("nparams", ctypes.c_int), ("dvtables", ctypes.POINTER(ctypes.c_double))]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def _torch_allocator():
+    """sop_allocator hooks onto PyTorch's caching allocator (current device):
+    the plan's tables then live in torch's memory pool."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:  # out of memory: the library reports SOP_ERR_NOMEM
+            return None
+
+    def free(ctx, ptr, stream):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:  # interpreter shutdown: the process releases the pool
+            pass
+
+    fa, ff = _ALLOC_FN(alloc), _FREE_FN(free)
+    return _Allocator(None, fa, ff), (fa, ff)
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("n_a", ctypes.c_int), ("n_b", ctypes.c_int),
                 ("n_a_unq", ctypes.c_int), ("n_b_unq", ctypes.c_int),
@@ -48,7 +78,8 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
-           "sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
+           "sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
+           "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
            "sop_plan_set_params",
@@ -79,6 +110,8 @@ def lib():
     L.sop_scheme_sequence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       dp, dp, dp, dp, ip, ip, ip]
     L.sop_plan_create.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(vp)]
+    L.sop_plan_create_with_allocator.argtypes = [ctypes.POINTER(_Desc), vp,
+                                                 ctypes.POINTER(_Allocator), ctypes.POINTER(vp)]
     L.sop_plan_destroy.argtypes = [vp]
     L.sop_plan_info_get.argtypes = [vp, ctypes.POINTER(_Info)]
     L.sop_plan_set_stream.argtypes = [vp, vp]
@@ -104,7 +137,8 @@ def lib():
     L.sop_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sop_batch_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                      ctypes.POINTER(ctypes.c_size_t)]
-    for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_destroy", "sop_plan_info_get",
+    for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
+              "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
               "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
               "sop_plan_set_params",
@@ -175,11 +209,15 @@ class Plan:
     n, lo, hi: per-axis grid (1D or cubic 3D); nsurf; inv_mass per axis;
     vtable: float64 [S(S+1)/2][npts] packed upper triangle of V(q);
     split: 'VTV' | 'TVT' | 'VT' | 'TV'; comp: 'strang' | 'triple_jump' |
-    'suzuki'; order; dt; dtype: torch.complex128 or torch.complex64.
+    'suzuki'; order; dt; dtype: torch.complex128 or torch.complex64;
+    allocator: None (the library's hipMalloc) or 'torch' (the plan's device
+    buffers come from PyTorch's caching allocator,
+    sop_plan_create_with_allocator).
     """
 
     def __init__(self, n, lo, hi, nsurf, inv_mass, vtable, split="VTV", comp="strang",
-                 order=2, dt=0.01, hbar=1.0, dtype=None, stream=None, dvtables=None):
+                 order=2, dt=0.01, hbar=1.0, dtype=None, stream=None, dvtables=None,
+                 allocator=None):
         import torch
         if dtype is None:
             dtype = torch.complex128
@@ -221,8 +259,17 @@ class Plan:
             d.dvtables = _dp(self._dv)
         self._stream = stream
         h = ctypes.c_void_p()
-        _check(L.sop_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)),
-               "sop_plan_create")
+        if allocator is None:
+            _check(L.sop_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)),
+                   "sop_plan_create")
+        elif allocator == "torch":
+            self._hooks = _torch_allocator()  # kept alive until the plan is destroyed
+            _check(L.sop_plan_create_with_allocator(ctypes.byref(d), _stream_handle(stream),
+                                                    ctypes.byref(self._hooks[0]),
+                                                    ctypes.byref(h)),
+                   "sop_plan_create_with_allocator")
+        else:
+            raise ValueError("allocator must be None or 'torch'")
         self._h = h
 
     @classmethod

@@ -582,6 +582,35 @@ def test_update_v_keeps_graphs_and_batches_valid(torch_cuda):
     np.testing.assert_array_equal(pair[0].cpu().numpy(), ref.cpu().numpy())
 
 
+def test_plan_with_torch_allocator(torch_cuda):
+    """A plan whose device buffers come from PyTorch's caching allocator
+    (sop_plan_create_with_allocator) computes bitwise what a hipMalloc plan
+    computes; its tables show in torch's allocated memory and go back to the
+    pool when the plan is destroyed."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32, dv_params=True)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    a = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=10.0, dvtables=m.dvtables,
+                               allocator="torch")
+    held = torch.cuda.memory_allocated() - before
+    assert held >= a.info.table_bytes
+    b = soprop.Plan.from_model(m, comp="suzuki", order=4, dt=10.0, dvtables=m.dvtables)
+    for p in (a, b):
+        p.set_params(np.array([0.03, 0.04, 0.2]))
+    pa = torch.from_numpy(m.psi0.copy()).cuda()
+    pb = torch.from_numpy(m.psi0.copy()).cuda()
+    a.propagate(pa, 6)
+    b.propagate(pb, 6)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+    assert a.observables(pa)["norm"] == b.observables(pb)["norm"]
+    a.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < held
+
+
 @pytest.mark.parametrize("c64", [False, True])
 def test_distance(torch_cuda, orc, c64):
     """sop_distance against the oracle's distance on the same stored values:
