@@ -282,6 +282,14 @@ sop_status sop_adjoint_forward(sop_plan* plan, const void* psi0_dev, int64_t nst
 sop_status sop_adjoint_backward(sop_plan* plan, int64_t nsteps, int K, const double* weights,
                                 void* workspace_dev, double* grad_out);
 
+/* Both sweeps in one call: pops_out [S] = P_s(T) from the forward sweep,
+ * grad_out [nparams] = sum_s weights[s] dP_s/dtheta_k from the backward one
+ * (host arrays; the workspace as for sop_adjoint_forward).  Synchronises;
+ * out-parameters are written only on SOP_OK. */
+sop_status sop_adjoint(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int K,
+                       const double* weights, void* workspace_dev, double* pops_out,
+                       double* grad_out);
+
 /* Plan options.  SOP_OPT_GRAPHS (default 1): on 3D grids, runs of 4 or more
  * steps launch the first step, the steady step (replayed) and the final
  * pass as HIP graphs captured once per state pointer, direction and count;

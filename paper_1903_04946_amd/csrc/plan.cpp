@@ -880,6 +880,19 @@ sop_status sop_adjoint_backward(sop_plan* p, int64_t nsteps, int K, const double
   return SOP_OK;
 }
 
+sop_status sop_adjoint(sop_plan* p, const void* psi0, int64_t nsteps, int K,
+                       const double* weights, void* ws, double* pops_out, double* grad_out) {
+  if (!pops_out || !grad_out) return fail(SOP_ERR_INVALID, "NULL argument");
+  std::vector<double> pops(p ? (size_t)p->S : 0), grad(p ? (size_t)p->nparams : 0);
+  sop_status st = sop_adjoint_forward(p, psi0, nsteps, K, ws, pops.data());
+  if (st != SOP_OK) return st;
+  st = sop_adjoint_backward(p, nsteps, K, weights, ws, grad.data());
+  if (st != SOP_OK) return st;
+  std::copy(pops.begin(), pops.end(), pops_out);
+  std::copy(grad.begin(), grad.end(), grad_out);
+  return SOP_OK;
+}
+
 sop_status sop_plan_set_option(sop_plan* p, int option, int value) {
   if (!p) return fail(SOP_ERR_INVALID, "plan is NULL");
   switch (option) {

@@ -85,6 +85,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_plan_set_params",
            "sop_plan_update_v",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
+           "sop_adjoint",
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
            "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
            "sop_batch_describe"]
@@ -129,6 +130,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_size_t)]
     L.sop_adjoint_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, dp]
     L.sop_adjoint_backward.argtypes = [vp, ctypes.c_int64, ctypes.c_int, dp, vp, dp]
+    L.sop_adjoint.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, dp, vp, dp, dp]
     L.sop_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
     L.sop_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.sop_batch_destroy.argtypes = [vp]
@@ -319,6 +321,17 @@ class Plan:
                                           ctypes.c_void_p(workspace.data_ptr()), _dp(g)),
                "sop_adjoint_backward")
         return g
+
+    def adjoint(self, psi0, nsteps: int, K: int, weights, workspace):
+        """(P_s(T), sum_s weights[s] dP_s/dtheta_k) in one call (sop_adjoint)."""
+        self._check_psi(psi0)
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(self.nsurf)
+        pops = np.zeros(self.nsurf)
+        g = np.zeros(self.nparams)
+        _check(lib().sop_adjoint(self._h, ctypes.c_void_p(psi0.data_ptr()), int(nsteps), int(K),
+                                 _dp(w), ctypes.c_void_p(workspace.data_ptr()), _dp(pops),
+                                 _dp(g)), "sop_adjoint")
+        return pops, g
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

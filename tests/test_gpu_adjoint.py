@@ -67,6 +67,10 @@ def test_adjoint_vs_oracle_tangent(torch_cuda, orc, comp, order, nsteps, K):
     print(f"[adjoint] gpu grad {grad} oracle {ograd}")
     np.testing.assert_allclose(pops, opops, rtol=0, atol=1e-12)
     assert np.max(np.abs(grad - ograd)) < 1e-10 * max(1.0, np.max(np.abs(ograd)))
+    # the single call gives the same two sweeps
+    pops1, grad1 = plan.adjoint(psi0, nsteps, K, w, ws)
+    np.testing.assert_array_equal(pops1, pops)
+    np.testing.assert_array_equal(grad1, grad)
 
 
 def test_adjoint_norm_and_k_independence(torch_cuda):
