@@ -810,6 +810,8 @@ def main(argv=None) -> int:
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic,
+                     "traffic_frac": None if traffic is None
+                     else traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch,
                      "stream_copy_GBps": copy_gbps},
         "kernels": kernels,
