@@ -339,6 +339,22 @@ def test_3d_64_fp32(torch_cuda, orc):
     assert err < 1e-5
 
 
+def test_3d_64_tj8_100_steps(torch_cuda, orc):
+    """64^3 x 3 LVC, TJ-8, dt = 10, 100 steps (2700 substeps): FP64 against
+    the oracle at the FP64 bar, and the FP32 error against the same oracle
+    result, stated (bound 5e-5)."""
+    torch = torch_cuda
+    m = synth.lvc_3d(n=64)
+    ref = oracle_run(orc, m, "VTV", "triple_jump", 8, 10.0, 100)
+    got, _ = gpu_run(torch, m, "VTV", "triple_jump", 8, 10.0, 100)
+    err64 = rel_l2(got, ref)
+    got32, _ = gpu_run(torch, m, "VTV", "triple_jump", 8, 10.0, 100, dtype=torch.complex64)
+    err32 = rel_l2(got32, ref)
+    print(f"[64^3 TJ-8, 100 steps] FP64 {err64:.3e}, FP32 {err32:.3e} vs the oracle")
+    assert err64 < FP64_TOL
+    assert err32 < 5e-5
+
+
 def test_fp32_error_growth_32cube_sf4(torch_cuda, orc):
     """FP32 round-off over many substeps: 32^3 x 3 LVC, SF-4 at dt = 500/128,
     128 steps (640 substeps), against the FP64 oracle at the same scheme and
