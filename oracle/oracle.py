@@ -82,10 +82,12 @@ def lib():
         L.orc_observables.argtypes = [pp, dp, dp]
         L.orc_overlap.argtypes = [pp, dp, dp, dp]
         L.orc_distance.argtypes = [pp, dp, dp, dp]
+        L.orc_propagate_driven.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
-                  "orc_distance",
+                  "orc_distance", "orc_propagate_driven",
                   "orc_exact", "orc_propagate_timed", "orc_threads", "orc_set_threads",
                   "orc_expm_frechet",
                   "orc_gradient"):
@@ -275,6 +277,21 @@ def overlap(prob: Problem, psi: np.ndarray, phi: np.ndarray) -> complex:
     out = np.zeros(2)
     lib().orc_overlap(prob.ptr(), _dp(a.view(np.float64)), _dp(b.view(np.float64)), _dp(out))
     return complex(out[0], out[1])
+
+
+def propagate_driven(prob: Problem, dtable: np.ndarray, psi: np.ndarray, split: int,
+                     scheme: int, order: int, dt: float, nsteps: int,
+                     drive: np.ndarray) -> np.ndarray:
+    """Pruned propagation with V(x, t) = V0 + s D: drive[n, v] is the value
+    s for the v-th potential action of step n (shape [nsteps, nv])."""
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    d = np.ascontiguousarray(dtable, dtype=np.float64).reshape(-1)
+    s = np.ascontiguousarray(drive, dtype=np.float64).reshape(-1)
+    rc = lib().orc_propagate_driven(prob.ptr(), _dp(d), split, scheme, order, float(dt),
+                                    int(nsteps), _dp(s), _dp(a.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle driven propagation rejected its arguments")
+    return a
 
 
 def distance(prob: Problem, psi: np.ndarray, phi: np.ndarray) -> float:

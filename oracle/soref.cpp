@@ -604,6 +604,51 @@ int orc_propagate(const orc_problem* prob, int split, int scheme, int order, dou
   return 0;
 }
 
+// Driven potential V(x, t) = V0(x) + s(t) D(x) (Sec. "Pruning splitting
+// coefficients": a time-dependent operator is formed on the fly, at every
+// action).  The v-th potential action of step n uses the drive value
+// drive[n * nv + v] (nv potential actions per step); its exp(-i tau V/hbar)
+// comes from a per-point eigen-decomposition of V0 + s D made for that
+// action.  The caller chooses the times at which s is sampled.
+int orc_propagate_driven(const orc_problem* prob, const double* dtable, int split, int scheme,
+                         int order, double dt, int64_t nsteps, const double* drive,
+                         double* psi_io) {
+  Grid g;
+  if (!make_grid(prob, g) || !prob->vtable || !dtable || nsteps < 0) return -1;
+  std::vector<ld> la, lb;
+  if (!splitting_ld(split, scheme, order, true, la, lb)) return -1;
+  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
+  const bool aV = a_is_potential(split);
+  int64_t nv = 0;  // potential actions per step
+  for (size_t j = 0; j < a.size(); ++j) nv += aV ? 1 : (b[j] != 0.0 ? 1 : 0);
+  const int NE = g.S * (g.S + 1) / 2;
+  const size_t ntab = (size_t)NE * g.npts;
+  std::vector<double> vt(ntab);
+  PotentialEigen pe;
+  cd* psi = reinterpret_cast<cd*>(psi_io);
+  auto potential = [&](double tau, double s) {
+    for (size_t i = 0; i < ntab; ++i) vt[i] = prob->vtable[i] + s * dtable[i];
+    potential_eigen(g, vt.data(), pe);
+    potential_action(g, pe, tau, psi);
+  };
+  for (int64_t step = 0; step < nsteps; ++step) {
+    int64_t v = 0;
+    for (size_t j = 0; j < a.size(); ++j) {
+      if (aV)
+        potential(a[j] * dt, drive[step * nv + v++]);
+      else
+        kinetic_action(g, a[j] * dt, psi);
+      if (b[j] != 0.0) {
+        if (aV)
+          kinetic_action(g, b[j] * dt, psi);
+        else
+          potential(b[j] * dt, drive[step * nv + v++]);
+      }
+    }
+  }
+  return 0;
+}
+
 // Same as orc_propagate, and writes to *seconds the wall time of the step
 // loop alone (std::chrono::steady_clock; the per-point eigen-decomposition
 // done before the loop is excluded).  Used to time the oracle as a CPU

@@ -303,3 +303,95 @@ def test_energy_error_follows_order(orc, scheme, order):
         errs.append(abs(orc.observables(P, psi)["energy"] - e0))
     assert errs[0] > 1e-10  # not conserved
     assert abs(fitted_slope(dts, errs, floor=1e-12) - order) < 0.5, errs
+
+
+# ------------------------------------------------------------------ driven potential
+def _drive_times(orc, split, scheme, order, nsteps, dt):
+    """Times of the potential actions with time advanced by the kinetic
+    actions: the v-th potential action of step n is at (n + c_v) dt, c_v the
+    sum of the kinetic coefficients before it (VTV)."""
+    a, b = orc.splitting(split, scheme, order, True)
+    c = np.concatenate([[0.0], np.cumsum(b)[:-1]])
+    return (np.arange(nsteps)[:, None] + c[None, :]) * dt
+
+
+def test_driven_constant_equals_static(orc):
+    """A constant drive s gives the propagation of the static V0 + s D."""
+    for n, S in (([64], 2), ([4, 4, 4], 3)):
+        m = synth.random_small(n, S, seed=7)
+        d = synth.random_small(n, S, seed=8).vtable
+        s = 0.37
+        P = problem(orc, m)
+        drive = np.full((3, 4), s)  # TJ-4 VTV: four potential actions a step
+        got = orc.propagate_driven(P, d, m.psi0, orc.VTV, orc.TRIPLE_JUMP, 4, 0.05, 3, drive)
+        Ps = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable + s * d, m.hbar)
+        ref = orc.propagate(Ps, m.psi0, orc.VTV, orc.TRIPLE_JUMP, 4, 0.05, 3)
+        assert np.linalg.norm(got - ref) < 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("scheme,order", [("STRANG", 2), ("TRIPLE_JUMP", 4), ("SUZUKI", 4)])
+def test_driven_two_level_quadrature_order(orc, scheme, order):
+    """x-independent two-level drive V = s(t) sigma_x, V0 = 0: the exact state
+    is exp(-i T t) [cos F(t); -i sin F(t)] psi0 with F = int_0^t s (closed
+    form), and the composed scheme reduces to exp(-i T t) exp(-i Q sigma_x)
+    with Q its quadrature of F over the action times.  The error must fall
+    with the scheme's order when the drive is sampled at the times of the
+    potential actions."""
+    n = 32
+    m = synth.random_small([n], 2, seed=3)
+    v0 = np.zeros_like(m.vtable)
+    d = np.zeros_like(m.vtable)
+    d[synth.packed_index(2, 0, 1)] = 1.0
+    psi0 = np.zeros_like(m.psi0)
+    psi0[0] = m.psi0[0]
+    P = orc.Problem(m.n, m.lo, m.hi, 2, m.inv_mass, v0, m.hbar)
+    tf, w = 4.0, 1.7
+    f = lambda t: np.cos(w * t) + 0.3 * np.sin(2.1 * t)
+    F = np.sin(w * tf) / w + 0.3 * (1 - np.cos(2.1 * tf)) / 2.1
+    # exp(-i T tf) psi0 on the grid
+    k = 2 * np.pi * np.fft.fftfreq(n, d=m.dx[0])
+    phi = np.fft.ifft(np.exp(-1j * tf * m.inv_mass[0] * k**2 / 2) * np.fft.fft(psi0[0]))
+    exact = np.stack([np.cos(F) * phi, -1j * np.sin(F) * phi])
+    sid = getattr(orc, scheme)
+    errs, dts = [], []
+    for kk in range(3, 7):
+        ns = 2**kk
+        dt = tf / ns
+        drive = f(_drive_times(orc, orc.VTV, sid, order, ns, dt))
+        got = orc.propagate_driven(P, d, psi0, orc.VTV, sid, order, dt, ns, drive)
+        errs.append(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+        dts.append(dt)
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    print(f"[driven] {scheme}-{order}: errors {['%.1e' % e for e in errs]}, slope {slope:.2f}")
+    assert abs(slope - order) < 0.3
+
+
+def test_driven_wrong_times_lose_the_order(orc):
+    """The pin above is sensitive to the time convention: sampling the drive
+    at the start of each step for every action (a plausible mistake) takes
+    the fourth-order triple jump down to about first order."""
+    n = 32
+    m = synth.random_small([n], 2, seed=3)
+    v0 = np.zeros_like(m.vtable)
+    d = np.zeros_like(m.vtable)
+    d[synth.packed_index(2, 0, 1)] = 1.0
+    psi0 = np.zeros_like(m.psi0)
+    psi0[0] = m.psi0[0]
+    P = orc.Problem(m.n, m.lo, m.hi, 2, m.inv_mass, v0, m.hbar)
+    tf, w = 4.0, 1.7
+    f = lambda t: np.cos(w * t) + 0.3 * np.sin(2.1 * t)
+    F = np.sin(w * tf) / w + 0.3 * (1 - np.cos(2.1 * tf)) / 2.1
+    k = 2 * np.pi * np.fft.fftfreq(n, d=m.dx[0])
+    phi = np.fft.ifft(np.exp(-1j * tf * m.inv_mass[0] * k**2 / 2) * np.fft.fft(psi0[0]))
+    exact = np.stack([np.cos(F) * phi, -1j * np.sin(F) * phi])
+    errs, dts = [], []
+    for kk in range(3, 7):
+        ns = 2**kk
+        dt = tf / ns
+        t = _drive_times(orc, orc.VTV, orc.TRIPLE_JUMP, 4, ns, dt)
+        drive = f(np.floor(t / dt + 1e-9) * dt)  # step start for every action
+        got = orc.propagate_driven(P, d, psi0, orc.VTV, orc.TRIPLE_JUMP, 4, dt, ns, drive)
+        errs.append(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+        dts.append(dt)
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    assert slope < 1.8  # about first order (1.35 over these steps), far from 4
