@@ -231,6 +231,31 @@ sop_status sop_distance(sop_plan* plan, const void* psi_dev, const void* phi_dev
  * The table for coef is formed on the fly into the plan's scratch. */
 sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
 
+/* Times of the potential actions of one step, in units of dt from the
+ * step's start (host, [count]): the kinetic actions advance time and the
+ * potential actions act at an instant, so for VTV c_v = b_1 + .. + b_{v-1}
+ * (Sec. "Compositions of split-operator algorithms": the sequence U_B(b_N dt)
+ * U_A(a_N dt) .. U_A(a_1 dt)).  Sampling a drive s(t) at t0 + (n + c_v) dt
+ * keeps the composition's order for a time-dependent potential.  c may be
+ * NULL to query count; SOP_ERR_INVALID if cap < count. */
+sop_status sop_action_times(const sop_plan* plan, double* c, int cap, int* count);
+
+/* Driven propagation with V(x, t) = V(x) + s D(x), D the plan's one
+ * parameter table (dvtables[0]) and V the table at theta = 0: the v-th
+ * potential action of step n uses s = drive[n * count + v] (host,
+ * [nsteps][count], count from sop_action_times).  A time-dependent operator
+ * is formed on the fly (Sec. "Pruning splitting coefficients"): before
+ * every potential action the library forms V + s D and its exponential
+ * (the eigen form, or the one table that action reads) on the device, and
+ * the actions run one at a time, eagerly.  Afterwards the plan's tables
+ * are those of its current parameter again.  Synchronises.
+ * SOP_ERR_STATE unless the plan has exactly one parameter table;
+ * SOP_ERR_INVALID for a NULL or non-finite drive; SOP_ERR_UNSUPPORTED if
+ * the plan holds the eigen form and the drive could take a phase beyond its
+ * range (then nothing changes). */
+sop_status sop_propagate_driven(sop_plan* plan, void* psi_dev, int64_t nsteps,
+                                const double* drive);
+
 /* Replaces the plan's V-table (host FP64, [S(S+1)/2][npts], the layout of
  * sop_plan_desc.vtable) and forms the potential tables again on the device,
  * in the same buffers, so captured graphs and batches that hold the plan stay

@@ -201,6 +201,8 @@ struct sop_plan {
   double* d_dv = nullptr;     // [nparams][NE][npts]
   double* d_theta = nullptr;  // [nparams]
   std::vector<double> theta;  // host copy of the current parameters
+  double* d_drive = nullptr;  // drive samples of sop_propagate_driven
+  size_t drive_cap = 0;       // doubles held by d_drive
   void* d_eig = nullptr;      // adjoint eigen table (FP64, tile layout)
   double* d_w = nullptr;      // [S] adjoint weights
   sop::GraphCache* graphs = nullptr;
@@ -236,7 +238,7 @@ void free_plan(sop_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
-                  p->d_dv, p->d_theta, p->d_eig, p->d_w};
+                  p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive};
   delete p->graphs;
   for (void* b : bufs) {
     if (!b) continue;
@@ -766,6 +768,95 @@ sop_status sop_plan_set_params(sop_plan* p, const double* theta) {
   if (p->d_eig) HIPTRY(sop::form_eig(p->dv, p->d_vraw, p->tile, p->d_eig));
   HIPTRY(hipStreamSynchronize(st));
   p->theta.assign(theta, theta + p->nparams);
+  return SOP_OK;
+}
+
+sop_status sop_action_times(const sop_plan* p, double* c, int cap, int* count) {
+  if (!p || !count) return fail(SOP_ERR_INVALID, "NULL argument");
+  // the kinetic actions advance time; potential actions happen at an instant
+  std::vector<double> t;
+  double elapsed = 0.0;
+  for (int code : p->dv.hprog) {
+    if ((code >> 16) == sop::OP_V)
+      t.push_back(elapsed);
+    else
+      elapsed += p->ttaus[code & 0xffff] / p->dt;
+  }
+  if (c && cap < (int)t.size()) return fail(SOP_ERR_INVALID, "cap is smaller than the count");
+  if (c) std::copy(t.begin(), t.end(), c);
+  *count = (int)t.size();
+  return SOP_OK;
+}
+
+sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const double* drive) {
+  if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
+  if (p->nparams != 1)
+    return fail(SOP_ERR_STATE, "a driven plan has exactly one parameter table (the drive's D)");
+  int nv = 0;
+  for (int code : p->dv.hprog) nv += (code >> 16) == sop::OP_V;
+  const size_t ns = (size_t)nsteps * (size_t)nv;
+  if (nsteps == 0) return SOP_OK;
+  if (!drive) return fail(SOP_ERR_INVALID, "drive is NULL");
+  double smax = 0.0;
+  for (size_t i = 0; i < ns; ++i) {
+    if (!std::isfinite(drive[i])) return fail(SOP_ERR_INVALID, "drive must be finite");
+    smax = std::max(smax, std::fabs(drive[i]));
+  }
+  if (p->eig_form && !phases_fit(p, p->vbound + smax * p->dvbound[0]))
+    return fail(SOP_ERR_UNSUPPORTED,
+                "the drive takes the phases tau*lambda beyond the eigen form's range");
+  hipStream_t st = p->dv.stream;
+  if (p->drive_cap < ns) {
+    if (p->d_drive) {
+      HIPTRY(hipStreamSynchronize(st));
+      if (p->hook.free)
+        p->hook.free(p->hook.ctx, p->d_drive, (void*)p->home);
+      else
+        HIPTRY(hipFree(p->d_drive));
+      p->d_drive = nullptr;
+      p->drive_cap = 0;
+    }
+    if (dalloc(p, &p->d_drive, ns * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SOP_ERR_NOMEM, "device allocation failed for the drive samples");
+    }
+    p->drive_cap = ns;
+  }
+  HIPTRY(hipMemcpyAsync(p->d_drive, drive, ns * sizeof(double), hipMemcpyHostToDevice, st));
+  // one action at a time, each potential action with its own V = V0 + s D
+  sop::DevView d = p->dv;
+  d.graphs = nullptr;
+  d.nact = 1;
+  const size_t tab = (size_t)(p->S * (p->S + 1) / 2) * p->npts * p->csize;
+  const int nact = (int)p->dv.hprog.size();
+  for (int64_t n = 0; n < nsteps; ++n) {
+    int v = 0;
+    for (int a = 0; a < nact; ++a) {
+      const int code = p->dv.hprog[a];
+      if ((code >> 16) == sop::OP_V) {
+        const double* s_dev = p->d_drive + (size_t)n * nv + v++;
+        HIPTRY(sop::set_vparams(d, p->d_vraw, p->d_vbase, p->d_dv, s_dev, 1));
+        if (p->eig_form) {
+          HIPTRY(sop::form_eigq(d, p->d_vraw, p->tile, p->d_vexp));
+        } else {  // only the table this action reads
+          const int idx = code & 0xffff;
+          HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + idx, 1, p->tile,
+                                (char*)p->d_vexp + (size_t)idx * tab));
+        }
+      }
+      d.prog = p->d_prog + a;
+      d.hprog = {code};
+      if (p->ndim == 1)
+        HIPTRY(sop::k1d_propagate(d, psi, 1, 0));
+      else
+        HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
+    }
+  }
+  // back to the plan's own potential (the current parameter) for later calls
+  HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
+  HIPTRY(form_tables(p));
+  HIPTRY(hipStreamSynchronize(st));
   return SOP_OK;
 }
 

@@ -83,7 +83,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
            "sop_plan_set_params",
-           "sop_plan_update_v",
+           "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
            "sop_adjoint",
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
@@ -124,6 +124,8 @@ def lib():
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
     L.sop_plan_update_v.argtypes = [vp, dp]
+    L.sop_action_times.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.sop_propagate_driven.argtypes = [vp, vp, ctypes.c_int64, dp]
     L.sop_propagate_many.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
     L.sop_plan_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.sop_adjoint_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int,
@@ -144,7 +146,8 @@ def lib():
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
               "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
               "sop_plan_set_params",
-              "sop_plan_update_v", "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
+              "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
+              "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
               "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
               "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
               "sop_batch_describe"):
@@ -250,6 +253,7 @@ class Plan:
         d.comp = COMPS[comp]
         d.order = int(order)
         d.dt = float(dt)
+        self.dt = float(dt)
         d.hbar = float(hbar)
         d.dtype = C128 if dtype == torch.complex128 else C64
         self.nparams = 0
@@ -283,6 +287,33 @@ class Plan:
         """V <- vtable + sum_k theta_k dvtables[k]; tables formed again."""
         th = np.ascontiguousarray(theta, dtype=np.float64).reshape(self.nparams)
         _check(lib().sop_plan_set_params(self._h, _dp(th)), "sop_plan_set_params")
+
+    def action_times(self) -> np.ndarray:
+        """Times of one step's potential actions, in units of dt from its start."""
+        cnt = ctypes.c_int()
+        _check(lib().sop_action_times(self._h, None, 0, ctypes.byref(cnt)), "sop_action_times")
+        c = np.zeros(cnt.value)
+        _check(lib().sop_action_times(self._h, _dp(c), cnt.value, ctypes.byref(cnt)),
+               "sop_action_times")
+        return c
+
+    def propagate_driven(self, psi, nsteps: int, drive=None, f=None, t0: float = 0.0):
+        """psi <- the composed steps with V + s D, s sampled per potential
+        action: `drive` [nsteps][count], or a callable f(t) evaluated at
+        t0 + (n + c_v) dt (c from action_times).  Synchronises."""
+        self._check_psi(psi)
+        c = self.action_times()
+        if drive is None:
+            if f is None:
+                raise ValueError("give drive samples or f")
+            t = t0 + (np.arange(int(nsteps))[:, None] + c[None, :]) * self.dt
+            drive = np.vectorize(f, otypes=[float])(t) if t.size else np.zeros((0, len(c)))
+        s = np.ascontiguousarray(drive, dtype=np.float64).reshape(-1)
+        if s.size != int(nsteps) * len(c):
+            raise ValueError("drive must hold nsteps x count samples")
+        _check(lib().sop_propagate_driven(self._h, ctypes.c_void_p(psi.data_ptr()),
+                                          int(nsteps), _dp(s)), "sop_propagate_driven")
+        return psi
 
     def update_v(self, vtable):
         """Replaces the V-table ([S(S+1)/2][npts] FP64) and forms the tables again."""

@@ -1,0 +1,160 @@
+"""GPU parity of the driven potential V(x, t) = V(x) + s(t) D(x)
+(sop_propagate_driven, sop_action_times) against the oracle's driven
+propagation, on the same drive samples: FP64 within 1e-12 relative L2, FP32
+within 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1903_04946_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_ID = {"VTV": 0, "TVT": 1}
+COMP_ID = {"strang": 0, "triple_jump": 1, "suzuki": 2}
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_04946_amd import soprop
+    soprop.lib()
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def oracle_times(orc, split, comp, order):
+    """Potential-action times of one step from the oracle's own sequence."""
+    a, b = orc.splitting(SPLIT_ID[split], COMP_ID[comp], order, True)
+    t, out = 0.0, []
+    for aj, bj in zip(a, b):
+        if split == "VTV":
+            out.append(t)
+            t += bj
+        else:
+            t += aj
+            if bj != 0.0:
+                out.append(t)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("split,comp,order", [("VTV", "strang", 2), ("VTV", "triple_jump", 4),
+                                              ("VTV", "suzuki", 6), ("TVT", "triple_jump", 4)])
+def test_action_times_match_the_sequence(torch_cuda, orc, split, comp, order):
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([64], 2, seed=1)
+    d = synth.random_small([64], 2, seed=2).vtable
+    plan = soprop.Plan.from_model(m, split=split, comp=comp, order=order, dt=0.1,
+                                  dvtables=d[None])
+    np.testing.assert_allclose(plan.action_times(), oracle_times(orc, split, comp, order),
+                               rtol=0, atol=1e-14)
+
+
+def drive_fn(t):
+    return 0.3 * np.cos(1.3 * t) + 0.1 * np.sin(0.4 * t)
+
+
+@pytest.mark.parametrize("split,comp,order", [("VTV", "triple_jump", 4), ("TVT", "suzuki", 4)])
+def test_driven_1d_vs_oracle(torch_cuda, orc, split, comp, order):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([256], 2, seed=11, lo=-6, hi=6)
+    d = synth.random_small([256], 2, seed=12, lo=-6, hi=6).vtable
+    dt, ns = 0.05, 6
+    plan = soprop.Plan.from_model(m, split=split, comp=comp, order=order, dt=dt,
+                                  dvtables=d[None])
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate_driven(psi, ns, f=drive_fn, t0=0.2)
+    c = oracle_times(orc, split, comp, order)
+    drive = drive_fn(0.2 + (np.arange(ns)[:, None] + c[None, :]) * dt)
+    P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
+    ref = orc.propagate_driven(P, d, m.psi0, SPLIT_ID[split], COMP_ID[comp], order, dt, ns,
+                               drive)
+    assert rel_l2(psi.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_driven_3d_vs_oracle(torch_cuda, orc, c64):
+    """32^3 x 3 LVC with the coupling lambda_23 driven around 0.2 eV (the
+    eigen form in FP64, per-coefficient tables in FP32)."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    dtype = torch.complex64 if c64 else torch.complex128
+    m = synth.lvc_3d(n=32, dv_params=True)
+    v0 = synth.lvc_vtable_theta(m, np.zeros(3))
+    d = m.dvtables[2]
+    dt, ns = 10.0, 3
+    plan = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, comp="triple_jump", order=4,
+                       dt=dt, dtype=dtype, dvtables=d[None])
+    f = lambda t: 0.2 + 0.05 * np.sin(0.01 * t)
+    psi = torch.from_numpy(m.psi0.copy()).to(dtype).cuda()
+    plan.propagate_driven(psi, ns, f=f)
+    c = oracle_times(orc, "VTV", "triple_jump", 4)
+    drive = f((np.arange(ns)[:, None] + c[None, :]) * dt)
+    P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, m.hbar)
+    ref = orc.propagate_driven(P, d, m.psi0, 0, 1, 4, dt, ns, drive)
+    err = rel_l2(psi.cpu().numpy().astype(np.complex128), ref)
+    print(f"[driven 3d] {'FP32' if c64 else 'FP64'} error {err:.3e}")
+    assert err < (1e-5 if c64 else 1e-12)
+    # the ground surface stays (numerically) empty: the theta = 0 table keeps
+    # couplings to it at the rounding level of lvc_vtable_theta's subtraction
+    assert np.abs(psi.cpu().numpy()[0]).max() < 1e-12
+
+
+def test_driven_constant_and_restored_tables(torch_cuda, orc):
+    """A constant drive s equals the static propagation of V + s D (to
+    1e-12: the actions run one at a time), and afterwards the plan
+    propagates bitwise like a fresh plan (its own tables are back)."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32, dv_params=True)
+    v0 = synth.lvc_vtable_theta(m, np.zeros(3))
+    d = m.dvtables[2]
+    kw = dict(comp="suzuki", order=4, dt=10.0)
+    plan = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, dvtables=d[None], **kw)
+    stat = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0 + 0.2 * d, **kw)
+    a = torch.from_numpy(m.psi0.copy()).cuda()
+    b = torch.from_numpy(m.psi0.copy()).cuda()
+    nv = len(plan.action_times())
+    plan.propagate_driven(a, 4, drive=np.full((4, nv), 0.2))
+    stat.propagate(b, 4)
+    torch.cuda.synchronize()
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-12
+    fresh = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, dvtables=d[None], **kw)
+    x = torch.from_numpy(m.psi0.copy()).cuda()
+    y = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate(x, 5)
+    fresh.propagate(y, 5)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def test_driven_refusals(torch_cuda):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32, dv_params=True)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plain = soprop.Plan.from_model(m, comp="strang", order=2, dt=10.0)
+    with pytest.raises(soprop.SopError):
+        plain.propagate_driven(psi, 1, drive=np.zeros((1, 2)))
+    three = soprop.Plan.from_model(m, comp="strang", order=2, dt=10.0, dvtables=m.dvtables)
+    with pytest.raises(soprop.SopError):
+        three.propagate_driven(psi, 1, drive=np.zeros((1, 2)))
+    one = soprop.Plan.from_model(m, comp="strang", order=2, dt=10.0, dvtables=m.dvtables[:1])
+    with pytest.raises(soprop.SopError):  # beyond the eigen form's phase range
+        one.propagate_driven(psi, 1, drive=np.full((1, 2), 1.0e12))
+    with pytest.raises(soprop.SopError):
+        one.propagate_driven(psi, 1, drive=np.array([[0.0, np.nan]]))
