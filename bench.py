@@ -61,6 +61,10 @@ ENSEMBLES = {"ensemble256_mixed_c128": "c128", "ensemble256_mixed_c64": "c64"}
 # adjoint gradients of the final surface-3 population w.r.t. the three
 # coupling constants (LVC with theta = (0.05, 0.05, 0.2) eV), TJ-6, dt = 10
 ADJOINTS = {"adjoint_lvc3d_128cube_x3_tj6_c128": 128, "adjoint_lvc3d_256cube_x3_tj6_c128": 256}
+# driven potential: the LVC model with the coupling lambda_23 following
+# s(t) = 0.2 + 0.05 sin(2 pi t / 2000 a.u.) eV, the operator formed at every
+# potential action; TJ-6, dt = 10
+DRIVEN = {"driven_lvc3d_128cube_x3_tj6_c128": 128}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
@@ -437,6 +441,95 @@ def ensemble_cpu_baseline(models, man, Ms, budget_s=10.0):
                       f"({sec:.2f} s of FP64 oracle step loops)"}
 
 
+def _drive(t):
+    return 0.2 + 0.05 * np.sin(2.0 * np.pi * np.asarray(t) / 2000.0)
+
+
+def run_driven(a, torch, soprop):
+    """The driven LVC model: a step forms V + s D and its eigen form before
+    every potential action (one action at a time, eager launches)."""
+    from paper_1903_04946_amd import synth
+    n = DRIVEN[a.workload]
+    m = synth.lvc_3d(n=n, dv_params=True)
+    v0 = synth.lvc_vtable_theta(m, np.zeros(3))
+    dtab = m.dvtables[2]
+    dt = 10.0
+    plan = soprop.Plan(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, comp="triple_jump", order=6,
+                       dt=dt, dvtables=dtab[None])
+    M = plan.info.M
+    c = plan.action_times()
+    psi = torch.from_numpy(m.psi0).cuda()
+
+    def samples(k0, k):
+        return _drive((k0 + np.arange(k)[:, None] + c[None, :]) * dt)
+
+    plan.propagate_driven(psi, a.warmup, drive=samples(0, a.warmup))
+    drive = samples(a.warmup, a.steps)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.propagate_driven(psi, a.steps, drive=drive)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    units = m.nsurf * m.npts * M * a.steps
+    plan.set_timing(True)
+    plan.propagate_driven(psi, a.steps, drive=drive)
+    kt = plan.timing_read()
+    plan.set_timing(False)
+    kt = {("form_driven" if k == "other" else k): v for k, v in kt.items()}
+    ev_total = sum(v["ms"] for v in kt.values())
+    scale = ms / ev_total if ev_total > 0 else 1.0
+    dom = max(kt, key=lambda k: kt[k]["ms"])
+    dk = kt[dom]
+    avg_ms = scale * dk["ms"] / dk["count"]
+    achieved = dk["bytes"] / dk["count"] / (avg_ms / 1e3) / 1e9
+    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * scale * v["ms"] / v["count"],
+                   "event_avg_us": 1e3 * v["ms"] / v["count"], "share": v["ms"] / ev_total,
+                   "alg_GBps": v["bytes"] / (scale * v["ms"] / 1e3) / 1e9}
+               for k, v in kt.items()}
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        P = O.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, m.hbar)
+        t1 = time.perf_counter()
+        O.propagate_driven(P, dtab, m.psi0, O.VTV, O.TRIPLE_JUMP, 6, dt, 1, samples(0, 1))
+        sec = time.perf_counter() - t1
+        k = 1
+        if sec < 5.0:  # about 10 s of CPU work
+            k = 1 + max(1, min(20, int(10.0 / max(sec, 1e-3))))
+            t1 = time.perf_counter()
+            O.propagate_driven(P, dtab, m.psi0, O.VTV, O.TRIPLE_JUMP, 6, dt, k, samples(0, k))
+            sec = time.perf_counter() - t1
+        cpu = {"value": m.nsurf * m.npts * M * k / sec, "unit": UNIT, "host": _host_cpu(),
+               "cores": int(O.lib().orc_threads()), "kind": "oracle",
+               "sample": f"{k} driven step(s) ({M} substeps each, every potential action with "
+                         f"its own per-point eigendecomposition) of the same workload "
+                         f"({sec:.1f} s)"}
+    return {
+        "metric": METRIC, "value": units / (ms / 1e3), "unit": UNIT, "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "ndim": 3, "grid": [n] * 3, "nsurf": m.nsurf,
+                   "split": "VTV", "composition": "triple_jump", "order": 6,
+                   "substeps_per_step": M, "dt": dt,
+                   "drive": "lambda_23(t) = 0.2 + 0.05 sin(2 pi t / 2000) eV"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3,
+                     "alg_bytes_per_launch": dk["bytes"] / dk["count"]},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "checks": {"norm_after": plan.observables(psi)["norm"], "wall_s_timed": wall},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def run_adjoint(a, torch, soprop):
     """Forward sweep (checkpoints every K steps) and backward sweep of the
     adjoint for d P_3(T) / d theta over `--steps` time steps (default 500 for
@@ -659,7 +752,8 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS))
+                    choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS)
+                    + sorted(DRIVEN))
     ap.add_argument("--fd-check", action="store_true",
                     help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -691,6 +785,9 @@ def main(argv=None) -> int:
         return 0
     if a.workload in ADJOINTS:
         print(json.dumps(run_adjoint(a, torch, soprop)))
+        return 0
+    if a.workload in DRIVEN:
+        print(json.dumps(run_driven(a, torch, soprop)))
         return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64

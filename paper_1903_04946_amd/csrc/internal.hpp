@@ -188,7 +188,8 @@ constexpr bool eig_form(int ndim, int S, bool f64) { return ndim == 3 && f64 && 
 // kernels_aux.hip
 // tile = 0: [u][entry][point] (1D); tile = C: the z-pass tile layout (3D).
 hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
-                     int tile, void* out);
+                     int tile, void* out,
+                     const double* dtab = nullptr, const double* s_dev = nullptr);
 hipError_t obs_reduce(const DevView& d, const void* psi, const void* psi_hat,
                       const double* vraw_dev, const double* inv_mass, const double* dx,
                       double hbar, double* partials_dev, double* out_dev);
@@ -198,7 +199,8 @@ hipError_t distance_reduce(const DevView& d, const void* psi, const void* phi,
                           double* partials_dev, double* out_dev);
 hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* out);
 // compact eigen form, eig_slots(S) slots per point in the z-pass tile layout
-hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out);
+hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out,
+                     const double* dtab = nullptr, const double* s_dev = nullptr);
 hipError_t set_vparams(const DevView& d, double* vraw, const double* vbase, const double* dv,
                        const double* delta_dev, int nparams);
 hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const double* w_dev,

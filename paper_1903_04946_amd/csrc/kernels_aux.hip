@@ -88,8 +88,10 @@ __device__ __forceinline__ int64_t table_index(int64_t npts, int NE, int tile, i
 template <typename T, int S>
 __global__ void __launch_bounds__(256)
     k_form_vexp(const double* __restrict__ vraw, int64_t npts, const double* __restrict__ taus,
-                int ntau, int tile, int n, cx<T>* __restrict__ out) {
+                int ntau, int tile, int n, cx<T>* __restrict__ out,
+                const double* __restrict__ dtab, const double* __restrict__ s_dev) {
   constexpr int NE = S * (S + 1) / 2;
+  const double sd = dtab ? *s_dev : 0.0;  // driven: V = vraw + s D
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
        x += (int64_t)gridDim.x * blockDim.x) {
     double A[S][S], R[S][S];
@@ -98,7 +100,8 @@ __global__ void __launch_bounds__(256)
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int j = i; j < S; ++j) {
-        const double vij = vraw[(int64_t)e * npts + x];
+        const int64_t o = (int64_t)e * npts + x;
+        const double vij = dtab ? vraw[o] + sd * dtab[o] : vraw[o];
         A[i][j] = vij;
         A[j][i] = vij;
         ++e;
@@ -276,9 +279,11 @@ __global__ void __launch_bounds__(kReduceThreads)
 template <int S>
 __global__ void __launch_bounds__(256)
     k_form_eigq(const double* __restrict__ vraw, int64_t npts, int tile, int n,
-                cx<double>* __restrict__ out) {
+                cx<double>* __restrict__ out, const double* __restrict__ dtab,
+                const double* __restrict__ s_dev) {
   constexpr int NE = S * (S + 1) / 2;
   constexpr int NQ = eig_slots(S);
+  const double sd = dtab ? *s_dev : 0.0;  // driven: V = vraw + s D
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
        x += (int64_t)gridDim.x * blockDim.x) {
     double A[S][S], R[S][S];
@@ -287,7 +292,8 @@ __global__ void __launch_bounds__(256)
     for (int i = 0; i < S; ++i)
 #pragma unroll
       for (int j = i; j < S; ++j) {
-        const double vij = vraw[(int64_t)e * npts + x];
+        const int64_t o = (int64_t)e * npts + x;
+        const double vij = dtab ? vraw[o] + sd * dtab[o] : vraw[o];
         A[i][j] = vij;
         A[j][i] = vij;
         ++e;
@@ -426,11 +432,11 @@ __global__ void __launch_bounds__(kReduceThreads)
 
 template <int S, typename T>
 hipError_t form_impl(const DevView& d, const double* vraw, const double* taus, int ntau, int tile,
-                     void* out) {
+                     void* out, const double* dtab, const double* s_dev) {
   int blocks = (int)((d.npts + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((k_form_vexp<T, S>), dim3(blocks), dim3(256), 0, d.stream, vraw, d.npts,
-                     taus, ntau, tile, d.n[0], (cx<T>*)out);
+                     taus, ntau, tile, d.n[0], (cx<T>*)out, dtab, s_dev);
   return hipGetLastError();
 }
 
@@ -445,24 +451,26 @@ hipError_t obs_points_impl(const DevView& d, const void* psi, const double* vraw
 }  // namespace
 
 hipError_t form_vexp(const DevView& d, const double* vraw_dev, const double* taus, int ntau,
-                     int tile, void* out) {
+                     int tile, void* out, const double* dtab, const double* s_dev) {
   switch (d.S) {
-    case 1: return d.f64 ? form_impl<1, double>(d, vraw_dev, taus, ntau, tile, out)
-                         : form_impl<1, float>(d, vraw_dev, taus, ntau, tile, out);
-    case 2: return d.f64 ? form_impl<2, double>(d, vraw_dev, taus, ntau, tile, out)
-                         : form_impl<2, float>(d, vraw_dev, taus, ntau, tile, out);
-    case 3: return d.f64 ? form_impl<3, double>(d, vraw_dev, taus, ntau, tile, out)
-                         : form_impl<3, float>(d, vraw_dev, taus, ntau, tile, out);
+    case 1: return d.f64 ? form_impl<1, double>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev)
+                         : form_impl<1, float>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev);
+    case 2: return d.f64 ? form_impl<2, double>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev)
+                         : form_impl<2, float>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev);
+    case 3: return d.f64 ? form_impl<3, double>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev)
+                         : form_impl<3, float>(d, vraw_dev, taus, ntau, tile, out, dtab, s_dev);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out) {
+hipError_t form_eigq(const DevView& d, const double* vraw_dev, int tile, void* out,
+                     const double* dtab, const double* s_dev) {
   int blocks = (int)((d.npts + 255) / 256);
   if (blocks > 4096) blocks = 4096;
+  cx<double>* o = (cx<double>*)out;
   switch (d.S) {
-    case 2: hipLaunchKernelGGL(k_form_eigq<2>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
-    case 3: hipLaunchKernelGGL(k_form_eigq<3>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    case 2: hipLaunchKernelGGL(k_form_eigq<2>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], o, dtab, s_dev); break;
+    case 3: hipLaunchKernelGGL(k_form_eigq<3>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], o, dtab, s_dev); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

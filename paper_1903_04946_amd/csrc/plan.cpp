@@ -829,20 +829,26 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
   d.graphs = nullptr;
   d.nact = 1;
   const size_t tab = (size_t)(p->S * (p->S + 1) / 2) * p->npts * p->csize;
+  // formation bytes per potential action: V0 and D read, the table written
+  const double fbytes =
+      (2.0 * (p->S * (p->S + 1) / 2) * sizeof(double) +
+       (p->eig_form ? sop::eig_slots(p->S) * 16.0 : (double)tab / (double)p->npts)) *
+      (double)p->npts;
   const int nact = (int)p->dv.hprog.size();
   for (int64_t n = 0; n < nsteps; ++n) {
     int v = 0;
     for (int a = 0; a < nact; ++a) {
       const int code = p->dv.hprog[a];
       if ((code >> 16) == sop::OP_V) {
+        // V = V0 + s D formed inside the table kernel (no V table written)
         const double* s_dev = p->d_drive + (size_t)n * nv + v++;
-        HIPTRY(sop::set_vparams(d, p->d_vraw, p->d_vbase, p->d_dv, s_dev, 1));
+        sop::TimedLaunch tl(d, sop::KIND_OTHER, fbytes);
         if (p->eig_form) {
-          HIPTRY(sop::form_eigq(d, p->d_vraw, p->tile, p->d_vexp));
+          HIPTRY(sop::form_eigq(d, p->d_vbase, p->tile, p->d_vexp, p->d_dv, s_dev));
         } else {  // only the table this action reads
           const int idx = code & 0xffff;
-          HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + idx, 1, p->tile,
-                                (char*)p->d_vexp + (size_t)idx * tab));
+          HIPTRY(sop::form_vexp(d, p->d_vbase, p->d_taus + idx, 1, p->tile,
+                                (char*)p->d_vexp + (size_t)idx * tab, p->d_dv, s_dev));
         }
       }
       d.prog = p->d_prog + a;
@@ -853,8 +859,7 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
         HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
     }
   }
-  // back to the plan's own potential (the current parameter) for later calls
-  HIPTRY(sop::set_vparams(p->dv, p->d_vraw, p->d_vbase, p->d_dv, p->d_theta, p->nparams));
+  // back to the tables of the plan's own V (its V-table was not touched)
   HIPTRY(form_tables(p));
   HIPTRY(hipStreamSynchronize(st));
   return SOP_OK;
