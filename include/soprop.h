@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SOP_ABI_VERSION 2
+#define SOP_ABI_VERSION 3
 
 typedef enum {
   SOP_OK = 0,
@@ -75,8 +75,16 @@ typedef enum { SOP_SPLIT_VTV = 0, SOP_SPLIT_TVT = 1, SOP_SPLIT_VT = 2, SOP_SPLIT
 
 /* Composition scheme (Sec. "Symmetric composition schemes"): Strang (the
  * bare second-order method, order 2), recursive triple jump (M = 3^n Strang
- * stages for order 2(n+1)) or Suzuki's fractal (M = 5^n). */
-typedef enum { SOP_COMP_STRANG = 0, SOP_COMP_TRIPLE_JUMP = 1, SOP_COMP_SUZUKI = 2 } sop_comp;
+ * stages for order 2(n+1)), Suzuki's fractal (M = 5^n), or a custom
+ * symmetric composition whose M coefficients the caller gives (the
+ * non-recursive "optimal" schemes the paper cites, whose coefficients it does
+ * not print, are of this kind: Table II lists their sequence lengths). */
+typedef enum {
+  SOP_COMP_STRANG = 0,
+  SOP_COMP_TRIPLE_JUMP = 1,
+  SOP_COMP_SUZUKI = 2,
+  SOP_COMP_CUSTOM = 3
+} sop_comp;
 
 typedef enum { SOP_C128 = 0, SOP_C64 = 1 } sop_dtype;
 
@@ -104,6 +112,15 @@ typedef struct {
    * when unused; at most 8.  dvtables: host, [nparams][S(S+1)/2][npts]. */
   int nparams;
   const double* dvtables;
+  /* SOP_COMP_CUSTOM only (0 and NULL otherwise): gamma[ngamma] host, the
+   * composition coefficients gamma_1..gamma_M of the Strang stages, applied
+   * as U(dt) = S(gamma_M dt) ... S(gamma_1 dt).  They must be finite and
+   * nonzero, sum to one (to 1e-12) and be symmetric, gamma_j = gamma_{M+1-j}
+   * (to 1e-14 of the largest |gamma|; the mirrored half is taken from the
+   * first), 1 <= M <= 625.  `order` then states the scheme's order (even,
+   * >= 2); the library does not check it.  The plan copies gamma. */
+  int ngamma;
+  const double* gamma;
 } sop_plan_desc;
 
 /* Sizes of a plan (Table II quantities for its scheme and order). */
@@ -146,6 +163,13 @@ int sop_supported_length(int ndim, int n);
 sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int cap, double* a,
                                double* b, double* a_unq, double* b_unq, int* ia, int* ib,
                                int* counts);
+
+/* The same for a custom symmetric composition (SOP_COMP_CUSTOM): gamma[ngamma]
+ * host, validated as for sop_plan_desc.gamma; split is VTV or TVT.
+ * sop_scheme_sequence refuses comp = SOP_COMP_CUSTOM. */
+sop_status sop_custom_sequence(sop_split split, int ngamma, const double* gamma, int cap,
+                               double* a, double* b, double* a_unq, double* b_unq, int* ia,
+                               int* ib, int* counts);
 
 /* Builds a plan: validates, computes the sequence on the host, uploads the
  * V-table and forms the unique potential tables exp(-i c dt V/hbar) on the

@@ -85,9 +85,11 @@ def lib():
         L.orc_propagate_driven.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
+        L.orc_propagate_gamma.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
+                                          ctypes.c_int64, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
-                  "orc_distance", "orc_propagate_driven",
+                  "orc_distance", "orc_propagate_driven", "orc_propagate_gamma",
                   "orc_exact", "orc_propagate_timed", "orc_threads", "orc_set_threads",
                   "orc_expm_frechet",
                   "orc_gradient"):
@@ -203,6 +205,19 @@ def propagate(prob: Problem, psi: np.ndarray, split: int, scheme: int, order: in
                              int(pruned), _dp(a.view(np.float64)))
     if rc != 0:
         raise ValueError("oracle propagate rejected its arguments")
+    return a
+
+
+def propagate_gamma(prob: Problem, psi: np.ndarray, split: int, gamma, dt: float,
+                    nsteps: int) -> np.ndarray:
+    """nsteps steps of the composition S(gamma_M dt) ... S(gamma_1 dt) of Strang
+    stages (Sec. "Symmetric composition schemes"), each applied unmerged."""
+    a = np.ascontiguousarray(psi, dtype=np.complex128).reshape(prob.shape).copy()
+    g = np.ascontiguousarray(gamma, dtype=np.float64).ravel()
+    rc = lib().orc_propagate_gamma(prob.ptr(), split, g.size, _dp(g), float(dt), int(nsteps),
+                                   _dp(a.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle propagate_gamma rejected its arguments")
     return a
 
 

@@ -604,6 +604,42 @@ int orc_propagate(const orc_problem* prob, int split, int scheme, int order, dou
   return 0;
 }
 
+// Propagation by a composition with given coefficients gamma_1..gamma_M
+// (Sec. "Symmetric composition schemes"): every time step applies the Strang
+// stages S(gamma_1 dt), ..., S(gamma_M dt) in turn, each one as A(gamma/2)
+// B(gamma) A(gamma/2) with nothing merged (Eq. second_order_so scaled by
+// gamma).  split is VTV or TVT.  The coefficients are taken as given: no
+// symmetry or sum is required here.  Returns 0 or -1.
+int orc_propagate_gamma(const orc_problem* prob, int split, int M, const double* gamma,
+                        double dt, int64_t nsteps, double* psi_io) {
+  Grid g;
+  if (!make_grid(prob, g) || !prob->vtable || nsteps < 0 || M < 1 || !gamma) return -1;
+  if (split != ORC_VTV && split != ORC_TVT) return -1;
+  PotentialEigen pe;
+  potential_eigen(g, prob->vtable, pe);
+  cd* psi = reinterpret_cast<cd*>(psi_io);
+  const bool aV = a_is_potential(split);
+  auto A = [&](double tau) {
+    if (aV)
+      potential_action(g, pe, tau, psi);
+    else
+      kinetic_action(g, tau, psi);
+  };
+  auto B = [&](double tau) {
+    if (aV)
+      kinetic_action(g, tau, psi);
+    else
+      potential_action(g, pe, tau, psi);
+  };
+  for (int64_t step = 0; step < nsteps; ++step)
+    for (int k = 0; k < M; ++k) {
+      A(0.5 * gamma[k] * dt);
+      B(gamma[k] * dt);
+      A(0.5 * gamma[k] * dt);
+    }
+  return 0;
+}
+
 // Driven potential V(x, t) = V0(x) + s(t) D(x) (Sec. "Pruning splitting
 // coefficients": a time-dependent operator is formed on the fly, at every
 // action).  The v-th potential action of step n uses the drive value

@@ -118,7 +118,41 @@ void unique_palindrome(const std::vector<double>& v, std::vector<double>& unq,
   }
 }
 
-sop_status build_sequence(sop_split split, sop_comp comp, int order, Sequence& s) {
+// Largest number of Strang stages a custom composition may have (Suzuki's
+// tenth order, the longest built-in scheme, has 625).
+constexpr int kMaxCustomStages = 625;
+
+// Caller-supplied composition coefficients (Sec. "Symmetric composition
+// schemes": a composition of Strang stages with coefficients gamma_1..gamma_M
+// that sum to one, symmetric under j -> M+1-j so that the composed method is
+// symmetric).  Symmetry is required because the unique-coefficient search
+// covers only the first half of the sequence.
+sop_status custom_composition(int M, const double* gamma, std::vector<ld>& g) {
+  if (!gamma) return fail(SOP_ERR_INVALID, "a custom composition needs gamma");
+  if (M < 1 || M > kMaxCustomStages)
+    return fail(SOP_ERR_INVALID, "custom composition: ngamma must be 1.." +
+                                     std::to_string(kMaxCustomStages));
+  double gmax = 0;
+  ld sum = 0;
+  for (int j = 0; j < M; ++j) {
+    if (!std::isfinite(gamma[j]) || gamma[j] == 0)
+      return fail(SOP_ERR_INVALID, "custom composition: every gamma must be finite and nonzero");
+    gmax = std::fmax(gmax, std::fabs(gamma[j]));
+    sum += gamma[j];
+  }
+  for (int j = 0; j < M / 2; ++j)
+    if (std::fabs(gamma[j] - gamma[M - 1 - j]) > 1e-14 * gmax)
+      return fail(SOP_ERR_INVALID, "custom composition: gamma must be symmetric (gamma_j = gamma_{M+1-j})");
+  if (std::fabs((double)(sum - 1.0L)) > 1e-12 * std::fmax(1.0, gmax))
+    return fail(SOP_ERR_INVALID, "custom composition: gamma must sum to 1");
+  g.assign(gamma, gamma + M);
+  // mirror exactly, so that the pruned sequence is an exact palindrome
+  for (int j = 0; j < M / 2; ++j) g[M - 1 - j] = g[j];
+  return SOP_OK;
+}
+
+sop_status build_sequence(sop_split split, sop_comp comp, int order, int ngamma,
+                          const double* gamma, Sequence& s) {
   s = Sequence();
   if (split == SOP_SPLIT_VT || split == SOP_SPLIT_TV) {
     if (order != 1 || comp != SOP_COMP_STRANG)
@@ -135,9 +169,17 @@ sop_status build_sequence(sop_split split, sop_comp comp, int order, Sequence& s
   }
   if (split != SOP_SPLIT_VTV && split != SOP_SPLIT_TVT)
     return fail(SOP_ERR_INVALID, "unknown splitting");
+  if (comp != SOP_COMP_CUSTOM && (ngamma != 0 || gamma))
+    return fail(SOP_ERR_INVALID, "gamma is given only with comp = SOP_COMP_CUSTOM");
   std::vector<ld> g;
-  if (!composition(comp, order, g))
+  if (comp == SOP_COMP_CUSTOM) {
+    if (order < 2 || (order & 1))
+      return fail(SOP_ERR_INVALID, "custom composition: order (the stated order) must be even and >= 2");
+    const sop_status st = custom_composition(ngamma, gamma, g);
+    if (st != SOP_OK) return st;
+  } else if (!composition(comp, order, g)) {
     return fail(SOP_ERR_INVALID, "invalid composition/order (Strang: 2; TJ/SF: 2..10 even)");
+  }
   const int M = (int)g.size();
   s.M = M;
   // Pruned sequence (Eq. merging_splitting_coeff_b_zero applied to every
@@ -396,12 +438,9 @@ const char* sop_last_error(void) { return g_err.c_str(); }
 
 int sop_supported_length(int ndim, int n) { return supported_length(ndim, n) ? 1 : 0; }
 
-sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int cap, double* a,
-                               double* b, double* a_unq, double* b_unq, int* ia, int* ib,
-                               int* counts) {
-  Sequence s;
-  sop_status st = build_sequence(split, comp, order, s);
-  if (st != SOP_OK) return st;
+namespace {
+sop_status write_sequence(const Sequence& s, int cap, double* a, double* b, double* a_unq,
+                          double* b_unq, int* ia, int* ib, int* counts) {
   const int N = (int)s.a.size();
   if (cap < N) return fail(SOP_ERR_INVALID, "capacity smaller than the sequence length");
   for (int j = 0; j < N; ++j) {
@@ -421,6 +460,27 @@ sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int ca
     counts[3] = s.M;
   }
   return SOP_OK;
+}
+}  // namespace
+
+sop_status sop_scheme_sequence(sop_split split, sop_comp comp, int order, int cap, double* a,
+                               double* b, double* a_unq, double* b_unq, int* ia, int* ib,
+                               int* counts) {
+  if (comp == SOP_COMP_CUSTOM)
+    return fail(SOP_ERR_INVALID, "custom compositions go through sop_custom_sequence");
+  Sequence s;
+  const sop_status st = build_sequence(split, comp, order, 0, nullptr, s);
+  if (st != SOP_OK) return st;
+  return write_sequence(s, cap, a, b, a_unq, b_unq, ia, ib, counts);
+}
+
+sop_status sop_custom_sequence(sop_split split, int ngamma, const double* gamma, int cap,
+                               double* a, double* b, double* a_unq, double* b_unq, int* ia,
+                               int* ib, int* counts) {
+  Sequence s;
+  const sop_status st = build_sequence(split, SOP_COMP_CUSTOM, 2, ngamma, gamma, s);
+  if (st != SOP_OK) return st;
+  return write_sequence(s, cap, a, b, a_unq, b_unq, ia, ib, counts);
 }
 
 sop_status sop_plan_create(const sop_plan_desc* desc, void* hip_stream, sop_plan** out) {
@@ -446,7 +506,7 @@ sop_status sop_plan_create_with_allocator(const sop_plan_desc* desc, void* hip_s
     }
   } guard{p};
 
-  st = build_sequence(desc->split, desc->comp, desc->order, p->seq);
+  st = build_sequence(desc->split, desc->comp, desc->order, desc->ngamma, desc->gamma, p->seq);
   if (st != SOP_OK) return st;
   p->ndim = desc->grid.ndim;
   p->S = desc->nsurf;

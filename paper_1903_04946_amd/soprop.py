@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsoprop.so")
 
 SPLITS = {"VTV": 0, "TVT": 1, "VT": 2, "TV": 3}
-COMPS = {"strang": 0, "triple_jump": 1, "tj": 1, "suzuki": 2, "sf": 2}
+COMPS = {"strang": 0, "triple_jump": 1, "tj": 1, "suzuki": 2, "sf": 2, "custom": 3}
+ABI_VERSION = 3
 C128, C64 = 0, 1
 
 
@@ -36,7 +37,8 @@ class _Desc(ctypes.Structure):
                 ("vtable", ctypes.POINTER(ctypes.c_double)),
                 ("split", ctypes.c_int), ("comp", ctypes.c_int), ("order", ctypes.c_int),
                 ("dt", ctypes.c_double), ("hbar", ctypes.c_double), ("dtype", ctypes.c_int),
-                ("nparams", ctypes.c_int), ("dvtables", ctypes.POINTER(ctypes.c_double))]
+                ("nparams", ctypes.c_int), ("dvtables", ctypes.POINTER(ctypes.c_double)),
+                ("ngamma", ctypes.c_int), ("gamma", ctypes.POINTER(ctypes.c_double))]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -78,7 +80,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_supported_length",
-           "sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
+           "sop_scheme_sequence", "sop_custom_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
            "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
            "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
@@ -104,11 +106,16 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     dp, ip, vp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
     L.sop_abi_version.restype = ctypes.c_int
+    if L.sop_abi_version() != ABI_VERSION:
+        raise SopError(f"{LIB_PATH} has ABI version {L.sop_abi_version()}, the binding "
+                       f"expects {ABI_VERSION}; rebuild it")
     L.sop_status_string.restype = ctypes.c_char_p
     L.sop_status_string.argtypes = [ctypes.c_int]
     L.sop_last_error.restype = ctypes.c_char_p
     L.sop_supported_length.argtypes = [ctypes.c_int, ctypes.c_int]
     L.sop_scheme_sequence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      dp, dp, dp, dp, ip, ip, ip]
+    L.sop_custom_sequence.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
                                       dp, dp, dp, dp, ip, ip, ip]
     L.sop_plan_create.argtypes = [ctypes.POINTER(_Desc), vp, ctypes.POINTER(vp)]
     L.sop_plan_create_with_allocator.argtypes = [ctypes.POINTER(_Desc), vp,
@@ -172,16 +179,24 @@ def _ip(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
-def scheme_sequence(split: str, comp: str, order: int):
-    """Pruned sequence and unique coefficients from the library's planner."""
+def scheme_sequence(split: str, comp: str, order: int = 2, gamma=None):
+    """Pruned sequence and unique coefficients from the library's planner
+    (comp = 'custom' takes the symmetric coefficients gamma)."""
     cap = 4096
     a, b, au, bu = (np.zeros(cap) for _ in range(4))
     ia = np.zeros(cap, np.int32)
     ib = np.zeros(cap, np.int32)
     counts = np.zeros(4, np.int32)
-    _check(lib().sop_scheme_sequence(SPLITS[split], COMPS[comp], order, cap, _dp(a), _dp(b),
-                                     _dp(au), _dp(bu), _ip(ia), _ip(ib), _ip(counts)),
-           "sop_scheme_sequence")
+    if comp == "custom":
+        g = np.ascontiguousarray(gamma, dtype=np.float64)
+        _check(lib().sop_custom_sequence(SPLITS[split], g.size, _dp(g), cap, _dp(a), _dp(b),
+                                         _dp(au), _dp(bu), _ip(ia), _ip(ib), _ip(counts)),
+               "sop_custom_sequence")
+    else:
+        _check(lib().sop_scheme_sequence(SPLITS[split], COMPS[comp], order, cap, _dp(a),
+                                         _dp(b), _dp(au), _dp(bu), _ip(ia), _ip(ib),
+                                         _ip(counts)),
+               "sop_scheme_sequence")
     N, na, nb, M = (int(c) for c in counts)
     return {"a": a[:N].copy(), "b": b[:N].copy(), "a_unq": au[:na].copy(),
             "b_unq": bu[:nb].copy(), "ia": ia[:N].copy(), "ib": ib[:N].copy(), "M": M}
@@ -214,7 +229,8 @@ class Plan:
     n, lo, hi: per-axis grid (1D or cubic 3D); nsurf; inv_mass per axis;
     vtable: float64 [S(S+1)/2][npts] packed upper triangle of V(q);
     split: 'VTV' | 'TVT' | 'VT' | 'TV'; comp: 'strang' | 'triple_jump' |
-    'suzuki'; order; dt; dtype: torch.complex128 or torch.complex64;
+    'suzuki' | 'custom' (gamma: the symmetric composition coefficients);
+    order; dt; dtype: torch.complex128 or torch.complex64;
     allocator: None (the library's hipMalloc) or 'torch' (the plan's device
     buffers come from PyTorch's caching allocator,
     sop_plan_create_with_allocator).
@@ -222,7 +238,7 @@ class Plan:
 
     def __init__(self, n, lo, hi, nsurf, inv_mass, vtable, split="VTV", comp="strang",
                  order=2, dt=0.01, hbar=1.0, dtype=None, stream=None, dvtables=None,
-                 allocator=None):
+                 allocator=None, gamma=None):
         import torch
         if dtype is None:
             dtype = torch.complex128
@@ -252,6 +268,10 @@ class Plan:
         d.split = SPLITS[split]
         d.comp = COMPS[comp]
         d.order = int(order)
+        if gamma is not None:
+            self._gamma = np.ascontiguousarray(gamma, dtype=np.float64).ravel()
+            d.ngamma = self._gamma.size
+            d.gamma = _dp(self._gamma)
         d.dt = float(dt)
         self.dt = float(dt)
         d.hbar = float(hbar)

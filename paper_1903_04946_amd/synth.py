@@ -204,6 +204,37 @@ def random_state(shape, seed, dV=1.0) -> np.ndarray:
     return normalise(psi, dV)
 
 
+# ----------------------------------------------------------------- compositions
+# Coefficients handed to a custom symmetric composition, as inputs.
+# Yoshida (1990), the sixth-order symmetric composition of seven Strang stages
+# (his "solution A", 15 digits as published): (w3, w2, w1, w0, w1, w2, w3)
+# with w0 = 1 - 2 (w1 + w2 + w3).
+_YOSHIDA6_W = (-1.17767998417887, 0.235573213359357, 0.784513610477560)
+
+
+def yoshida6_gammas() -> np.ndarray:
+    w1, w2, w3 = _YOSHIDA6_W
+    w0 = 1.0 - 2.0 * (w1 + w2 + w3)
+    return np.array([w3, w2, w1, w0, w1, w2, w3])
+
+
+def random_symmetric_gammas(M: int, seed: int, spread: float = 0.4) -> np.ndarray:
+    """M coefficients, symmetric (g_j = g_{M+1-j}), summing to one, whose first
+    (M+1)/2 values are distinct: uniform draws around 1/M, the middle one then
+    set so that the sum is one."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = (M + 1) // 2
+    g = np.empty(M)
+    h = (1.0 + spread * rng.uniform(-1.0, 1.0, size=half)) / M
+    g[:half] = h
+    g[M - half:] = h[::-1]
+    if M % 2:
+        g[half - 1] = 1.0 - 2.0 * h[:half - 1].sum()
+    else:
+        g *= 1.0 / g.sum()
+    return g
+
+
 # ----------------------------------------------------------------- batches
 def batch_manifest(count: int = 256, seed: int = 4946, t_final: float = 0.5):
     """Members of a batched ensemble: grid type, x0, p0, dt, order, scheme.

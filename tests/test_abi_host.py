@@ -13,7 +13,7 @@ import re
 import numpy as np
 import pytest
 
-from paper_1903_04946_amd import soprop
+from paper_1903_04946_amd import soprop, synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "soprop.h")
@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(soprop.EXPORTS)
-    assert L.sop_abi_version() == 2
+    assert L.sop_abi_version() == 3
 
 
 def test_supported_lengths(L):
@@ -151,3 +151,89 @@ def test_batch_argument_checks(L):
     assert L.sop_batch_set_option(None, 1, 0) == 1
     assert L.sop_batch_describe(None, None, 0, None) == 1
     assert L.sop_batch_destroy(None) == 0
+
+
+# ------------------------------------------------------------------ custom compositions
+def optimal_rows():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "table2_optimal_counts.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append(tuple(int(x) for x in line.split()))
+    return rows
+
+
+@pytest.mark.parametrize("row", optimal_rows(), ids=lambda r: f"optimal{r[0]}")
+@pytest.mark.parametrize("split", ["VTV", "TVT"])
+def test_custom_sequence_table2_optimal_rows(L, row, split):
+    """Table II's rows of the optimal schemes from symmetric coefficients of
+    the same stage counts, and the pruned sequence against its definition."""
+    order, before, after, na, nb = row
+    M = before // 3
+    g = synth.random_symmetric_gammas(M, seed=order)
+    q = soprop.scheme_sequence(split, "custom", gamma=g)
+    assert q["M"] == M and len(q["a"]) == M + 1
+    assert len(q["a"]) + M == after
+    assert (len(q["a_unq"]), len(q["b_unq"])) == (na, nb)
+    a = np.concatenate([[g[0] / 2], (g[:-1] + g[1:]) / 2, [g[-1] / 2]])
+    np.testing.assert_allclose(q["a"], a, rtol=2.3e-16, atol=0)
+    np.testing.assert_array_equal(q["b"][:M], g)
+    assert q["b"][M] == 0 and q["ib"][M] == -1
+    np.testing.assert_array_equal(q["a_unq"][q["ia"]], q["a"])
+    np.testing.assert_array_equal(q["b_unq"][q["ib"][:M]], q["b"][:M])
+
+
+@pytest.mark.parametrize("comp,scheme,order", [("triple_jump", 1, 6), ("suzuki", 2, 4),
+                                               ("triple_jump", 1, 8)])
+def test_custom_sequence_of_builtin_gammas(L, orc, comp, scheme, order):
+    """The recursive schemes' coefficients (from the oracle) given as a custom
+    list give the built-in sequence and the same unique tables."""
+    g = orc.gammas(scheme, order)
+    q = soprop.scheme_sequence("VTV", "custom", gamma=g)
+    r = soprop.scheme_sequence("VTV", comp, order)
+    # the built-in sums come from long-double coefficients, the custom ones
+    # from the same coefficients rounded to double first: two roundings apart
+    np.testing.assert_allclose(q["a"], r["a"], rtol=4.5e-16, atol=0)
+    np.testing.assert_allclose(q["b"], r["b"], rtol=2.3e-16, atol=0)
+    for k in ("ia", "ib"):
+        np.testing.assert_array_equal(q[k], r[k])
+    assert (len(q["a_unq"]), len(q["b_unq"])) == (len(r["a_unq"]), len(r["b_unq"]))
+
+
+def test_custom_sequence_rejects(L):
+    g = synth.random_symmetric_gammas(9, seed=1)
+    bad = [g[::-1] * np.r_[1.0, np.ones(8)] + np.r_[1e-9, np.zeros(7), -1e-9],  # asymmetric
+           g * 1.01,                                                         # sum != 1
+           np.r_[0.5, 0.0, 0.5],                                            # a zero stage
+           np.r_[np.nan, 1.0, np.nan],
+           np.full(626, 1 / 626.0)]                                          # too many stages
+    for b in bad:
+        with pytest.raises(soprop.SopError):
+            soprop.scheme_sequence("VTV", "custom", gamma=b)
+    with pytest.raises(soprop.SopError):
+        soprop.scheme_sequence("VTV", "custom", gamma=np.zeros(0))
+    with pytest.raises(soprop.SopError):
+        soprop.scheme_sequence("VT", "custom", gamma=g)
+    with pytest.raises(soprop.SopError):  # custom schemes take their own entry point
+        soprop.scheme_sequence("VTV", "custom", order=2, gamma=None)
+    assert L.sop_scheme_sequence(0, 3, 2, 64, None, None, None, None, None, None, None) == 1
+    # 625 equal stages are accepted
+    q = soprop.scheme_sequence("TVT", "custom", gamma=np.full(625, 1 / 625.0))
+    assert q["M"] == 625 and len(q["a_unq"]) == 2 and len(q["b_unq"]) == 1
+
+
+def test_custom_desc_validation_before_device_work(L):
+    g = synth.random_symmetric_gammas(9, seed=1)
+    cases = [({"comp": 3}, None),          # custom without gamma
+             ({"comp": 1, "order": 4}, g),  # gamma on a built-in scheme
+             ({"comp": 3, "order": 3}, g),  # stated order odd
+             ({"comp": 3, "order": 6}, g * 1.5)]
+    for kw, gam in cases:
+        d, keep = _desc(**kw)
+        if gam is not None:
+            gam = np.ascontiguousarray(gam)
+            d.ngamma = gam.size
+            d.gamma = soprop._dp(gam)
+        h = ctypes.c_void_p()
+        assert L.sop_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == 1, kw
+        assert h.value is None
+        assert "gamma" in L.sop_last_error().decode() or "order" in L.sop_last_error().decode()
