@@ -349,16 +349,36 @@ sop_status sop_adjoint(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int
 enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2 };
 sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
+/* Trigonometric interpolation of a state onto another grid (Appendix B:
+ * states on grids of different range and density are compared through the
+ * trigonometric interpolant of the one on the sparser grid).  psi_dst
+ * (dst's grid, layout [S][grid]) receives, on every surface and at every
+ * point of dst's grid, the value of psi_src's interpolant: along each axis
+ * sum over |k| < n/2 of c_k exp(2 pi i k xi), c_k the DFT coefficients of the
+ * samples divided by n, xi = (x - lo)/(hi - lo) of src's grid, plus for even
+ * n the Nyquist term c_{n/2} cos(pi n xi); points outside src's [lo, hi)
+ * receive zero.  Equal grids give psi_dst = psi_src up to rounding.
+ * Both plans need the same ndim and nsurf and SOP_C128 (SOP_ERR_UNSUPPORTED
+ * otherwise); their lengths and boxes may differ freely (destination axes up
+ * to 65535 points).  psi_src and psi_dst are device buffers and must differ.
+ * Runs asynchronously on dst's stream (psi_src must be ready there); the
+ * axis matrices and intermediate states live in a workspace that dst keeps
+ * and grows on demand (16 bytes per matrix entry and per intermediate
+ * element; growing it synchronises dst's stream), released with dst. */
+sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* dst,
+                           void* psi_dst);
+
 /* Per-kernel timing (measurement aid).  While enabled, every kernel launch
  * of the plan is bracketed by HIP events on the plan's stream, and
  * consecutive launches within one call share their boundary event (so the
  * intervals of a propagate call tile its wall time).  Graph capture is off
  * while timing is on.  sop_timing_read synchronises the stream and returns, per kernel kind
  * (SOP_KIND_*), the summed event time in ms, the launch count and the summed
- * algorithmic bytes (state read + written, tables read), then clears the
+ * algorithmic bytes (state read + written, tables read; for SOP_KIND_INTERP,
+ * the products of sop_interpolate, FP64 flops instead), then clears the
  * records.  ms, counts, bytes: host arrays of SOP_KIND_COUNT entries. */
 enum { SOP_KIND_ZPASS = 0, SOP_KIND_YPASS = 1, SOP_KIND_XPASS = 2, SOP_KIND_1D = 3,
-       SOP_KIND_OTHER = 4, SOP_KIND_PLANE = 5, SOP_KIND_COUNT = 6 };
+       SOP_KIND_OTHER = 4, SOP_KIND_PLANE = 5, SOP_KIND_INTERP = 6, SOP_KIND_COUNT = 7 };
 sop_status sop_plan_set_timing(sop_plan* plan, int enable);
 sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* bytes);
 

@@ -85,11 +85,14 @@ def lib():
         L.orc_propagate_driven.argtypes = [pp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_exact.argtypes = [pp, ctypes.c_double, dp]
+        ip_ = ctypes.POINTER(ctypes.c_int)
+        L.orc_interpolate.argtypes = [ctypes.c_int, ctypes.c_int, ip_, dp, dp, dp, ip_, dp, dp, dp]
         L.orc_propagate_gamma.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
                                           ctypes.c_int64, dp]
         for f in ("orc_gammas", "orc_splitting", "orc_unique", "orc_fft", "orc_expm_potential",
                   "orc_eigh", "orc_propagate", "orc_action", "orc_observables", "orc_overlap",
                   "orc_distance", "orc_propagate_driven", "orc_propagate_gamma",
+                  "orc_interpolate",
                   "orc_exact", "orc_propagate_timed", "orc_threads", "orc_set_threads",
                   "orc_expm_frechet",
                   "orc_gradient"):
@@ -219,6 +222,24 @@ def propagate_gamma(prob: Problem, psi: np.ndarray, split: int, gamma, dt: float
     if rc != 0:
         raise ValueError("oracle propagate_gamma rejected its arguments")
     return a
+
+
+def interpolate(psi: np.ndarray, n_src, lo_src, hi_src, n_dst, lo_dst, hi_dst) -> np.ndarray:
+    """Trigonometric interpolant of psi [S][grid] (grid n_src on [lo, hi) per
+    axis) evaluated on the grid n_dst on [lo_dst, hi_dst); zero outside."""
+    nd = len(n_src)
+    a = np.ascontiguousarray(psi, dtype=np.complex128)
+    S = a.shape[0]
+    assert tuple(a.shape[1:]) == tuple(n_src)
+    out = np.zeros((S, *n_dst), np.complex128)
+    ns = np.ascontiguousarray(n_src, dtype=np.int32)
+    nn = np.ascontiguousarray(n_dst, dtype=np.int32)
+    f = [np.ascontiguousarray(v, dtype=np.float64) for v in (lo_src, hi_src, lo_dst, hi_dst)]
+    rc = lib().orc_interpolate(nd, S, _ip(ns), _dp(f[0]), _dp(f[1]), _dp(a.view(np.float64)),
+                               _ip(nn), _dp(f[2]), _dp(f[3]), _dp(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle interpolate rejected its arguments")
+    return out
 
 
 def set_threads(n: int) -> int:

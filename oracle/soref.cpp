@@ -685,6 +685,86 @@ int orc_propagate_driven(const orc_problem* prob, const double* dtable, int spli
   return 0;
 }
 
+// Trigonometric interpolation (Appendix B: a state on one grid is compared
+// with a state on a grid of other range and density through the
+// trigonometric interpolant of the one on the sparser grid).  Along one axis,
+// the samples u_m at x_m = lo + m dx (n points, L = hi - lo) define
+// c_k = (1/n) sum_m u_m exp(-2 pi i k m/n), and the interpolant at x is
+// sum_{|k| < n/2} c_k exp(2 pi i k xi) + [n even] c_{n/2} cos(pi n xi),
+// xi = (x - lo)/L; it is taken as zero where xi is outside [0, 1).  The 3D
+// interpolant is this applied along every axis (the axes separate).  The
+// destination points are x = lo_d + j (hi_d - lo_d)/n_d.  Sums and phases in
+// long double.  psi arrays are [S][grid] complex (interleaved).  Returns 0 or -1.
+static void interp_line(int n, double lo, double hi, const cd* u, int64_t su, int nd,
+                        double lod, double hid, cd* out, int64_t so) {
+  std::vector<std::complex<ld>> c(n);
+  for (int k = 0; k < n; ++k) {
+    std::complex<ld> acc = 0;
+    for (int m = 0; m < n; ++m) {
+      const ld ph = -2 * PI_L * (ld)(((int64_t)k * m) % n) / n;
+      acc += std::complex<ld>(u[m * su].real(), u[m * su].imag()) *
+             std::complex<ld>(cosl(ph), sinl(ph));
+    }
+    c[k] = acc / (ld)n;
+  }
+  const double dxd = (hid - lod) / nd;
+  for (int j = 0; j < nd; ++j) {
+    const double x = lod + j * dxd;
+    const double xi = (x - lo) / (hi - lo);
+    std::complex<ld> v = 0;
+    if (xi >= 0.0 && xi < 1.0) {
+      for (int k = -((n - 1) / 2); k <= (n - 1) / 2; ++k) {
+        const ld ph = 2 * PI_L * (ld)k * (ld)xi;
+        v += c[(k + n) % n] * std::complex<ld>(cosl(ph), sinl(ph));
+      }
+      if (n % 2 == 0) v += c[n / 2] * cosl(PI_L * (ld)n * (ld)xi);
+    }
+    out[j * so] = cd((double)v.real(), (double)v.imag());
+  }
+}
+
+int orc_interpolate(int ndim, int S, const int* n_src, const double* lo_src, const double* hi_src,
+                    const double* psi_src, const int* n_dst, const double* lo_dst,
+                    const double* hi_dst, double* psi_dst) {
+  if ((ndim != 1 && ndim != 3) || S < 1 || !psi_src || !psi_dst) return -1;
+  int64_t cur[3] = {1, 1, 1};
+  for (int a = 0; a < ndim; ++a) {
+    if (n_src[a] < 1 || n_dst[a] < 1 || !(hi_src[a] > lo_src[a]) || !(hi_dst[a] > lo_dst[a]))
+      return -1;
+    cur[a] = n_src[a];
+  }
+  std::vector<cd> buf(reinterpret_cast<const cd*>(psi_src),
+                      reinterpret_cast<const cd*>(psi_src) + S * cur[0] * cur[1] * cur[2]);
+  // interpolate axis by axis, last (contiguous) axis first
+  for (int a = ndim - 1; a >= 0; --a) {
+    int64_t shape[3] = {cur[0], cur[1], cur[2]};
+    int64_t nshape[3] = {cur[0], cur[1], cur[2]};
+    nshape[a] = n_dst[a];
+    int64_t stride[3] = {shape[1] * shape[2], shape[2], 1};
+    int64_t nstride[3] = {nshape[1] * nshape[2], nshape[2], 1};
+    const int64_t nblock = S * shape[0] * shape[1] * shape[2];
+    std::vector<cd> next((size_t)S * nshape[0] * nshape[1] * nshape[2]);
+    const int64_t per_s = shape[0] * shape[1] * shape[2];
+    const int64_t nper_s = nshape[0] * nshape[1] * nshape[2];
+    (void)nblock;
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int s = 0; s < S; ++s)
+      for (int64_t i0 = 0; i0 < (a == 0 ? 1 : shape[0]); ++i0)
+        for (int64_t i1 = 0; i1 < (a == 1 || ndim == 1 ? 1 : shape[1]); ++i1)
+          for (int64_t i2 = 0; i2 < (a == 2 || ndim == 1 ? 1 : shape[2]); ++i2) {
+            const int64_t src_off = s * per_s + i0 * stride[0] + i1 * stride[1] + i2 * stride[2];
+            const int64_t dst_off =
+                s * nper_s + i0 * nstride[0] + i1 * nstride[1] + i2 * nstride[2];
+            interp_line((int)shape[a], lo_src[a], hi_src[a], buf.data() + src_off, stride[a],
+                        n_dst[a], lo_dst[a], hi_dst[a], next.data() + dst_off, nstride[a]);
+          }
+    buf.swap(next);
+    cur[a] = n_dst[a];
+  }
+  std::copy(buf.begin(), buf.end(), reinterpret_cast<cd*>(psi_dst));
+  return 0;
+}
+
 // Same as orc_propagate, and writes to *seconds the wall time of the step
 // loop alone (std::chrono::steady_clock; the per-point eigen-decomposition
 // done before the loop is excluded).  Used to time the oracle as a CPU

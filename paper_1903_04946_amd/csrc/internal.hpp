@@ -22,7 +22,7 @@ inline int prog_idx(int e) { return e & 0xffff; }
 
 // Kernel kinds reported by the timing hook.
 enum { KIND_ZPASS = 0, KIND_YPASS = 1, KIND_XPASS = 2, KIND_1D = 3, KIND_OTHER = 4, KIND_PLANE = 5,
-       KIND_COUNT = 6 };
+       KIND_INTERP = 6, KIND_COUNT = 7 };
 
 // Optional per-launch timing: HIP events recorded on the plan's stream
 // between kernel launches, resolved after a synchronisation.  Consecutive
@@ -184,6 +184,23 @@ constexpr int eig_slots(int S) { return S == 3 ? 4 : 2; }
 // per-coefficient tables (it does when every phase tau lam stays within
 // kPhaseMax).
 constexpr bool eig_form(int ndim, int S, bool f64) { return ndim == 3 && f64 && S >= 2; }
+
+// kernels_interp.hip: trigonometric interpolation between uniform grids.
+// Complex FP64 product C[b] = A[b] B[b] (M x K by K x N) with element and
+// batch strides; A needs sak = 1 or sai = 1, B sbj = 1 or sbk = 1.
+struct CgemmArgs {
+  const double2* A = nullptr;
+  const double2* B = nullptr;
+  double2* C = nullptr;
+  int M = 0, N = 0, K = 0;
+  long long sai = 0, sak = 0, sbk = 0, sbj = 0, sci = 0, scj = 0;
+  long long bsa = 0, bsb = 0, bsc = 0;
+};
+// W [nd][n]: the interpolation matrix from the n-point grid on [lo, hi) to the
+// nd-point grid on [lod, hid).
+hipError_t interp_weights(hipStream_t s, double2* W, int n, double lo, double hi, int nd,
+                          double lod, double hid);
+hipError_t cgemm(hipStream_t s, const CgemmArgs& g, int batch);
 
 // kernels_aux.hip
 // tile = 0: [u][entry][point] (1D); tile = C: the z-pass tile layout (3D).

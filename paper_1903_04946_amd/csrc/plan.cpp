@@ -228,6 +228,8 @@ struct sop_plan {
   int* d_prog1 = nullptr;  // single-action programs {V(0), T(0)}
   double* d_taus = nullptr;
   void* d_scratch = nullptr;
+  void* d_iws = nullptr;  // sop_interpolate workspace (grown on demand)
+  size_t iws_bytes = 0;
   void* d_atab = nullptr;  // table for sop_apply_action
   void* d_akin = nullptr;
   double* d_part = nullptr;
@@ -280,7 +282,7 @@ void free_plan(sop_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
-                  p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive};
+                  p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive, p->d_iws};
   delete p->graphs;
   for (void* b : bufs) {
     if (!b) continue;
@@ -768,6 +770,137 @@ sop_status sop_distance(sop_plan* p, const void* psi, const void* phi, double* o
   HIPTRY(hipStreamSynchronize(p->dv.stream));
   out[0] = std::sqrt(raw[0] * p->dV);
   out[1] = raw[1] > 0.0 ? std::sqrt(raw[0] / raw[1]) : 0.0;
+  return SOP_OK;
+}
+
+sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* dst,
+                           void* psi_dst) {
+  if (!src || !dst || !psi_src || !psi_dst) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (psi_src == psi_dst) return fail(SOP_ERR_INVALID, "psi_src and psi_dst must differ");
+  if (src->ndim != dst->ndim || src->S != dst->S)
+    return fail(SOP_ERR_INVALID, "plans differ in ndim or nsurf");
+  if (src->dtype != SOP_C128 || dst->dtype != SOP_C128)
+    return fail(SOP_ERR_UNSUPPORTED, "interpolation is implemented for SOP_C128 plans");
+  const int nax = src->ndim;
+  for (int a = 0; a < nax; ++a)
+    if (dst->n[a] > 65535) return fail(SOP_ERR_UNSUPPORTED, "destination axis too long");
+  const int S = src->S;
+  // axis a of the arrays: 0 slowest; 1D grids use axis 0 only
+  const long long ns[3] = {src->n[0], nax == 3 ? src->n[1] : 1, nax == 3 ? src->n[2] : 1};
+  const long long nd[3] = {dst->n[0], nax == 3 ? dst->n[1] : 1, nax == 3 ? dst->n[2] : 1};
+  // workspace: the axis matrices, then (3D) the state after z and after y
+  size_t wel = 0;
+  for (int a = 0; a < nax; ++a) wel += (size_t)nd[a] * ns[a];
+  const size_t t1 = nax == 3 ? (size_t)S * ns[0] * ns[1] * nd[2] : 0;
+  const size_t t2 = nax == 3 ? (size_t)S * ns[0] * nd[1] * nd[2] : 0;
+  const size_t need = (wel + t1 + t2) * sizeof(double2);
+  if (need > dst->iws_bytes) {
+    if (dst->d_iws) {
+      HIPTRY(hipStreamSynchronize(dst->dv.stream));
+      if (dst->hook.free)
+        dst->hook.free(dst->hook.ctx, dst->d_iws, (void*)dst->home);
+      else
+        HIPTRY(hipFree(dst->d_iws));
+      dst->d_iws = nullptr;
+      dst->iws_bytes = 0;
+    }
+    if (dalloc(dst, &dst->d_iws, need) != hipSuccess)
+      return fail(SOP_ERR_NOMEM, "interpolation workspace");
+    dst->iws_bytes = need;
+  }
+  double2* W[3];
+  double2* w = (double2*)dst->d_iws;
+  for (int a = 0; a < nax; ++a) {
+    W[a] = w;
+    w += (size_t)nd[a] * ns[a];
+  }
+  double2* T1 = w;
+  double2* T2 = w + t1;
+  const DevView& d = dst->dv;
+  {
+    sop::TimedLaunch tl(d, sop::KIND_OTHER, (double)wel * sizeof(double2));
+    for (int a = 0; a < nax; ++a)
+      HIPTRY(sop::interp_weights(d.stream, W[a], (int)ns[a], src->lo[a], src->hi[a],
+                                 (int)nd[a], dst->lo[a], dst->hi[a]));
+  }
+  auto flops = [](const sop::CgemmArgs& g, int batch) {
+    return 8.0 * g.M * (double)g.N * g.K * batch;
+  };
+  // Host check, before every launch, that the product's last elements lie
+  // inside the buffers it reads and writes.
+  auto fits = [](const sop::CgemmArgs& g, int batch, size_t na, size_t nb, size_t nc) {
+    const long long b = batch - 1, m = g.M - 1, n = g.N - 1, k = g.K - 1;
+    return (size_t)(b * g.bsa + m * g.sai + k * g.sak) < na &&
+           (size_t)(b * g.bsb + k * g.sbk + n * g.sbj) < nb &&
+           (size_t)(b * g.bsc + m * g.sci + n * g.scj) < nc;
+  };
+  const size_t nsrc = (size_t)S * ns[0] * ns[1] * ns[2];
+  const size_t ndst = (size_t)S * nd[0] * nd[1] * nd[2];
+  const int zax = nax - 1;  // the contiguous axis
+  {  // along z: rows of the source times W_z^T
+    sop::CgemmArgs g;
+    g.A = (const double2*)psi_src;
+    g.M = (int)(S * (nax == 3 ? ns[0] * ns[1] : 1));  // every line along z
+    g.K = (int)ns[zax];
+    g.N = (int)nd[zax];
+    g.sai = g.K;
+    g.sak = 1;
+    g.B = W[zax];
+    g.sbk = 1;
+    g.sbj = g.K;
+    g.C = nax == 3 ? T1 : (double2*)psi_dst;
+    g.sci = g.N;
+    g.scj = 1;
+    if (!fits(g, 1, nsrc, (size_t)nd[zax] * ns[zax], nax == 3 ? t1 : ndst))
+      return fail(SOP_ERR_INVALID, "interpolation: internal size check failed (z)");
+    sop::TimedLaunch tl(d, sop::KIND_INTERP, flops(g, 1));
+    HIPTRY(sop::cgemm(d.stream, g, 1));
+  }
+  if (nax == 3) {
+    {  // along y: W_y times each (y, z) slab
+      sop::CgemmArgs g;
+      g.A = W[1];
+      g.M = (int)nd[1];
+      g.K = (int)ns[1];
+      g.N = (int)nd[2];
+      g.sai = g.K;
+      g.sak = 1;
+      g.B = T1;
+      g.sbk = nd[2];
+      g.sbj = 1;
+      g.bsb = ns[1] * nd[2];
+      g.C = T2;
+      g.sci = nd[2];
+      g.scj = 1;
+      g.bsc = nd[1] * nd[2];
+      const int batch = (int)(S * ns[0]);
+      if (!fits(g, batch, (size_t)nd[1] * ns[1], t1, t2))
+        return fail(SOP_ERR_INVALID, "interpolation: internal size check failed (y)");
+      sop::TimedLaunch tl(d, sop::KIND_INTERP, flops(g, batch));
+      HIPTRY(sop::cgemm(d.stream, g, batch));
+    }
+    {  // along x: W_x times each surface's (x, yz) matrix
+      sop::CgemmArgs g;
+      g.A = W[0];
+      g.M = (int)nd[0];
+      g.K = (int)ns[0];
+      g.N = (int)(nd[1] * nd[2]);
+      g.sai = g.K;
+      g.sak = 1;
+      g.B = T2;
+      g.sbk = nd[1] * nd[2];
+      g.sbj = 1;
+      g.bsb = ns[0] * nd[1] * nd[2];
+      g.C = (double2*)psi_dst;
+      g.sci = nd[1] * nd[2];
+      g.scj = 1;
+      g.bsc = nd[0] * nd[1] * nd[2];
+      if (!fits(g, S, (size_t)nd[0] * ns[0], t2, ndst))
+        return fail(SOP_ERR_INVALID, "interpolation: internal size check failed (x)");
+      sop::TimedLaunch tl(d, sop::KIND_INTERP, flops(g, S));
+      HIPTRY(sop::cgemm(d.stream, g, S));
+    }
+  }
   return SOP_OK;
 }
 

@@ -83,7 +83,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_scheme_sequence", "sop_custom_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
            "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+           "sop_distance", "sop_interpolate", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
            "sop_plan_set_params",
            "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -91,7 +91,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
            "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
            "sop_batch_describe"]
-KINDS = ["zpass", "ypass", "xpass", "k1d", "other", "plane"]
+KINDS = ["zpass", "ypass", "xpass", "k1d", "other", "plane", "interp"]
 
 _lib = None
 
@@ -127,6 +127,7 @@ def lib():
     L.sop_observables.argtypes = [vp, vp, dp]
     L.sop_overlap.argtypes = [vp, vp, vp, dp]
     L.sop_distance.argtypes = [vp, vp, vp, dp]
+    L.sop_interpolate.argtypes = [vp, vp, vp, vp]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
@@ -151,7 +152,7 @@ def lib():
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
               "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_distance", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+              "sop_distance", "sop_interpolate", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
               "sop_plan_set_params",
               "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
               "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -177,6 +178,15 @@ def _dp(a: np.ndarray):
 
 def _ip(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def interpolate(src: "Plan", psi_src, dst: "Plan", psi_dst) -> None:
+    """psi_dst <- the trigonometric interpolant of psi_src (src's grid)
+    evaluated on dst's grid, zero outside src's box (sop_interpolate)."""
+    for plan, psi in ((src, psi_src), (dst, psi_dst)):
+        plan._check_psi(psi)
+    _check(lib().sop_interpolate(src._h, ctypes.c_void_p(psi_src.data_ptr()), dst._h,
+                                 ctypes.c_void_p(psi_dst.data_ptr())), "sop_interpolate")
 
 
 def scheme_sequence(split: str, comp: str, order: int = 2, gamma=None):
