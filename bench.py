@@ -65,6 +65,11 @@ ADJOINTS = {"adjoint_lvc3d_128cube_x3_tj6_c128": 128, "adjoint_lvc3d_256cube_x3_
 # s(t) = 0.2 + 0.05 sin(2 pi t / 2000 a.u.) eV, the operator formed at every
 # potential action; TJ-6, dt = 10
 DRIVEN = {"driven_lvc3d_128cube_x3_tj6_c128": 128}
+# Grid-convergence interpolation (Appendix B): a 3D state moved by
+# trigonometric interpolation onto a grid with range and density each sqrt(2)
+# larger per axis (n -> 2n).
+INTERPS = {"interp_lvc3d_128to256cube_x3_c128": (128, 256)}
+FP64_PEAK_TFS = 78.6
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
@@ -530,6 +535,82 @@ def run_driven(a, torch, soprop):
     }
 
 
+def run_interp(a, torch, soprop):
+    """sop_interpolate from the n-point grid on [-7, 7)^3 to the 2n-point grid
+    on [-7 sqrt 2, 7 sqrt 2)^3, three surfaces; one call per step."""
+    from paper_1903_04946_amd import synth
+    na, nb = INTERPS[a.workload]
+    r2 = 2.0**0.5
+    ma = synth.lvc_3d(n=na, lo=-7.0, hi=7.0)
+    mb = synth.lvc_3d(n=nb, lo=-7.0 * r2, hi=7.0 * r2)
+    pa = soprop.Plan.from_model(ma, comp="strang", order=2, dt=10.0)
+    pb = soprop.Plan.from_model(mb, comp="strang", order=2, dt=10.0)
+    src = torch.from_numpy(ma.psi0).cuda()
+    pa.propagate(src, 5)  # a propagated state, as in a convergence study
+    dst = torch.empty(pb.shape, dtype=torch.complex128, device="cuda")
+    for _ in range(a.warmup):
+        soprop.interpolate(pa, src, pb, dst)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(a.steps):
+        soprop.interpolate(pa, src, pb, dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    pb.set_timing(True)
+    for _ in range(a.steps):
+        soprop.interpolate(pa, src, pb, dst)
+    kt = pb.timing_read()
+    pb.set_timing(False)
+    kt = {("weights" if k == "other" else k): v for k, v in kt.items()}
+    ev_total = sum(v["ms"] for v in kt.values())
+    scale = ms / ev_total if ev_total > 0 else 1.0
+    gk = kt["interp"]
+    flops_call = gk["bytes"] / a.steps  # FP64 flops of the three products
+    tflops = flops_call / (ms / a.steps / 1e3) / 1e12
+    kernels = {k: {"launches": v["count"], "avg_us": 1e3 * scale * v["ms"] / v["count"],
+                   "event_avg_us": 1e3 * v["ms"] / v["count"], "share": v["ms"] / ev_total}
+               for k, v in kt.items()}
+    kernels["interp"]["TFLOPs"] = gk["bytes"] / (scale * gk["ms"] / 1e3) / 1e12
+    achieved = kernels["interp"]["TFLOPs"]
+    unit = "interpolated grid-pt·surface/s"
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        ns, nd = 48, 96  # same ratio and boxes, at a size the oracle finishes in seconds
+        sa = synth.lvc_3d(n=ns, lo=-7.0, hi=7.0)
+        t1 = time.perf_counter()
+        O.interpolate(sa.psi0, sa.n, sa.lo, sa.hi, [nd] * 3, [-7.0 * r2] * 3, [7.0 * r2] * 3)
+        sec = time.perf_counter() - t1
+        cpu = {"value": sa.nsurf * nd**3 / sec, "unit": unit, "host": _host_cpu(),
+               "cores": int(O.lib().orc_threads()), "kind": "oracle",
+               "sample": f"the oracle's interpolation {ns}^3 -> {nd}^3 (same boxes and ratio; "
+                         f"{sec:.1f} s); its cost per output point grows about linearly with "
+                         f"n, so at {na}^3 -> {nb}^3 its rate would be about {ns / na:.2f} of this"}
+    return {
+        "metric": "trigonometric interpolation onto a sqrt(2)-wider, sqrt(2)-denser grid",
+        "value": mb.nsurf * mb.npts / (ms / a.steps / 1e3), "unit": unit, "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "ndim": 3, "grid_src": [na] * 3, "grid_dst": [nb] * 3,
+                   "box_src": [-7.0, 7.0], "box_dst": [-7.0 * r2, 7.0 * r2], "nsurf": ma.nsurf},
+        "roofline": {"bound": "alu", "kernel": "interp (complex FP64 products, three per call)",
+                     "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+                     "flops_per_call": flops_call, "call_TFLOPs": tflops},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "checks": {"wall_s_timed": wall},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def run_adjoint(a, torch, soprop):
     """Forward sweep (checkpoints every K steps) and backward sweep of the
     adjoint for d P_3(T) / d theta over `--steps` time steps (default 500 for
@@ -753,7 +834,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS)
-                    + sorted(DRIVEN))
+                    + sorted(DRIVEN) + sorted(INTERPS))
     ap.add_argument("--fd-check", action="store_true",
                     help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -788,6 +869,9 @@ def main(argv=None) -> int:
         return 0
     if a.workload in DRIVEN:
         print(json.dumps(run_driven(a, torch, soprop)))
+        return 0
+    if a.workload in INTERPS:
+        print(json.dumps(run_interp(a, torch, soprop)))
         return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64

@@ -364,7 +364,9 @@ sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
  * Runs asynchronously on dst's stream (psi_src must be ready there); the
  * axis matrices and intermediate states live in a workspace that dst keeps
  * and grows on demand (16 bytes per matrix entry and per intermediate
- * element; growing it synchronises dst's stream), released with dst. */
+ * element; growing it synchronises dst's stream), released with dst.  The
+ * matrices are formed on the first call and again only when the source
+ * grid (lengths and box) differs from the previous call's. */
 sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* dst,
                            void* psi_dst);
 

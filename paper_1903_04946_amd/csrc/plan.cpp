@@ -230,6 +230,8 @@ struct sop_plan {
   void* d_scratch = nullptr;
   void* d_iws = nullptr;  // sop_interpolate workspace (grown on demand)
   size_t iws_bytes = 0;
+  double iws_key[9] = {0};  // source grid whose axis matrices the workspace holds
+  bool iws_valid = false;
   void* d_atab = nullptr;  // table for sop_apply_action
   void* d_akin = nullptr;
   double* d_part = nullptr;
@@ -804,10 +806,20 @@ sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* d
       dst->d_iws = nullptr;
       dst->iws_bytes = 0;
     }
+    dst->iws_valid = false;
     if (dalloc(dst, &dst->d_iws, need) != hipSuccess)
       return fail(SOP_ERR_NOMEM, "interpolation workspace");
     dst->iws_bytes = need;
   }
+  // the axis matrices depend only on the two grids: formed again only when
+  // the source grid differs from the last call's
+  double key[9];
+  for (int a = 0; a < 3; ++a) {
+    key[3 * a] = (double)ns[a];
+    key[3 * a + 1] = a < nax ? src->lo[a] : 0.0;
+    key[3 * a + 2] = a < nax ? src->hi[a] : 0.0;
+  }
+  const bool reuse = dst->iws_valid && std::equal(key, key + 9, dst->iws_key);
   double2* W[3];
   double2* w = (double2*)dst->d_iws;
   for (int a = 0; a < nax; ++a) {
@@ -817,11 +829,14 @@ sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* d
   double2* T1 = w;
   double2* T2 = w + t1;
   const DevView& d = dst->dv;
-  {
+  if (!reuse) {
+    dst->iws_valid = false;
     sop::TimedLaunch tl(d, sop::KIND_OTHER, (double)wel * sizeof(double2));
     for (int a = 0; a < nax; ++a)
       HIPTRY(sop::interp_weights(d.stream, W[a], (int)ns[a], src->lo[a], src->hi[a],
                                  (int)nd[a], dst->lo[a], dst->hi[a]));
+    std::copy(key, key + 9, dst->iws_key);
+    dst->iws_valid = true;
   }
   auto flops = [](const sop::CgemmArgs& g, int batch) {
     return 8.0 * g.M * (double)g.N * g.K * batch;

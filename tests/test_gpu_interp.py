@@ -142,3 +142,24 @@ def test_refusals(torch_cuda):
     with pytest.raises(soprop.SopError):  # ndim differs
         soprop.interpolate(p1, torch.zeros(p1.shape, dtype=torch.complex128).cuda(), pb,
                            torch.zeros(pb.shape, dtype=torch.complex128).cuda())
+
+
+def test_matrices_follow_the_source_grid(torch_cuda, orc):
+    """One destination plan fed from two source grids in turn: the kept axis
+    matrices are formed again whenever the source grid changes."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m1 = synth.lvc_3d(n=32, lo=-7.0, hi=7.0)
+    m2 = synth.lvc_3d(n=32, lo=-6.0, hi=6.5)
+    mb = synth.lvc_3d(n=48, lo=-8.0, hi=8.0)
+    p1, p2, pb = plan_for(m1), plan_for(m2), plan_for(mb)
+    psi = synth.random_state(m1.psi0.shape, seed=4)
+    src = torch.from_numpy(psi).cuda()
+    dst = torch.empty(pb.shape, dtype=torch.complex128).cuda()
+    for p, m in ((p1, m1), (p2, m2), (p1, m1), (p1, m1)):
+        soprop.interpolate(p, src, pb, dst)
+        got = dst.cpu().numpy()
+        ref = oracle_interp(orc, psi, m, mb)
+        err = rel_l2(got, ref)
+        print(f"[interp source switch] rel L2 {err:.2e}")
+        assert err < TOL
