@@ -349,6 +349,28 @@ sop_status sop_adjoint(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int
 enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2 };
 sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
+/* Compositions of the trapezoidal rule (the implicit, unitary and
+ * energy-conserving comparison integrator of the paper's figures; for a
+ * linear equation the trapezoidal rule and the implicit midpoint rule are the
+ * same map).  Each of the plan's composition stages g_j solves
+ * (1 + i tau H) psi' = (1 - i tau H) psi, tau = g_j dt / (2 hbar), with
+ * H = T + V of the plan (its current V-table) and T(k) = hbar^2 kappa^2
+ * inv_mass / 2 on the grid's frequencies.  The solve is the conjugate
+ * orthogonal conjugate gradient method for the complex symmetric matrix
+ * 1 + i tau H, started from psi, stopped when the residual's norm falls to
+ * tol times the right-hand side's (the error of psi' is then at most that
+ * residual), at most max_iter iterations per stage.
+ * 1D SOP_C128 plans of 512..8192 points (SOP_ERR_UNSUPPORTED otherwise);
+ * VT/TV plans have no composition (SOP_ERR_INVALID).  psi: device
+ * [count][S][N], count (1..65535) independent states, one workgroup each,
+ * advanced in place by nsteps steps.  *iterations (may be NULL) receives the
+ * total iteration count over all states.  Synchronises the plan's stream;
+ * SOP_ERR_STATE if a stage did not reach tol (psi then holds the last
+ * iterate).  Keeps a workspace of count S N complex values (grown on
+ * demand) in the plan. */
+sop_status sop_propagate_trapezoid(sop_plan* plan, void* psi, int count, int64_t nsteps,
+                                   double tol, int max_iter, int64_t* iterations);
+
 /* Trigonometric interpolation of a state onto another grid (Appendix B:
  * states on grids of different range and density are compared through the
  * trigonometric interpolant of the one on the sparser grid).  psi_dst

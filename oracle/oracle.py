@@ -242,6 +242,52 @@ def interpolate(psi: np.ndarray, n_src, lo_src, hi_src, n_dst, lo_dst, hi_dst) -
     return out
 
 
+def dense_hamiltonian_1d(n, lo, hi, nsurf, inv_mass, vtable, hbar=1.0) -> np.ndarray:
+    """H = T (x) 1_S + V on an n-point 1D grid (Eq. diab_mol_ham with the
+    Fourier grid of Sec. "Dynamic Fourier method"): T = F^-1 diag(T_k) F with
+    F the DFT matrix, T_k = (hbar kappa_k)^2 inv_mass / 2, kappa_k = 2 pi k / L
+    over the signed frequencies; V = the S x S blocks of point-wise diagonals.
+    Rows and columns ordered [surface][point]."""
+    n = int(n)
+    L = float(hi) - float(lo)
+    m = np.arange(n)
+    F = np.exp(-2j * np.pi * np.outer(m, m) / n)
+    ks = np.where(m <= n // 2, m, m - n).astype(float)
+    Tk = (hbar * 2 * np.pi * ks / L) ** 2 * float(np.ravel(inv_mass)[0]) / 2
+    T = (F.conj().T * Tk) @ F / n
+    S = int(nsurf)
+    vt = np.asarray(vtable, dtype=float).reshape(-1, n)
+    H = np.kron(np.eye(S), T)
+    pk = 0
+    for i in range(S):
+        for j in range(i, S):
+            blk = np.diag(vt[pk])
+            H[i * n:(i + 1) * n, j * n:(j + 1) * n] += blk
+            if j != i:
+                H[j * n:(j + 1) * n, i * n:(i + 1) * n] += blk
+            pk += 1
+    return H
+
+
+def propagate_trapezoid(H: np.ndarray, psi: np.ndarray, gammas, dt: float, nsteps: int,
+                        hbar: float = 1.0) -> np.ndarray:
+    """nsteps steps of the composition of the trapezoidal rule with the
+    coefficients gammas: each stage solves (1 + i tau H) x = (1 - i tau H) psi,
+    tau = g dt / (2 hbar), by a dense direct solve (the stage matrix is formed
+    once per distinct tau)."""
+    shape = np.shape(psi)
+    x = np.ascontiguousarray(psi, dtype=np.complex128).ravel().copy()
+    eye = np.eye(H.shape[0])
+    cache = {}
+    for _ in range(int(nsteps)):
+        for g in np.ravel(gammas):
+            tau = float(g) * dt / (2 * hbar)
+            if tau not in cache:
+                cache[tau] = np.linalg.solve(eye + 1j * tau * H, eye - 1j * tau * H)
+            x = cache[tau] @ x
+    return x.reshape(shape)
+
+
 def set_threads(n: int) -> int:
     """Threads of the oracle's OpenMP loops; returns the count now in use."""
     if lib().orc_set_threads(int(n)) != 0:

@@ -185,6 +185,24 @@ constexpr int eig_slots(int S) { return S == 3 ? 4 : 2; }
 // kPhaseMax).
 constexpr bool eig_form(int ndim, int S, bool f64) { return ndim == 3 && f64 && S >= 2; }
 
+// kernels_trap.hip: compositions of the trapezoidal rule on 1D FP64 plans,
+// one workgroup per state (count states of S x N, consecutive).
+struct TrapArgs {
+  void* psi = nullptr;        // [count][S][N] complex, advanced in place
+  void* rbuf = nullptr;       // [count][S][N] complex residual workspace
+  const double* vraw = nullptr;  // [S(S+1)/2][N] V-table
+  const double* taus = nullptr;  // [nst] g_j dt / (2 hbar)
+  int nst = 0;
+  int64_t nsteps = 0;
+  double tk = 0;    // T(k) = tk * k^2 (k the signed frequency index)
+  double tol2 = 0;  // squared relative residual at which a solve stops
+  int maxit = 0;
+  int* stats = nullptr;  // [count][3]
+  int count = 1;
+};
+bool k1d_trap_supported(int n, int S);
+hipError_t k1d_trapezoid(const DevView& d, const TrapArgs& g);
+
 // kernels_interp.hip: trigonometric interpolation between uniform grids.
 // Complex FP64 product C[b] = A[b] B[b] (M x K by K x N) with element and
 // batch strides; A needs sak = 1 or sai = 1, B sbj = 1 or sbk = 1.

@@ -93,6 +93,7 @@ struct Sequence {
   std::vector<double> a, b;    // pruned sequence, a has M+1 entries (1 for VT/TV)
   std::vector<double> au, bu;  // unique values
   std::vector<int> ia, ib;     // indices (ib has M entries)
+  std::vector<double> g;       // composition coefficients (empty for VT/TV)
   bool a_is_v = true;
 };
 
@@ -182,6 +183,7 @@ sop_status build_sequence(sop_split split, sop_comp comp, int order, int ngamma,
   }
   const int M = (int)g.size();
   s.M = M;
+  s.g.assign(g.begin(), g.end());
   // Pruned sequence (Eq. merging_splitting_coeff_b_zero applied to every
   // Strang stage A(g/2) B(g) A(g/2)): a_1 = g_1/2, a_j = (g_{j-1} + g_j)/2,
   // a_{M+1} = g_M/2 and b_j = g_j.
@@ -228,6 +230,8 @@ struct sop_plan {
   int* d_prog1 = nullptr;  // single-action programs {V(0), T(0)}
   double* d_taus = nullptr;
   void* d_scratch = nullptr;
+  void* d_trap = nullptr;  // trapezoidal rule: residual, stats, stage taus
+  size_t trap_bytes = 0;
   void* d_iws = nullptr;  // sop_interpolate workspace (grown on demand)
   size_t iws_bytes = 0;
   double iws_key[9] = {0};  // source grid whose axis matrices the workspace holds
@@ -284,7 +288,7 @@ void free_plan(sop_plan* p) {
   if (!p) return;
   void* bufs[] = {p->d_vraw, p->d_vexp, p->d_kin, p->d_tw, p->d_prog, p->d_prog1, p->d_taus,
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
-                  p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive, p->d_iws};
+                  p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive, p->d_iws, p->d_trap};
   delete p->graphs;
   for (void* b : bufs) {
     if (!b) continue;
@@ -772,6 +776,75 @@ sop_status sop_distance(sop_plan* p, const void* psi, const void* phi, double* o
   HIPTRY(hipStreamSynchronize(p->dv.stream));
   out[0] = std::sqrt(raw[0] * p->dV);
   out[1] = raw[1] > 0.0 ? std::sqrt(raw[0] / raw[1]) : 0.0;
+  return SOP_OK;
+}
+
+sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t nsteps, double tol,
+                                   int max_iter, int64_t* iterations) {
+  if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
+  if (count < 1 || count > 65535) return fail(SOP_ERR_INVALID, "count must be 1..65535");
+  if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
+  if (!(tol > 0) || !(tol < 1)) return fail(SOP_ERR_INVALID, "tol must be in (0, 1)");
+  if (max_iter < 1) return fail(SOP_ERR_INVALID, "max_iter must be >= 1");
+  if (p->ndim != 1 || p->dtype != SOP_C128 || !sop::k1d_trap_supported(p->n[0], p->S))
+    return fail(SOP_ERR_UNSUPPORTED,
+                "the trapezoidal rule runs on 1D SOP_C128 plans of 512..8192 points");
+  if (p->seq.g.empty())
+    return fail(SOP_ERR_INVALID, "the plan's splitting has no composition (VT/TV)");
+  const int nst = (int)p->seq.g.size();
+  const size_t vec = (size_t)count * p->S * p->n[0] * sizeof(double2);
+  const size_t sbytes = ((size_t)count * 3 * sizeof(int) + 255) / 256 * 256;
+  const size_t need = vec + sbytes + (size_t)nst * sizeof(double);
+  if (need > p->trap_bytes) {
+    if (p->d_trap) {
+      HIPTRY(hipStreamSynchronize(p->dv.stream));
+      if (p->hook.free)
+        p->hook.free(p->hook.ctx, p->d_trap, (void*)p->home);
+      else
+        HIPTRY(hipFree(p->d_trap));
+      p->d_trap = nullptr;
+      p->trap_bytes = 0;
+    }
+    if (dalloc(p, &p->d_trap, need) != hipSuccess) return fail(SOP_ERR_NOMEM, "trapezoid workspace");
+    p->trap_bytes = need;
+  }
+  char* base = (char*)p->d_trap;
+  std::vector<double> taus(nst);
+  for (int j = 0; j < nst; ++j) taus[j] = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
+  const DevView& d = p->dv;
+  HIPTRY(hipMemcpyAsync(base + vec + sbytes, taus.data(), nst * sizeof(double),
+                        hipMemcpyHostToDevice, d.stream));
+  sop::TrapArgs g;
+  g.psi = psi;
+  g.rbuf = base;
+  g.vraw = p->d_vraw;
+  g.taus = (const double*)(base + vec + sbytes);
+  g.nst = nst;
+  g.nsteps = nsteps;
+  const ld L = (ld)p->hi[0] - (ld)p->lo[0];
+  const ld kap = kTwoPi / L;
+  g.tk = (double)((ld)p->hbar * p->hbar * p->inv_mass[0] * kap * kap / 2);
+  g.tol2 = tol * tol;
+  g.maxit = max_iter;
+  g.stats = (int*)(base + vec);
+  g.count = count;
+  {
+    sop::TimedLaunch tl(d, sop::KIND_1D, 0.0);
+    HIPTRY(sop::k1d_trapezoid(d, g));
+  }
+  std::vector<int> st((size_t)count * 3);
+  HIPTRY(hipMemcpyAsync(st.data(), g.stats, st.size() * sizeof(int), hipMemcpyDeviceToHost,
+                        d.stream));
+  HIPTRY(hipStreamSynchronize(d.stream));
+  int64_t total = 0, failed = 0;
+  for (int c = 0; c < count; ++c) {
+    total += st[3 * c];
+    failed += st[3 * c + 1];
+  }
+  if (iterations) *iterations = total;
+  if (failed > 0)
+    return fail(SOP_ERR_STATE, std::to_string(failed) + " of the linear solves did not reach tol in " +
+                                   std::to_string(max_iter) + " iterations");
   return SOP_OK;
 }
 

@@ -83,7 +83,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_scheme_sequence", "sop_custom_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
            "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_distance", "sop_interpolate", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+           "sop_distance", "sop_interpolate", "sop_propagate_trapezoid", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
            "sop_plan_set_params",
            "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -128,6 +128,8 @@ def lib():
     L.sop_overlap.argtypes = [vp, vp, vp, dp]
     L.sop_distance.argtypes = [vp, vp, vp, dp]
     L.sop_interpolate.argtypes = [vp, vp, vp, vp]
+    L.sop_propagate_trapezoid.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
@@ -152,7 +154,7 @@ def lib():
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
               "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_distance", "sop_interpolate", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+              "sop_distance", "sop_interpolate", "sop_propagate_trapezoid", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
               "sop_plan_set_params",
               "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
               "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -420,6 +422,27 @@ class Plan:
             raise TypeError(f"psi dtype {psi.dtype} != plan dtype {self.dtype}")
         if tuple(psi.shape) != self.shape or not psi.is_contiguous():
             raise ValueError(f"psi must be a contiguous tensor of shape {self.shape}")
+
+    def propagate_trapezoid(self, psi, nsteps: int, tol: float = 1e-13,
+                            max_iter: int = 10000) -> int:
+        """psi ([S, N], or [count, S, N] independent states) advanced in place
+        by nsteps steps of the plan's composition of the trapezoidal rule
+        (sop_propagate_trapezoid); returns the number of linear-solver
+        iterations."""
+        import torch
+        if psi.dim() == len(self.shape) + 1:
+            count = psi.shape[0]
+            if (not isinstance(psi, torch.Tensor) or not psi.is_cuda or psi.dtype != self.dtype
+                    or tuple(psi.shape[1:]) != self.shape or not psi.is_contiguous()):
+                raise ValueError(f"psi must be a contiguous CUDA tensor [count, {self.shape}]")
+        else:
+            self._check_psi(psi)
+            count = 1
+        it = ctypes.c_int64()
+        _check(lib().sop_propagate_trapezoid(self._h, ctypes.c_void_p(psi.data_ptr()), int(count),
+                                             int(nsteps), float(tol), int(max_iter),
+                                             ctypes.byref(it)), "sop_propagate_trapezoid")
+        return int(it.value)
 
     def set_stream(self, stream=None):
         self._stream = stream

@@ -1,0 +1,126 @@
+"""GPU parity of the trapezoidal-rule compositions (sop_propagate_trapezoid)
+against the oracle's dense direct solves, and at the largest 1D size against
+the invariants the rule keeps exactly (norm and energy).
+
+Tolerance: 1e-12 relative L2 with the solver's tolerance at 1e-14 (the error
+of each stage is at most its final residual, since |1 + i tau lambda| >= 1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1903_04946_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_04946_amd import soprop
+    soprop.lib()
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("n,S,comp,order,split", [(512, 1, "strang", 2, "VTV"),
+                                                  (512, 2, "triple_jump", 4, "TVT"),
+                                                  (1024, 2, "suzuki", 4, "VTV")])
+def test_against_dense_oracle(torch_cuda, orc, n, S, comp, order, split):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([n], S, seed=5, lo=-8, hi=8, coupling=0.4)
+    dt, nsteps = 0.05, 4
+    plan = soprop.Plan.from_model(m, split=split, comp=comp, order=order, dt=dt)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    iters = plan.propagate_trapezoid(psi, nsteps, tol=1e-14)
+    got = psi.cpu().numpy()
+    H = orc.dense_hamiltonian_1d(n, m.lo[0], m.hi[0], S, m.inv_mass, m.vtable, m.hbar)
+    g = orc.gammas({"strang": 0, "triple_jump": 1, "suzuki": 2}[comp], order)
+    ref = orc.propagate_trapezoid(H, m.psi0, g, dt, nsteps, m.hbar)
+    err = rel_l2(got, ref)
+    print(f"[trapezoid n={n} S={S} {comp}{order}] rel L2 {err:.2e}, {iters} iterations")
+    assert err < 1e-12
+    assert iters >= nsteps * len(g)
+
+
+def test_custom_composition_against_dense_oracle(torch_cuda, orc):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([512], 2, seed=6, lo=-8, hi=8, coupling=0.4)
+    g = synth.yoshida6_gammas()
+    plan = soprop.Plan.from_model(m, comp="custom", order=6, gamma=g, dt=0.1)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate_trapezoid(psi, 3, tol=1e-14)
+    H = orc.dense_hamiltonian_1d(512, m.lo[0], m.hi[0], 2, m.inv_mass, m.vtable, m.hbar)
+    ref = orc.propagate_trapezoid(H, m.psi0, g, 0.1, 3, m.hbar)
+    err = rel_l2(psi.cpu().numpy(), ref)
+    print(f"[trapezoid yoshida6] rel L2 {err:.2e}")
+    assert err < 1e-12
+
+
+def test_largest_grid_keeps_norm_and_energy(torch_cuda):
+    """8192 points, two surfaces: the rule is unitary and conserves <H>."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([8192], 2, seed=7, lo=-40, hi=40, coupling=0.4)
+    plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=0.05)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    ob0 = plan.observables(psi)
+    iters = plan.propagate_trapezoid(psi, 3, tol=1e-14)
+    ob1 = plan.observables(psi)
+    e0 = ob0["energy"]
+    print(f"[trapezoid 8192] norm {ob1['norm']:.15f}, energy {e0:.12f} -> {ob1['energy']:.12f}, "
+          f"{iters} iterations")
+    assert abs(ob1["norm"] - ob0["norm"]) < 1e-12
+    assert abs(ob1["energy"] - e0) < 1e-10 * abs(e0)
+
+
+def test_refusals_and_non_convergence(torch_cuda):
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([512], 2, seed=5, lo=-8, hi=8)
+    plan = soprop.Plan.from_model(m, comp="strang", order=2, dt=0.5)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    with pytest.raises(soprop.SopError, match="did not reach"):  # one iteration is not enough
+        plan.propagate_trapezoid(psi, 1, tol=1e-14, max_iter=1)
+    for kw in ({"tol": 0.0}, {"tol": 1.5}, {"max_iter": 0}):
+        with pytest.raises(soprop.SopError):
+            plan.propagate_trapezoid(psi, 1, **kw)
+    small = synth.random_small([256], 2, seed=5)
+    p2 = soprop.Plan.from_model(small, comp="strang", order=2, dt=0.1)
+    with pytest.raises(soprop.SopError):  # below the supported lengths
+        p2.propagate_trapezoid(torch.from_numpy(small.psi0.copy()).cuda(), 1)
+    p3 = soprop.Plan.from_model(m, comp="strang", order=2, dt=0.1, dtype=torch.complex64)
+    with pytest.raises(soprop.SopError):  # FP64 only
+        p3.propagate_trapezoid(torch.from_numpy(m.psi0.astype(np.complex64)).cuda(), 1)
+
+
+def test_many_states_match_one_at_a_time(torch_cuda):
+    """count states in one launch (one workgroup each) give bitwise the
+    results of one state per call."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.random_small([1024], 2, seed=8, lo=-8, hi=8, coupling=0.4)
+    plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=0.05)
+    x = m.axes()[0]
+    states = np.stack([m.psi0 * np.exp(1j * 0.7 * i * x) for i in range(5)])
+    many = torch.from_numpy(states.copy()).cuda()
+    plan.propagate_trapezoid(many, 2, tol=1e-13)
+    for i in range(5):
+        one = torch.from_numpy(states[i].copy()).cuda()
+        plan.propagate_trapezoid(one, 2, tol=1e-13)
+        assert torch.equal(one, many[i])
