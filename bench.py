@@ -70,6 +70,9 @@ DRIVEN = {"driven_lvc3d_128cube_x3_tj6_c128": 128}
 # larger per axis (n -> 2n).
 INTERPS = {"interp_lvc3d_128to256cube_x3_c128": (128, 256)}
 FP64_PEAK_TFS = 78.6
+# Compositions of the trapezoidal rule (the implicit comparison integrator):
+# count independent 1D two-surface states, one workgroup each.
+TRAPS = {"trapezoid_random1d_1024_x2_tj4_c128": (1024, 256)}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
@@ -611,6 +614,67 @@ def run_interp(a, torch, soprop):
     }
 
 
+def run_trapezoid(a, torch, soprop):
+    """sop_propagate_trapezoid on count smooth states of a random two-surface
+    1D model (TJ-4 composition, dt = 0.05, solver tolerance 1e-13)."""
+    from paper_1903_04946_amd import synth
+    n, count = TRAPS[a.workload]
+    m = synth.random_small([n], 2, seed=5, lo=-8.0, hi=8.0, coupling=0.4)
+    dt, tol = 0.05, 1e-13
+    plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=dt)
+    M = plan.info.M
+    x = m.axes()[0]
+    states = np.stack([m.psi0 * np.exp(1j * (0.05 * (i % 32)) * x) for i in range(count)])
+    psi = torch.from_numpy(states).cuda()
+    plan.propagate_trapezoid(psi, a.warmup, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = plan.propagate_trapezoid(psi, a.steps, tol=tol)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    log2n = int(np.log2(n))
+    # FP64 flops of one iteration for one state: two S-pencil FFTs (5 N log2 N
+    # each per pencil), T(k) scaling, the S x S matvec and the vector updates
+    flops_iter = 2 * (2 * 5 * n * log2n + 2 * n + 2 * 4 * 2 * n + 40 * n)
+    achieved = flops_iter * iters / sec / 1e12
+    units = m.nsurf * n * M * a.steps * count
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        H = O.dense_hamiltonian_1d(n, m.lo[0], m.hi[0], 2, m.inv_mass, m.vtable, m.hbar)
+        g = O.gammas(1, 4)
+        t1 = time.perf_counter()
+        O.propagate_trapezoid(H, states[0], g, dt, 1, m.hbar)  # forms the stage matrices
+        setup = time.perf_counter() - t1
+        k = 200
+        t1 = time.perf_counter()
+        for i in range(4):
+            O.propagate_trapezoid(H, states[i], g, dt, k, m.hbar)
+        csec = time.perf_counter() - t1 - 4 * setup
+        cpu = {"value": m.nsurf * n * M * k * 4 / max(csec, 1e-9), "unit": UNIT,
+               "host": _host_cpu(), "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"4 states x {k} steps of the oracle's dense direct solves "
+                         f"(stage matrices formed per call, {setup:.2f} s each, excluded; "
+                         f"numpy's threads)"}
+    return {
+        "metric": METRIC, "value": units / sec, "unit": UNIT, "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * sec / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "ndim": 1, "grid": [n], "nsurf": 2, "states": count,
+                   "integrator": "trapezoidal rule", "composition": "triple_jump", "order": 4,
+                   "substeps_per_step": M, "dt": dt, "solver_tol": tol},
+        "roofline": {"bound": "alu", "kernel": "k1d_trap_kernel", "achieved": achieved,
+                     "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
+                     "traffic": None, "flops_per_iteration_state": flops_iter},
+        "solver": {"iterations": iters, "iterations_per_stage": iters / (count * M * a.steps),
+                   "H_applications_per_s": (iters + count * M * a.steps) / sec},
+        "cpu_baseline": cpu,
+        "checks": {"norm_after": plan.observables(psi[0])["norm"], "wall_s_timed": sec},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def run_adjoint(a, torch, soprop):
     """Forward sweep (checkpoints every K steps) and backward sweep of the
     adjoint for d P_3(T) / d theta over `--steps` time steps (default 500 for
@@ -834,7 +898,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS)
-                    + sorted(DRIVEN) + sorted(INTERPS))
+                    + sorted(DRIVEN) + sorted(INTERPS) + sorted(TRAPS))
     ap.add_argument("--fd-check", action="store_true",
                     help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -872,6 +936,9 @@ def main(argv=None) -> int:
         return 0
     if a.workload in INTERPS:
         print(json.dumps(run_interp(a, torch, soprop)))
+        return 0
+    if a.workload in TRAPS:
+        print(json.dumps(run_trapezoid(a, torch, soprop)))
         return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64
