@@ -72,7 +72,7 @@ INTERPS = {"interp_lvc3d_128to256cube_x3_c128": (128, 256)}
 FP64_PEAK_TFS = 78.6
 # Compositions of the trapezoidal rule (the implicit comparison integrator):
 # count independent 1D two-surface states, one workgroup each.
-TRAPS = {"trapezoid_random1d_1024_x2_tj4_c128": (1024, 256)}
+TRAPS = {"trapezoid_random1d_1024_x2_tj4_c128": (1024, 512)}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
