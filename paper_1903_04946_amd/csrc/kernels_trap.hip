@@ -24,6 +24,15 @@ namespace {
 
 using namespace s1d;
 
+// Schedules of four values per thread (twice the threads of the propagation
+// schedules, half the registers): the solver keeps two vectors in registers,
+// and at eight values per thread it needs all 256 VGPRs, one wave per SIMD.
+using T512 = Sched<512, 4, RList<4, 4, 4, 4, 2>, RList<2, 4, 4, 4, 4>, 4, 2>;
+using T1024 = Sched<1024, 4, RList<4, 4, 4, 4, 4>, RList<4, 4, 4, 4, 4>, 4, 4>;
+using T2048 = Sched<2048, 4, RList<4, 4, 4, 4, 4, 2>, RList<2, 4, 4, 4, 4, 4>, 4, 2>;
+using T4096 = Sched<4096, 4, RList<4, 4, 4, 4, 4, 4>, RList<4, 4, 4, 4, 4, 4>, 4, 4>;
+using T8192 = S8192;  // 1024 threads already
+
 typedef cx<double> cd_t;
 
 __device__ __forceinline__ cd_t cdiv(cd_t a, cd_t b) {
@@ -102,7 +111,7 @@ __device__ __forceinline__ void apply_h(cd_t (&p)[S][SC::E], cd_t (&v)[S][SC::E]
 
 // stats[3 * block] = {iterations, stages not converged, most iterations of a stage}.
 template <class SC, int S, int PL>
-__global__ void __launch_bounds__(SC::TPC)
+__global__ void __launch_bounds__(SC::TPC) __attribute__((amdgpu_waves_per_eu(2)))
     k1d_trap_kernel(cd_t* __restrict__ psi, cd_t* __restrict__ rbuf,
                     const double* __restrict__ vraw, const cd_t* __restrict__ tw,
                     const double* __restrict__ taus, int nst, int64_t nsteps, double tk,
@@ -123,7 +132,7 @@ __global__ void __launch_bounds__(SC::TPC)
       for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int q = 0; q < E; ++q) p[s][q] = psi[s * N + own_idx<N, E, SC::RF>(t, q)];
-      apply_h<SC, S, PL>(p, v, lds, tw, vraw, tk, t);
+      apply_h<SC, S, PL>(p, v, lds, tw, vraw, tk, opaque(t));
       // b = psi - i tau H psi; with x0 = psi the residual is r0 = -2 i tau H psi
       double s4[4] = {0.0, 0.0, 0.0, 0.0};  // |b|^2, |r|^2, r^T r
 #pragma unroll
@@ -146,7 +155,7 @@ __global__ void __launch_bounds__(SC::TPC)
       int it = 0;
       bool ok = rr <= tol2 * bb;
       while (!ok && it < maxit) {
-        apply_h<SC, S, PL>(p, v, lds, tw, vraw, tk, t);
+        apply_h<SC, S, PL>(p, v, lds, tw, vraw, tk, opaque(t));
         double m2[2] = {0.0, 0.0};  // p^T A p
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -228,7 +237,7 @@ hipError_t k1d_trapezoid(const DevView& d, const TrapArgs& g) {
   if (!d.f64 || g.count < 1 || !k1d_trap_supported(d.n[0], d.S)) return hipErrorInvalidValue;
 #define SOP_TRAP_CASE(NN)                                      \
   case NN:                                                     \
-    return d.S == 1 ? launch_trap<S##NN, 1>(d, g) : launch_trap<S##NN, 2>(d, g);
+    return d.S == 1 ? launch_trap<T##NN, 1>(d, g) : launch_trap<T##NN, 2>(d, g);
   switch (d.n[0]) {
     SOP_TRAP_CASE(512)
     SOP_TRAP_CASE(1024)
