@@ -614,6 +614,51 @@ def run_interp(a, torch, soprop):
     }
 
 
+def _trapezoid_vs_split(torch, soprop, m, states, tf=1.0, eps=1e-7):
+    """Error at t_f against a converged split-operator reference (Suzuki-8,
+    dt = 2^-12) for the TJ-4 compositions of the trapezoidal rule and of the
+    split-operator step, over halving dt; the GPU time per state to reach eps
+    is interpolated in log-log between the bracketing runs."""
+    count = states.shape[0]
+    ref_plan = soprop.Plan.from_model(m, comp="suzuki", order=8, dt=2.0**-12)
+    ref = torch.from_numpy(states.copy()).cuda()
+    ref_plan.propagate_many(ref, int(round(tf / 2.0**-12)))
+    torch.cuda.synchronize()
+    out = {}
+    for name in ("trapezoid", "split"):
+        pts = []
+        for k in range(2, 11):
+            dt = 2.0**-k
+            ns = int(round(tf / dt))
+            plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=dt)
+            psi = torch.from_numpy(states.copy()).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "trapezoid":
+                plan.propagate_trapezoid(psi, ns, tol=1e-13, max_iter=100000)
+            else:
+                plan.propagate_many(psi, ns)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / count
+            err = float(max(torch.linalg.vector_norm(psi[i] - ref[i]) /
+                            torch.linalg.vector_norm(ref[i]) for i in range(count)))
+            pts.append({"dt": dt, "error": err, "s_per_state": wall})
+            if err < eps / 10:
+                break
+        t_eps = None
+        for p0, p1 in zip(pts, pts[1:]):
+            if p0["error"] >= eps > p1["error"]:
+                f = np.log(eps / p0["error"]) / np.log(p1["error"] / p0["error"])
+                t_eps = float(np.exp(np.log(p0["s_per_state"]) +
+                                     f * np.log(p1["s_per_state"] / p0["s_per_state"])))
+        out[name] = {"points": pts, "s_per_state_to_eps": t_eps}
+    tt, ts = out["trapezoid"]["s_per_state_to_eps"], out["split"]["s_per_state_to_eps"]
+    out["eps"] = eps
+    out["t_f"] = tf
+    out["trapezoid_over_split"] = tt / ts if tt and ts else None
+    return out
+
+
 def run_trapezoid(a, torch, soprop):
     """sop_propagate_trapezoid on count smooth states of a random two-surface
     1D model (TJ-4 composition, dt = 0.05, solver tolerance 1e-13)."""
@@ -656,6 +701,7 @@ def run_trapezoid(a, torch, soprop):
                "sample": f"4 states x {k} steps of the oracle's dense direct solves "
                          f"(stage matrices formed per call, {setup:.2f} s each, excluded; "
                          f"numpy's threads)"}
+    tte = _trapezoid_vs_split(torch, soprop, m, states[:64]) if a.time_to_error else None
     return {
         "metric": METRIC, "value": units / sec, "unit": UNIT, "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * sec / a.steps,
@@ -667,6 +713,7 @@ def run_trapezoid(a, torch, soprop):
         "roofline": {"bound": "alu", "kernel": "k1d_trap_kernel", "achieved": achieved,
                      "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
                      "traffic": None, "flops_per_iteration_state": flops_iter},
+        "time_to_error": tte,
         "solver": {"iterations": iters, "iterations_per_stage": iters / (count * M * a.steps),
                    "H_applications_per_s": (iters + count * M * a.steps) / sec},
         "cpu_baseline": cpu,
