@@ -35,10 +35,10 @@
  *
  * Streams and synchronisation
  *   All device work is enqueued on the HIP stream given at plan creation
- *   (NULL = the default stream).  sop_propagate is asynchronous.
- *   sop_plan_create, sop_plan_update_v, sop_plan_set_params,
- *   sop_observables, sop_overlap and sop_distance synchronise the stream
- *   before returning.
+ *   (NULL = the default stream).  sop_propagate and sop_interpolate are
+ *   asynchronous.  sop_plan_create, sop_plan_update_v, sop_plan_set_params,
+ *   sop_observables, sop_overlap, sop_distance, sop_propagate_driven and
+ *   sop_propagate_trapezoid synchronise the stream before returning.
  *
  * Errors
  *   Every call returns a sop_status.  Arguments are validated before any
