@@ -133,7 +133,12 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
     comp_id = {"strang": O.STRANG, "triple_jump": O.TRIPLE_JUMP, "suzuki": O.SUZUKI}[comp]
     P = O.Problem(model.n, model.lo, model.hi, model.nsurf, model.inv_mass, model.vtable,
                   model.hbar)
-    _, sec1, threads = O.propagate_timed(P, model.psi0, O.VTV, comp_id, order, dt, 1)
+    psi1, sec1, threads = O.propagate_timed(P, model.psi0, O.VTV, comp_id, order, dt, 1)
+    # the timed loop must be the oracle's propagation: one step of it equals
+    # orc_propagate bitwise
+    ref1 = O.propagate(P, model.psi0, O.VTV, comp_id, order, dt, 1)
+    if not np.array_equal(psi1.view(np.float64), ref1.view(np.float64)):
+        raise RuntimeError("cpu_baseline: the timed oracle loop differs from orc_propagate")
     steps = 1
     if sec1 < budget_s / 2:
         steps = max(1, int(budget_s / max(sec1, 1e-3)))

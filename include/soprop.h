@@ -37,8 +37,10 @@
  *   All device work is enqueued on the HIP stream given at plan creation
  *   (NULL = the default stream).  sop_propagate and sop_interpolate are
  *   asynchronous.  sop_plan_create, sop_plan_update_v, sop_plan_set_params,
- *   sop_observables, sop_overlap, sop_distance, sop_propagate_driven and
- *   sop_propagate_trapezoid synchronise the stream before returning.
+ *   sop_observables, sop_overlap, sop_distance, sop_apply_action,
+ *   sop_propagate_driven, sop_propagate_trapezoid, the adjoint calls,
+ *   sop_timing_read, sop_batch_create and sop_plan_destroy synchronise the
+ *   stream before returning.
  *
  * Errors
  *   Every call returns a sop_status.  Arguments are validated before any
@@ -250,9 +252,11 @@ sop_status sop_overlap(sop_plan* plan, const void* psi_dev, const void* phi_dev,
  * closely).  Fixed-order reduction; synchronises. */
 sop_status sop_distance(sop_plan* plan, const void* psi_dev, const void* phi_dev, double* out);
 
-/* Applies one action to psi (testing aid; asynchronous): op = 0 potential
+/* Applies one action to psi (testing aid): op = 0 potential
  * exp(-i tau V/hbar) with tau = coef * dt, op = 1 kinetic exp(-i tau T/hbar).
- * The table for coef is formed on the fly into the plan's scratch. */
+ * The table for coef is formed on the fly into the plan's scratch (allocated
+ * on first use).  Synchronises the stream before returning (its host staging
+ * buffers must outlive the copies). */
 sop_status sop_apply_action(sop_plan* plan, void* psi_dev, int op, double coef);
 
 /* Times of the potential actions of one step, in units of dt from the

@@ -270,11 +270,13 @@ def dense_hamiltonian_1d(n, lo, hi, nsurf, inv_mass, vtable, hbar=1.0) -> np.nda
 
 
 def propagate_trapezoid(H: np.ndarray, psi: np.ndarray, gammas, dt: float, nsteps: int,
-                        hbar: float = 1.0) -> np.ndarray:
+                        hbar: float = 1.0, per_stage: bool = False) -> np.ndarray:
     """nsteps steps of the composition of the trapezoidal rule with the
     coefficients gammas: each stage solves (1 + i tau H) x = (1 - i tau H) psi,
-    tau = g dt / (2 hbar), by a dense direct solve (the stage matrix is formed
-    once per distinct tau)."""
+    tau = g dt / (2 hbar), by a dense direct solve.  By default the stage
+    matrix (1 + i tau H)^-1 (1 - i tau H) is formed once per distinct tau;
+    per_stage=True solves for the one right-hand side at every stage instead
+    (the cheaper choice on large grids with few stages)."""
     shape = np.shape(psi)
     x = np.ascontiguousarray(psi, dtype=np.complex128).ravel().copy()
     eye = np.eye(H.shape[0])
@@ -282,6 +284,9 @@ def propagate_trapezoid(H: np.ndarray, psi: np.ndarray, gammas, dt: float, nstep
     for _ in range(int(nsteps)):
         for g in np.ravel(gammas):
             tau = float(g) * dt / (2 * hbar)
+            if per_stage:
+                x = np.linalg.solve(eye + 1j * tau * H, x - 1j * tau * (H @ x))
+                continue
             if tau not in cache:
                 cache[tau] = np.linalg.solve(eye + 1j * tau * H, eye - 1j * tau * H)
             x = cache[tau] @ x

@@ -571,22 +571,12 @@ int orc_eigh(int n, const double* A_in, double* lam_out, double* R_out) {
 }
 
 // ---------------------------------------------------------------- propagation
-// Propagates psi in place by nsteps time steps of size dt (negative dt runs
-// backwards in time).  pruned = 0 applies every Strang stage separately
-// (A(g/2) B(g) A(g/2)); pruned = 1 applies the merged sequence.  Within a
-// step the actions run A(a_1), B(b_1), A(a_2), ...; a zero b is skipped.
-// No merging across steps.  Returns 0 or -1.
-int orc_propagate(const orc_problem* prob, int split, int scheme, int order, double dt,
-                  int64_t nsteps, int pruned, double* psi_io) {
-  Grid g;
-  if (!make_grid(prob, g) || !prob->vtable || nsteps < 0) return -1;
-  std::vector<ld> la, lb;
-  if (!splitting_ld(split, scheme, order, pruned != 0, la, lb)) return -1;
-  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
-  PotentialEigen pe;
-  potential_eigen(g, prob->vtable, pe);
-  cd* psi = reinterpret_cast<cd*>(psi_io);
-  const bool aV = a_is_potential(split);
+// The step loop shared by orc_propagate and orc_propagate_timed: nsteps time
+// steps of the sequence (a, b) with the actions run A(a_1), B(b_1), A(a_2),
+// ... left to right in time (Sec. "Compositions of split-operator
+// algorithms"); a zero b is skipped.  No merging across steps.
+static void step_loop(const Grid& g, const PotentialEigen& pe, bool aV, const std::vector<double>& a,
+                      const std::vector<double>& b, double dt, int64_t nsteps, cd* psi) {
   for (int64_t step = 0; step < nsteps; ++step) {
     for (size_t j = 0; j < a.size(); ++j) {
       if (aV)
@@ -601,7 +591,34 @@ int orc_propagate(const orc_problem* prob, int split, int scheme, int order, dou
       }
     }
   }
+}
+
+// Propagates psi in place by nsteps time steps of size dt (negative dt runs
+// backwards in time).  pruned = 0 applies every Strang stage separately
+// (A(g/2) B(g) A(g/2)); pruned = 1 applies the merged sequence.  Returns 0 or
+// -1.  When seconds is not null it receives the wall time of the step loop
+// alone (std::chrono::steady_clock; the per-point eigen-decomposition done
+// before the loop is excluded), for timing the oracle as a CPU baseline.
+static int propagate_impl(const orc_problem* prob, int split, int scheme, int order, double dt,
+                          int64_t nsteps, int pruned, double* psi_io, double* seconds) {
+  Grid g;
+  if (!make_grid(prob, g) || !prob->vtable || nsteps < 0) return -1;
+  std::vector<ld> la, lb;
+  if (!splitting_ld(split, scheme, order, pruned != 0, la, lb)) return -1;
+  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
+  PotentialEigen pe;
+  potential_eigen(g, prob->vtable, pe);
+  cd* psi = reinterpret_cast<cd*>(psi_io);
+  const auto t0 = std::chrono::steady_clock::now();
+  step_loop(g, pe, a_is_potential(split), a, b, dt, nsteps, psi);
+  if (seconds)
+    *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return 0;
+}
+
+int orc_propagate(const orc_problem* prob, int split, int scheme, int order, double dt,
+                  int64_t nsteps, int pruned, double* psi_io) {
+  return propagate_impl(prob, split, scheme, order, dt, nsteps, pruned, psi_io, nullptr);
 }
 
 // Propagation by a composition with given coefficients gamma_1..gamma_M
@@ -765,38 +782,13 @@ int orc_interpolate(int ndim, int S, const int* n_src, const double* lo_src, con
   return 0;
 }
 
-// Same as orc_propagate, and writes to *seconds the wall time of the step
-// loop alone (std::chrono::steady_clock; the per-point eigen-decomposition
-// done before the loop is excluded).  Used to time the oracle as a CPU
-// baseline.
+// orc_propagate with pruned = 1, and writes to *seconds the wall time of the
+// step loop alone (the same loop, see propagate_impl).  Used to time the
+// oracle as a CPU baseline.
 int orc_propagate_timed(const orc_problem* prob, int split, int scheme, int order, double dt,
                         int64_t nsteps, double* psi_io, double* seconds) {
-  Grid g;
-  if (!make_grid(prob, g) || !prob->vtable || nsteps < 0 || !seconds) return -1;
-  std::vector<ld> la, lb;
-  if (!splitting_ld(split, scheme, order, true, la, lb)) return -1;
-  std::vector<double> a(la.begin(), la.end()), b(lb.begin(), lb.end());
-  PotentialEigen pe;
-  potential_eigen(g, prob->vtable, pe);
-  cd* psi = reinterpret_cast<cd*>(psi_io);
-  const bool aV = a_is_potential(split);
-  auto t0 = std::chrono::steady_clock::now();
-  for (int64_t step = 0; step < nsteps; ++step) {
-    for (size_t j = 0; j < a.size(); ++j) {
-      if (aV)
-        potential_action(g, pe, a[j] * dt, psi);
-      else
-        kinetic_action(g, a[j] * dt, psi);
-      if (b[j] != 0.0) {
-        if (aV)
-          kinetic_action(g, b[j] * dt, psi);
-        else
-          potential_action(g, pe, b[j] * dt, psi);
-      }
-    }
-  }
-  *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return 0;
+  if (!seconds) return -1;
+  return propagate_impl(prob, split, scheme, order, dt, nsteps, 1, psi_io, seconds);
 }
 
 // Sets the number of threads of the OpenMP loops (n >= 1; no effect without

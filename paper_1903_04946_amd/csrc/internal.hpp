@@ -197,7 +197,7 @@ struct TrapArgs {
   double tk = 0;    // T(k) = tk * k^2 (k the signed frequency index)
   double tol2 = 0;  // squared relative residual at which a solve stops
   int maxit = 0;
-  int* stats = nullptr;  // [count][3]
+  long long* stats = nullptr;  // [count][3]: iterations, failed stages, most iterations
   int count = 1;
 };
 bool k1d_trap_supported(int n, int S);

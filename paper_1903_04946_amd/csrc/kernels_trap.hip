@@ -32,6 +32,10 @@ using T1024 = Sched<1024, 4, RList<4, 4, 4, 4, 4>, RList<4, 4, 4, 4, 4>, 4, 4>;
 using T2048 = Sched<2048, 4, RList<4, 4, 4, 4, 4, 2>, RList<2, 4, 4, 4, 4, 4>, 4, 2>;
 using T4096 = Sched<4096, 4, RList<4, 4, 4, 4, 4, 4>, RList<4, 4, 4, 4, 4, 4>, 4, 4>;
 using T8192 = S8192;  // 1024 threads already
+// At 1024 threads a wave gets at most 128 VGPRs, so the 4096- and 8192-point
+// kernels spill (gfx950 build: 160 / 504 bytes per lane at 4096 points with
+// one / two surfaces, 212 / 1592 at 8192); 512 threads of eight values per
+// thread spill as much at 4096 points and two surfaces (460 bytes).
 
 typedef cx<double> cd_t;
 
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(SC::TPC) __attribute__((amdgpu_waves_per_eu(2)
     k1d_trap_kernel(cd_t* __restrict__ psi, cd_t* __restrict__ rbuf,
                     const double* __restrict__ vraw, const cd_t* __restrict__ tw,
                     const double* __restrict__ taus, int nst, int64_t nsteps, double tk,
-                    double tol2, int maxit, int* __restrict__ stats) {
+                    double tol2, int maxit, long long* __restrict__ stats) {
   extern __shared__ char smem_raw[];
   cd_t* lds = reinterpret_cast<cd_t*>(smem_raw);
   __shared__ double red[4 * (SC::TPC / 64)];
@@ -124,7 +128,8 @@ __global__ void __launch_bounds__(SC::TPC) __attribute__((amdgpu_waves_per_eu(2)
   psi += (size_t)blockIdx.x * S * N;
   rbuf += (size_t)blockIdx.x * S * N;
   cd_t p[S][E], v[S][E];
-  int iters = 0, fails = 0, worst = 0;
+  long long iters = 0, fails = 0;
+  int worst = 0;
   for (int64_t step = 0; step < nsteps; ++step) {
     for (int j = 0; j < nst; ++j) {
       const double tau = taus[j];

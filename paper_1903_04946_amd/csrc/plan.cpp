@@ -793,7 +793,7 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
     return fail(SOP_ERR_INVALID, "the plan's splitting has no composition (VT/TV)");
   const int nst = (int)p->seq.g.size();
   const size_t vec = (size_t)count * p->S * p->n[0] * sizeof(double2);
-  const size_t sbytes = ((size_t)count * 3 * sizeof(int) + 255) / 256 * 256;
+  const size_t sbytes = ((size_t)count * 3 * sizeof(long long) + 255) / 256 * 256;
   const size_t need = vec + sbytes + (size_t)nst * sizeof(double);
   if (need > p->trap_bytes) {
     if (p->d_trap) {
@@ -826,14 +826,14 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
   g.tk = (double)((ld)p->hbar * p->hbar * p->inv_mass[0] * kap * kap / 2);
   g.tol2 = tol * tol;
   g.maxit = max_iter;
-  g.stats = (int*)(base + vec);
+  g.stats = (long long*)(base + vec);
   g.count = count;
   {
     sop::TimedLaunch tl(d, sop::KIND_1D, 0.0);
     HIPTRY(sop::k1d_trapezoid(d, g));
   }
-  std::vector<int> st((size_t)count * 3);
-  HIPTRY(hipMemcpyAsync(st.data(), g.stats, st.size() * sizeof(int), hipMemcpyDeviceToHost,
+  std::vector<long long> st((size_t)count * 3);
+  HIPTRY(hipMemcpyAsync(st.data(), g.stats, st.size() * sizeof(long long), hipMemcpyDeviceToHost,
                         d.stream));
   HIPTRY(hipStreamSynchronize(d.stream));
   int64_t total = 0, failed = 0;
@@ -1116,6 +1116,7 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
        (p->eig_form ? sop::eig_slots(p->S) * 16.0 : (double)tab / (double)p->npts)) *
       (double)p->npts;
   const int nact = (int)p->dv.hprog.size();
+  const sop_status run = [&]() -> sop_status {
   for (int64_t n = 0; n < nsteps; ++n) {
     int v = 0;
     for (int a = 0; a < nact; ++a) {
@@ -1140,9 +1141,15 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
         HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
     }
   }
-  // back to the tables of the plan's own V (its V-table was not touched)
-  HIPTRY(form_tables(p));
-  HIPTRY(hipStreamSynchronize(st));
+  return SOP_OK;
+  }();
+  // back to the tables of the plan's own V (its V-table was not touched), on
+  // every exit path: a failed action must not leave the driven tables behind
+  const hipError_t ef = form_tables(p);
+  const hipError_t es = hipStreamSynchronize(st);
+  if (run != SOP_OK) return run;  // the loop's failure text is kept
+  HIPTRY(ef);
+  HIPTRY(es);
   return SOP_OK;
 }
 

@@ -118,6 +118,44 @@ def test_adjoint_vs_finite_differences_128(torch_cuda):
     assert np.max(np.abs(grad - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd)))
 
 
+@pytest.mark.timeout(300)
+def test_adjoint_config5_500_steps_k50(torch_cuda):
+    """The full adjoint configuration at 128^3 x 3: TJ-6, dt = 10, 500 steps,
+    checkpoints every K = 50 steps, so that ten reconstructions by time
+    reversibility (Appendix A) each run 50 steps backwards before a stored
+    state replaces the recomputed one.  Gradient of P_3 against central
+    differences (h = 1e-5 eV) within 1e-6 relative, and the gradient of the
+    total norm vanishes (sum_s dP_s/dtheta = 0)."""
+    torch = torch_cuda
+    m, theta0, v0 = base_model(128)
+    nsteps, K = 500, 50
+    plan = make_plan(torch, m, v0, "triple_jump", 6, 10.0)
+    psi0 = torch.from_numpy(m.psi0).cuda()
+    plan.set_params(theta0)
+    ws = plan.adjoint_workspace(nsteps, K)
+    pops = plan.adjoint_forward(psi0, nsteps, K, ws)
+    grad = plan.adjoint_backward(nsteps, K, [0, 0, 1.0], ws)
+    print(f"[adjoint 128^3 x 500] pops {pops}", flush=True)
+    plan.adjoint_forward(psi0, nsteps, K, ws)
+    gn = plan.adjoint_backward(nsteps, K, [1.0, 1.0, 1.0], ws)
+    h = 1e-5
+    fd = np.zeros(3)
+    for k in range(3):
+        vals = []
+        for sgn in (1, -1):
+            th = theta0.copy()
+            th[k] += sgn * h
+            plan.set_params(th)
+            vals.append(plan.adjoint_forward(psi0, nsteps, K, ws)[2])
+        fd[k] = (vals[0] - vals[1]) / (2 * h)
+        print(f"[adjoint 128^3 x 500] theta_{k}: grad {grad[k]:.12e} fd {fd[k]:.12e}",
+              flush=True)
+    print(f"[adjoint 128^3 x 500] norm gradient {gn}")
+    assert np.max(np.abs(gn)) < 1e-10 * max(1.0, np.max(np.abs(grad)))
+    assert np.max(np.abs(grad - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd)))
+    assert np.all(np.abs(fd) > 0)
+
+
 def test_adjoint_256_bench_shape(torch_cuda):
     """256^3 x 3, TJ-6, dt = 10 (the largest adjoint configuration, at the
     bench's launch shape): gradient of P_3 vs central differences (h = 1e-5

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1903_04946_amd import synth
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -141,10 +142,8 @@ def test_batch_fp64_matches_oracle_and_single_runs(torch_cuda, orc):
             continue
         P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
         ref = orc.propagate(P, m.psi0, SPLIT_ID[split], COMP_ID[comp], order, dt, k)
-        err = rel_l2(got[i], ref)
-        print(f"[batch] member {i} {kind} n={n} S={S} {split} {comp}-{order} "
-              f"nsteps={k}: {err:.2e}", flush=True)
-        assert err < FP64_TOL, f"member {i}"
+        assert_parity(got[i], ref, FP64_TOL, f"batch member {i} {kind} n={n} S={S} {split} "
+                      f"{comp}-{order} nsteps={k}")
     check_vs_single(batch, got, single_runs(torch, plans, models, ns, torch.complex128),
                     FP64_TOL)
 
@@ -205,9 +204,8 @@ def test_batch_fp32(torch_cuda, orc):
     for i, ((kind, n, S, split, comp, order, dt, k, off), m) in enumerate(zip(mix, models)):
         P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
         ref = orc.propagate(P, m.psi0, SPLIT_ID[split], COMP_ID[comp], order, dt, k)
-        err = rel_l2(psis[i].cpu().numpy().astype(np.complex128), ref)
-        print(f"[batch fp32] member {i} {kind} n={n} {comp}-{order}: {err:.2e}", flush=True)
-        assert err < 2e-5, f"member {i}"
+        assert_parity(psis[i].cpu().numpy().astype(np.complex128), ref, 2e-5,
+                      f"batch fp32 member {i} {kind} n={n} {comp}-{order}", elem_tol=8e-5)
 
 
 def test_batch_tuning_cache(torch_cuda, tmp_path):
@@ -272,8 +270,7 @@ def test_batch_every_variant_matches_oracle(torch_cuda, orc):
             batch.propagate(psis, ns)
             torch.cuda.synchronize()
             for i, ref in enumerate(refs):
-                err = rel_l2(psis[i].cpu().numpy(), ref)
-                assert err < FP64_TOL, f"variant {v} member {i}: {err:.2e} {json.dumps(d)}"
+                assert_parity(psis[i].cpu().numpy(), ref, FP64_TOL, f"variant {v} member {i}")
             batch.close()
     finally:
         if os.path.exists(path):
@@ -327,10 +324,9 @@ def test_ensemble_manifest_bench_shape(torch_cuda, orc):
         P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
         ref = orc.propagate(P, m.psi0, SPLIT_ID["VTV"], COMP_ID[e["scheme"]], e["order"],
                             e["dt"], ns[i])
-        err = rel_l2(psis[i].cpu().numpy(), ref)
-        print(f"[ensemble] member {i} {e['kind']} n={e['n']} {e['scheme']}-{e['order']} "
-              f"nsteps={ns[i]}: {err:.2e} vs oracle", flush=True)
-        assert err < FP64_TOL, f"member {i}"
+        assert_parity(psis[i].cpu().numpy(), ref, FP64_TOL,
+                      f"ensemble member {i} {e['kind']} n={e['n']} {e['scheme']}-{e['order']} "
+                      f"nsteps={ns[i]} vs oracle")
 
 
 def test_batch_plane_pass_equals_three_passes(torch_cuda):
@@ -352,3 +348,56 @@ def test_batch_plane_pass_equals_three_passes(torch_cuda):
     assert not any(g["plane"] for g in b.describe()["groups"])
     for i in range(len(ns)):
         np.testing.assert_array_equal(pa[i].cpu().numpy(), pb[i].cpu().numpy(), err_msg=f"{i}")
+
+
+@pytest.mark.timeout(600)
+def test_ensemble_manifest_full_final_time(torch_cuda, orc):
+    """The 256-member manifest with every member run to t_f = 10 a.u.
+    (200 to 2000 steps of up to 125 substeps): the longest runs exceed the
+    graph's launch budget, so this covers the batch's eager path too.
+    Sampled members (the most expensive of each kind and a spread) equal
+    their single-plan runs (3D bitwise, 1D to the FP64 bar); the cheapest 1D
+    and 3D members match the oracle; every member keeps its norm."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    man = synth.batch_manifest(t_final=10.0)
+    models = [synth.ensemble_model(e) for e in man]
+    plans = [soprop.Plan.from_model(m, comp=e["scheme"], order=e["order"], dt=e["dt"])
+             for e, m in zip(man, models)]
+    ns = [e["nsteps"] for e in man]
+    assert min(ns) >= 200 and max(ns) <= 2000
+    batch = soprop.Batch(plans)
+    psis = states(torch, models, torch.complex128)
+    batch.propagate(psis, ns)
+    torch.cuda.synchronize()
+    d = batch.describe()
+    print("[ensemble t_f=10] " + json.dumps({k: v for k, v in d.items() if k != "families"}),
+          flush=True)
+    Ms = [p.info.M for p in plans]
+    cost = [k * M * int(np.prod(m.n)) for k, M, m in zip(ns, Ms, models)]
+    kinds = [e["kind"] for e in man]
+    pick = {int(np.argmax([c if k == kk else -1 for c, k in zip(cost, kinds)]))
+            for kk in ("1d", "3d")}
+    pick.update(range(5, 256, 51))
+    for i in sorted(pick):
+        one = torch.from_numpy(models[i].psi0.copy()).cuda()
+        plans[i].propagate(one, ns[i])
+        a, b = psis[i].cpu().numpy(), one.cpu().numpy()
+        print(f"[ensemble t_f=10] member {i} {kinds[i]} n={man[i]['n']} "
+              f"{man[i]['scheme']}-{man[i]['order']} nsteps={ns[i]} vs single run", flush=True)
+        if kinds[i] == "3d":
+            np.testing.assert_array_equal(a, b, err_msg=f"member {i}")
+        else:
+            assert_parity(a, b, FP64_TOL, f"member {i} vs its single run")
+    for i, (p, x) in enumerate(zip(plans, psis)):
+        assert abs(p.observables(x)["norm"] - 1.0) < 1e-10, f"member {i}"
+    for kk in ("1d", "3d"):
+        i = int(np.argmin([c if k == kk else np.inf for c, k in zip(cost, kinds)]))
+        m, e = models[i], man[i]
+        P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
+        ref = orc.propagate(P, m.psi0, SPLIT_ID["VTV"], COMP_ID[e["scheme"]], e["order"],
+                            e["dt"], ns[i])
+        assert_parity(psis[i].cpu().numpy(), ref, FP64_TOL,
+                      f"ensemble t_f=10 member {i} {kk} n={e['n']} {e['scheme']}-{e['order']} "
+                      f"nsteps={ns[i]} vs oracle")
+    batch.close()

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1903_04946_amd import synth
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -63,9 +64,7 @@ def test_1d_yoshida6(torch_cuda, orc, split, n):
     g = synth.yoshida6_gammas()
     got, plan = run_custom(torch, m, split, g, 6, 0.05, 20, torch.complex128)
     ref = oracle_custom(orc, m, split, g, 0.05, 20)
-    err = rel_l2(got, ref)
-    print(f"[custom 1d n={n} {split}] rel L2 {err:.2e}")
-    assert err < FP64_TOL
+    assert_parity(got, ref, FP64_TOL, f"custom 1d n={n} {split}")
     info = plan.info
     assert (info.M, info.n_a_unq, info.n_b_unq) == (7, 4, 4)
 
@@ -79,9 +78,7 @@ def test_3d_table2_optimal_stage_counts(torch_cuda, orc, order, M):
     g = synth.random_symmetric_gammas(M, seed=order)
     got, plan = run_custom(torch, m, "VTV", g, order, 10.0, 3, torch.complex128)
     ref = oracle_custom(orc, m, "VTV", g, 10.0, 3)
-    err = rel_l2(got, ref)
-    print(f"[custom 3d M={M}] rel L2 {err:.2e}")
-    assert err < FP64_TOL
+    assert_parity(got, ref, FP64_TOL, f"custom 3d M={M}")
     info = plan.info
     assert (info.M, info.n_a, info.n_a_unq, info.n_b_unq) == (M, M + 1, (M + 1) // 2,
                                                                 (M + 1) // 2)
@@ -95,9 +92,8 @@ def test_3d_yoshida6(torch_cuda, orc, n, dtype_name, tol):
     g = synth.yoshida6_gammas()
     got, _ = run_custom(torch, m, "TVT" if n == 32 else "VTV", g, 6, 10.0, 2, dtype)
     ref = oracle_custom(orc, m, "TVT" if n == 32 else "VTV", g, 10.0, 2)
-    err = rel_l2(got, ref)
-    print(f"[custom 3d n={n} {dtype_name}] rel L2 {err:.2e}")
-    assert err < tol
+    assert_parity(got, ref, tol, f"custom 3d n={n} {dtype_name}",
+                  elem_tol=4 * tol if dtype_name == "complex64" else None)
 
 
 def test_builtin_coefficients_as_custom_match_builtin_plan(torch_cuda, orc):

@@ -395,3 +395,33 @@ def test_driven_wrong_times_lose_the_order(orc):
         dts.append(dt)
     slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
     assert slope < 1.8  # about first order (1.35 over these steps), far from 4
+
+
+@pytest.mark.parametrize("case", ["1d_tj4", "3d_16cube_sf4"])
+@pytest.mark.parametrize("split", ["VTV", "TVT"])
+def test_timed_loop_equals_propagate(orc, case, split):
+    """The loop the CPU baseline times is the pruned propagation itself: its
+    state is bitwise that of orc_propagate(pruned=1), and both equal the
+    unpruned stage-by-stage application to rounding (Sec. "Compositions of
+    split-operator algorithms": the pruned sequence is the same map)."""
+    if case == "1d_tj4":
+        m = synth.two_surface_1d(n=256)
+        scheme, order, dt, nsteps = orc.TRIPLE_JUMP, 4, 0.05, 7
+    else:
+        m = synth.lvc_3d(n=16)
+        scheme, order, dt, nsteps = orc.SUZUKI, 4, 10.0, 3
+    sp = getattr(orc, split)
+    P = problem(orc, m)
+    psi0 = m.psi0 + 0.1 * synth.random_state(m.psi0.shape, seed=5, dV=m.dV)
+    got, sec, threads = orc.propagate_timed(P, psi0, sp, scheme, order, dt, nsteps)
+    ref = orc.propagate(P, psi0, sp, scheme, order, dt, nsteps)
+    assert sec >= 0.0 and threads >= 1
+    assert np.array_equal(got.view(np.float64), ref.view(np.float64))
+    # the merged half-steps round their summed phase once: at the 1D model's
+    # wall (V22 up to 1e7 Ha) the phases reach 1e5 rad, so agreement is to
+    # about eps * 1e5 there
+    unpruned = orc.propagate(P, psi0, sp, scheme, order, dt, nsteps, pruned=False)
+    assert l2(m, got - unpruned) < 1e-11 * l2(m, unpruned)
+    # a zero-step run leaves the state alone
+    same, _, _ = orc.propagate_timed(P, psi0, sp, scheme, order, dt, 0)
+    assert np.array_equal(same, psi0.reshape(same.shape))
