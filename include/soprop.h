@@ -375,6 +375,24 @@ sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 sop_status sop_propagate_trapezoid(sop_plan* plan, void* psi, int count, int64_t nsteps,
                                    double tol, int max_iter, int64_t* iterations);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): sop_propagate_trapezoid with the same
+ * arguments, kernel and results (bitwise), whose workspace is a static
+ * device array of SOP_TRAP_SCRATCH_BYTES (32 MiB) that every GPU the library
+ * runs on holds until the process ends, instead of plan memory grown on
+ * demand.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); it needs count * nsurf * N * 16 bytes of residuals plus
+ * 24 bytes of statistics per state (rounded up to 256) and 8 bytes per
+ * composition stage, and returns SOP_ERR_INVALID, before any device work, if
+ * that exceeds the array (e.g. at most 1023 states of 1024 points and two
+ * surfaces).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  Nothing in the array needs clearing between
+ * calls.  Synchronises the plan's stream. */
+#define SOP_TRAP_SCRATCH_BYTES ((size_t)32 << 20)
+sop_status sop_propagate_trapezoid_noalloc(sop_plan* plan, void* psi, int count, int64_t nsteps,
+                                           double tol, int max_iter, int64_t* iterations);
+
 /* Trigonometric interpolation of a state onto another grid (Appendix B:
  * states on grids of different range and density are compared through the
  * trigonometric interpolant of the one on the sparser grid).  psi_dst

@@ -202,6 +202,11 @@ struct TrapArgs {
 };
 bool k1d_trap_supported(int n, int S);
 hipError_t k1d_trapezoid(const DevView& d, const TrapArgs& g);
+// The allocation-free trapezoid call's static device scratch: its size, and
+// its device address on the GPU of `stream` (NULL: the current device),
+// looked up once per device and kept.
+size_t trap_scratch_bytes();
+hipError_t trap_scratch(hipStream_t stream, void** out);
 
 // kernels_interp.hip: trigonometric interpolation between uniform grids.
 // Complex FP64 product C[b] = A[b] B[b] (M x K by K x N) with element and

@@ -17,7 +17,17 @@
 // touched only by the thread that owns it), the direction p and H p in
 // registers; dot products are workgroup sums in a fixed order.  The loop
 // ends for every thread together: its conditions are block-wide values.
+#include <mutex>
+
 #include "body_1d.hpp"
+
+// Device scratch of sop_propagate_trapezoid_noalloc (residuals, per-state
+// statistics, stage coefficients): a fixed array per GPU, held until the
+// process ends, so that the call needs no allocation.  Host code never
+// passes this name to a kernel or a copy: it is a host-side stand-in, and
+// the device address comes from hipGetSymbolAddress (sop::trap_scratch).
+static constexpr size_t kTrapScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kTrapScratchBytes];
 
 namespace sop {
 namespace {
@@ -233,6 +243,38 @@ hipError_t launch_trap(const DevView& d, const TrapArgs& g) {
 }
 
 }  // namespace
+
+size_t trap_scratch_bytes() { return kTrapScratchBytes; }
+
+hipError_t trap_scratch(hipStream_t stream, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = stream ? hipStreamGetDevice(stream, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    // once per device, with that device current: every GPU holds its own
+    // copy of the array at its own address
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
 
 bool k1d_trap_supported(int n, int S) {
   return (S == 1 || S == 2) && (n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 8192);

@@ -779,8 +779,19 @@ sop_status sop_distance(sop_plan* p, const void* psi, const void* phi, double* o
   return SOP_OK;
 }
 
-sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t nsteps, double tol,
-                                   int max_iter, int64_t* iterations) {
+}  // extern "C"
+
+namespace {
+
+// Device workspace of the trapezoidal rule: count S N complex residuals, the
+// per-state statistics (three int64 each) and the stage coefficients.
+struct TrapLayout {
+  size_t vec = 0, sbytes = 0, need = 0;
+  int nst = 0;
+};
+
+sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nsteps, double tol,
+                      int max_iter, TrapLayout* lay) {
   if (!p || !psi) return fail(SOP_ERR_INVALID, "NULL argument");
   if (count < 1 || count > 65535) return fail(SOP_ERR_INVALID, "count must be 1..65535");
   if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
@@ -791,34 +802,29 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
                 "the trapezoidal rule runs on 1D SOP_C128 plans of 512..8192 points");
   if (p->seq.g.empty())
     return fail(SOP_ERR_INVALID, "the plan's splitting has no composition (VT/TV)");
-  const int nst = (int)p->seq.g.size();
-  const size_t vec = (size_t)count * p->S * p->n[0] * sizeof(double2);
-  const size_t sbytes = ((size_t)count * 3 * sizeof(long long) + 255) / 256 * 256;
-  const size_t need = vec + sbytes + (size_t)nst * sizeof(double);
-  if (need > p->trap_bytes) {
-    if (p->d_trap) {
-      HIPTRY(hipStreamSynchronize(p->dv.stream));
-      if (p->hook.free)
-        p->hook.free(p->hook.ctx, p->d_trap, (void*)p->home);
-      else
-        HIPTRY(hipFree(p->d_trap));
-      p->d_trap = nullptr;
-      p->trap_bytes = 0;
-    }
-    if (dalloc(p, &p->d_trap, need) != hipSuccess) return fail(SOP_ERR_NOMEM, "trapezoid workspace");
-    p->trap_bytes = need;
-  }
-  char* base = (char*)p->d_trap;
+  lay->nst = (int)p->seq.g.size();
+  lay->vec = (size_t)count * p->S * p->n[0] * sizeof(double2);
+  lay->sbytes = ((size_t)count * 3 * sizeof(long long) + 255) / 256 * 256;
+  lay->need = lay->vec + lay->sbytes + (size_t)lay->nst * sizeof(double);
+  return SOP_OK;
+}
+
+// Runs the trapezoidal-rule compositions with the workspace at `base`
+// (device, lay.need bytes; nothing in it needs clearing: every element is
+// written before it is read).  Synchronises the plan's stream.
+sop_status trap_run(sop_plan* p, void* psi, int count, int64_t nsteps, double tol, int max_iter,
+                    char* base, const TrapLayout& lay, int64_t* iterations) {
+  const int nst = lay.nst;
   std::vector<double> taus(nst);
   for (int j = 0; j < nst; ++j) taus[j] = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
   const DevView& d = p->dv;
-  HIPTRY(hipMemcpyAsync(base + vec + sbytes, taus.data(), nst * sizeof(double),
+  HIPTRY(hipMemcpyAsync(base + lay.vec + lay.sbytes, taus.data(), nst * sizeof(double),
                         hipMemcpyHostToDevice, d.stream));
   sop::TrapArgs g;
   g.psi = psi;
   g.rbuf = base;
   g.vraw = p->d_vraw;
-  g.taus = (const double*)(base + vec + sbytes);
+  g.taus = (const double*)(base + lay.vec + lay.sbytes);
   g.nst = nst;
   g.nsteps = nsteps;
   const ld L = (ld)p->hi[0] - (ld)p->lo[0];
@@ -826,7 +832,7 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
   g.tk = (double)((ld)p->hbar * p->hbar * p->inv_mass[0] * kap * kap / 2);
   g.tol2 = tol * tol;
   g.maxit = max_iter;
-  g.stats = (long long*)(base + vec);
+  g.stats = (long long*)(base + lay.vec);
   g.count = count;
   {
     sop::TimedLaunch tl(d, sop::KIND_1D, 0.0);
@@ -846,6 +852,48 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
     return fail(SOP_ERR_STATE, std::to_string(failed) + " of the linear solves did not reach tol in " +
                                    std::to_string(max_iter) + " iterations");
   return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t nsteps, double tol,
+                                   int max_iter, int64_t* iterations) {
+  TrapLayout lay;
+  const sop_status st = trap_check(p, psi, count, nsteps, tol, max_iter, &lay);
+  if (st != SOP_OK) return st;
+  if (lay.need > p->trap_bytes) {
+    if (p->d_trap) {
+      HIPTRY(hipStreamSynchronize(p->dv.stream));
+      if (p->hook.free)
+        p->hook.free(p->hook.ctx, p->d_trap, (void*)p->home);
+      else
+        HIPTRY(hipFree(p->d_trap));
+      p->d_trap = nullptr;
+      p->trap_bytes = 0;
+    }
+    if (dalloc(p, &p->d_trap, lay.need) != hipSuccess)
+      return fail(SOP_ERR_NOMEM, "trapezoid workspace");
+    p->trap_bytes = lay.need;
+  }
+  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)p->d_trap, lay, iterations);
+}
+
+sop_status sop_propagate_trapezoid_noalloc(sop_plan* p, void* psi, int count, int64_t nsteps,
+                                           double tol, int max_iter, int64_t* iterations) {
+  TrapLayout lay;
+  const sop_status st = trap_check(p, psi, count, nsteps, tol, max_iter, &lay);
+  if (st != SOP_OK) return st;
+  const size_t cap = sop::trap_scratch_bytes();
+  if (lay.need > cap)
+    return fail(SOP_ERR_INVALID,
+                "count * nsurf * N complex residuals plus statistics and coefficients need " +
+                    std::to_string(lay.need) + " bytes, more than the static scratch of " +
+                    std::to_string(cap) + " bytes");
+  void* base = nullptr;
+  HIPTRY(sop::trap_scratch(p->dv.stream, &base));
+  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)base, lay, iterations);
 }
 
 sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* dst,

@@ -83,7 +83,8 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_scheme_sequence", "sop_custom_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
            "sop_plan_destroy", "sop_plan_info_get",
            "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-           "sop_distance", "sop_interpolate", "sop_propagate_trapezoid", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+           "sop_distance", "sop_interpolate", "sop_propagate_trapezoid",
+           "sop_propagate_trapezoid_noalloc", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
            "sop_plan_set_params",
            "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
            "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -130,6 +131,9 @@ def lib():
     L.sop_interpolate.argtypes = [vp, vp, vp, vp]
     L.sop_propagate_trapezoid.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
                                           ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+    L.sop_propagate_trapezoid_noalloc.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64,
+                                                  ctypes.c_double, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_int64)]
     L.sop_apply_action.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double]
     L.sop_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.sop_plan_set_params.argtypes = [vp, dp]
@@ -154,7 +158,8 @@ def lib():
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
               "sop_plan_destroy", "sop_plan_info_get",
               "sop_plan_set_stream", "sop_propagate", "sop_observables", "sop_overlap",
-              "sop_distance", "sop_interpolate", "sop_propagate_trapezoid", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
+              "sop_distance", "sop_interpolate", "sop_propagate_trapezoid",
+           "sop_propagate_trapezoid_noalloc", "sop_apply_action", "sop_plan_set_timing", "sop_timing_read",
               "sop_plan_set_params",
               "sop_plan_update_v", "sop_action_times", "sop_propagate_driven",
               "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
@@ -424,10 +429,12 @@ class Plan:
             raise ValueError(f"psi must be a contiguous tensor of shape {self.shape}")
 
     def propagate_trapezoid(self, psi, nsteps: int, tol: float = 1e-13,
-                            max_iter: int = 10000) -> int:
+                            max_iter: int = 10000, noalloc: bool = False) -> int:
         """psi ([S, N], or [count, S, N] independent states) advanced in place
         by nsteps steps of the plan's composition of the trapezoidal rule
-        (sop_propagate_trapezoid); returns the number of linear-solver
+        (sop_propagate_trapezoid, or with noalloc=True
+        sop_propagate_trapezoid_noalloc, whose workspace is the library's
+        static device scratch); returns the number of linear-solver
         iterations."""
         import torch
         if psi.dim() == len(self.shape) + 1:
@@ -439,9 +446,10 @@ class Plan:
             self._check_psi(psi)
             count = 1
         it = ctypes.c_int64()
-        _check(lib().sop_propagate_trapezoid(self._h, ctypes.c_void_p(psi.data_ptr()), int(count),
-                                             int(nsteps), float(tol), int(max_iter),
-                                             ctypes.byref(it)), "sop_propagate_trapezoid")
+        name = "sop_propagate_trapezoid_noalloc" if noalloc else "sop_propagate_trapezoid"
+        _check(getattr(lib(), name)(self._h, ctypes.c_void_p(psi.data_ptr()), int(count),
+                                    int(nsteps), float(tol), int(max_iter), ctypes.byref(it)),
+               name)
         return int(it.value)
 
     def set_stream(self, stream=None):
