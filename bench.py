@@ -70,6 +70,10 @@ DRIVEN = {"driven_lvc3d_128cube_x3_tj6_c128": 128}
 # larger per axis (n -> 2n).
 INTERPS = {"interp_lvc3d_128to256cube_x3_c128": (128, 256)}
 FP64_PEAK_TFS = 78.6
+# Appendix B: convergence with grid density on the LVC model, 32..256 points
+# per axis with range and density x sqrt(2) per doubling, SF-6, t_f = 500 a.u.
+# in 128 steps (the paper: t_f/2^7 with a sixth-order composition)
+GRIDCONV = {"gridconv_lvc3d_32to256_sf6_c128": (32, 64, 128, 256)}
 # Compositions of the trapezoidal rule (the implicit comparison integrator):
 # count independent 1D two-surface states, one workgroup each.
 TRAPS = {"trapezoid_random1d_1024_x2_tj4_c128": (1024, 512)}
@@ -163,6 +167,35 @@ def cpu_baseline(model, comp, order, dt, substeps_per_step, budget_s=12.0):
             "single_thread": {"value": units_1t / sec_1t, "sample": f"1 step ({sec_1t:.2f} s)"}}
 
 
+def zpass_beyond_cache(torch, soprop, comp, order, dt, steps=2):
+    """The dominant kernel where no last-level cache can hold its data: the
+    same composition on the 256^3 grid (805 MB state, 1.07 GB eigen table,
+    against the 256 MB MALL), its z-pass timed with HIP events on the plan's
+    stream over `steps` steps, and a plain device copy at the 128^3 z-pass's
+    read footprint (256 MiB, which the MALL can partly hold) next to the
+    1 GiB one."""
+    m = make_model(3, 256)
+    plan = soprop.Plan.from_model(m, comp=comp, order=order, dt=dt, dtype=torch.complex128)
+    psi = torch.from_numpy(m.psi0).cuda()
+    del m
+    plan.propagate(psi, 1)
+    plan.set_timing(True)
+    plan.propagate(psi, steps)
+    kt = plan.timing_read()
+    plan.set_timing(False)
+    z = kt["zpass"]
+    us = 1e3 * z["ms"] / z["count"]
+    gbs = z["bytes"] / z["count"] / (us / 1e6) / 1e9
+    plan.close()
+    del psi
+    torch.cuda.empty_cache()
+    return {"workload": "lvc3d_256cube_x3 (same scheme and dt)", "kernel": "zpass",
+            "avg_launch_us": us, "alg_bytes_per_launch": z["bytes"] / z["count"],
+            "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "timing": "HIP events on the plan's stream around every launch",
+            "stream_copy_256MiB_GBps": stream_copy_gbps(torch, 1 << 28)}
+
+
 def stream_copy_gbps(torch, nbytes=1 << 30, reps=5):
     """Context for the roofline: read + write bandwidth of a plain 1 GiB
     elementwise device copy (torch's vectorized kernel), best of reps."""
@@ -246,15 +279,16 @@ def _l2(a, b, dV, batch=False):
 
 
 def _sweep(run, psi0, ref, dV, tf, schemes, kmax, dtype, eps_stop, count=1, kmax_strang=None,
-           nsteps_scale=1):
-    """dt = tf / (nsteps_scale 2^k), k = 1, 2, ..., until the error is below
-    eps_stop or stops falling."""
+           nsteps_scale=1, kmin=1, kmin_strang=None):
+    """dt = tf / (nsteps_scale 2^k), k = kmin, kmin + 1, ..., until the error
+    is below eps_stop or stops falling."""
     out = {}
     for comp, order in schemes:
         top = kmax_strang if (comp == "strang" and kmax_strang) else kmax
+        bottom = kmin_strang if (comp == "strang" and kmin_strang) else kmin
         pts = []
         prev = None
-        for k in range(1, top + 1):
+        for k in range(bottom, top + 1):
             psi, sec = run(psi0, comp, order, nsteps_scale * 2**k, tf, dtype, count=count)
             e = _l2(psi, ref, dV, batch=count > 1)
             pts.append((sec / count, e, k))
@@ -279,24 +313,40 @@ def _strang_extrapolation(pts, tf, eps):
     return t2 / 2**k2 * tf / dt_star
 
 
-def time_to_error(torch, soprop, members=256):
+def _lvc32_packets(m, members, seed=4946):
+    """`members` Gaussian packets on surface 3 of the 32^3 LVC grid with
+    q0 ~ U[-3, 3]^3, p0 ~ U[-2, 2]^3 (seeded)."""
+    from paper_1903_04946_amd import synth
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ax = m.axes()
+    psis = np.zeros((members, 3, 32, 32, 32), complex)
+    for i in range(members):
+        q0 = rng.uniform(-3, 3, 3)
+        p0 = rng.uniform(-2, 2, 3)
+        g = [synth.gaussian_1d(ax[d], q0[d], p0[d], 1.0) for d in range(3)]
+        psis[i, 2] = g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :]
+        psis[i] = synth.normalise(psis[i], m.dV)
+    return psis
+
+
+def tte_lvc3d(torch, soprop, members=256, full=False):
     """Time to reach a final-time L2 error of 1e-10 (FP64, single run) and of
-    1e-5 (FP32, batched) for every composition, against plain Strang.
+    1e-5 (FP32, batched, worst member) for the compositions, against plain
+    Strang, on the same GPU.
 
     Workload: the three-mode, three-surface LVC model on a 32^3 grid (the
     paper's pyrazine grid: 32 points per mode on [-7, 7]), t_f = 500 a.u.
-    FP64 reference: TJ-10 at dt = t_f/2^12 (checked against SF-10 at
-    t_f/2^9).  FP32 batch: `members` initial packets on surface 3 with
-    q0 ~ U[-3, 3]^3, p0 ~ U[-2, 2]^3 (seed 4946), each compared with its own
-    FP64 reference (TJ-8 at t_f/2^10, one batched launch); times are per
-    member.  Also records the configured 1D two-surface sweep (dt = 2^-1 ..
-    2^-10 to t = 10 against TJ-10 at 2^-12) as measured.
-    """
-    import numpy as np
+    FP64 reference: TJ-10 at dt = t_f/2^12, checked against SF-10 at
+    t_f/2^9.  Strang does not reach 1e-10 above its step-count budget, so
+    its time is extrapolated along its dt^2 asymptote from the finest
+    points.  FP32 batch: `members` packets on surface 3 with q0 ~ U[-3, 3]^3,
+    p0 ~ U[-2, 2]^3 (seed 4946), each compared with its own FP64 reference
+    (TJ-8, one batched launch); times are per member (batch wall time /
+    members).  full=False trims the sweeps to the points around the
+    crossings (a default benchmark run); full=True sweeps every dt from
+    t_f/2 down."""
     from paper_1903_04946_amd import synth
 
-    res = {}
-    # ----------------------------------------------------------- 3D LVC, 32^3
     m = synth.lvc_3d(n=32)
     run = _Runner(torch, soprop, m)
     tf = 500.0
@@ -305,8 +355,14 @@ def time_to_error(torch, soprop, members=256):
     r3 = {"model": "LVC 3 modes x 3 surfaces, 32^3 on [-7,7)^3, t_f = 500 a.u.",
           "reference": "TJ-10, dt = t_f/2^12, FP64", "reference_time_s": tref,
           "reference_vs_sf10_t_f/2^9": _l2(chk, ref, m.dV)}
-    sw = _sweep(run, m.psi0, ref, m.dV, tf, TTE_SCHEMES, 12, torch.complex128, 1e-11,
-                kmax_strang=17)
+    if full:
+        sw = _sweep(run, m.psi0, ref, m.dV, tf, TTE_SCHEMES, 12, torch.complex128, 1e-11,
+                    kmax_strang=17)
+    else:
+        sw = _sweep(run, m.psi0, ref, m.dV, tf,
+                    [("strang", 2), ("triple_jump", 6), ("suzuki", 4), ("suzuki", 6),
+                     ("suzuki", 8)], 11, torch.complex128, 3e-11, kmin=5, kmin_strang=10,
+                    kmax_strang=14)
     fp64 = {}
     for name, pts in sw.items():
         rec = {"runs": [{"dt": f"t_f/2^{k}", "seconds": t, "error": e} for t, e, k in pts],
@@ -326,34 +382,78 @@ def time_to_error(torch, soprop, members=256):
                            "speedup_vs_strang": (st / best[0]) if st else None,
                            "strang_extrapolated": bool(fp64["strang-2"].get("extrapolated"))}
     # FP32 batched
-    rng = np.random.Generator(np.random.PCG64(4946))
-    ax = m.axes()
-    psis = np.zeros((members, 3, 32, 32, 32), complex)
-    for i in range(members):
-        q0 = rng.uniform(-3, 3, 3)
-        p0 = rng.uniform(-2, 2, 3)
-        g = [synth.gaussian_1d(ax[d], q0[d], p0[d], 1.0) for d in range(3)]
-        psis[i, 2] = g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :]
-        psis[i] = synth.normalise(psis[i], m.dV)
-    refs, trefs = run(psis, "triple_jump", 8, 2**10, tf, torch.complex128, count=members,
+    psis = _lvc32_packets(m, members)
+    kref = 10 if full else 8
+    refs, trefs = run(psis, "triple_jump", 8, 2**kref, tf, torch.complex128, count=members,
                       label="batched references")
-    b32 = _sweep(run, psis, refs, m.dV, tf,
-                 [("strang", 2), ("suzuki", 4), ("triple_jump", 4), ("suzuki", 6)], 10,
-                 torch.complex64, 1e-6, count=members)
+    if full:
+        b32 = _sweep(run, psis, refs, m.dV, tf,
+                     [("strang", 2), ("suzuki", 4), ("triple_jump", 4), ("suzuki", 6)], 10,
+                     torch.complex64, 1e-6, count=members)
+    else:
+        b32 = _sweep(run, psis, refs, m.dV, tf,
+                     [("strang", 2), ("suzuki", 4), ("suzuki", 6)], 11, torch.complex64, 1e-6,
+                     count=members, kmin=5, kmin_strang=8)
     r3["fp32_batched"] = {
-        "members": members, "reference": "TJ-8, dt = t_f/2^10, FP64 (batched)",
+        "members": members, "reference": f"TJ-8, dt = t_f/2^{kref}, FP64 (batched)",
         "schemes": {n: {"runs": [{"dt": f"t_f/2^{k}", "seconds_per_member": t, "max_error": e}
                                  for t, e, k in pts],
                         "time_to_1e-5_s_per_member": _interp_time([(t, e) for t, e, _ in pts],
-                                                                  1e-5)}
+                                                                  1e-5),
+                        "floor_max_error": min(e for _, e, _ in pts)}
                     for n, pts in b32.items()}}
     b64 = _sweep(run, psis, refs, m.dV, tf, [("strang", 2)], 12, torch.complex128, 1e-6,
-                 count=members)
+                 count=members, kmin=7)
     r3["fp64_strang_batched_time_to_1e-5_s_per_member"] = _interp_time(
         [(t, e) for t, e, _ in b64["strang-2"]], 1e-5)
-    r3["fp64_strang_single_time_to_1e-5_s"] = _interp_time(
-        [(r["seconds"], r["error"]) for r in fp64["strang-2"]["runs"]], 1e-5)
-    res["lvc3d_32cube"] = r3
+    srun = fp64["strang-2"]["runs"]
+    if full or any(r["error"] > 1e-5 for r in srun):
+        r3["fp64_strang_single_time_to_1e-5_s"] = _interp_time(
+            [(r["seconds"], r["error"]) for r in srun], 1e-5)
+    else:  # the trimmed sweep starts below 1e-5: one single run brackets it
+        pts = []
+        for k in (8, 9, 10):
+            psi, sec = run(m.psi0, "strang", 2, 2**k, tf, torch.complex128)
+            pts.append((sec, _l2(psi, ref, m.dV)))
+        r3["fp64_strang_single_time_to_1e-5_s"] = _interp_time(pts, 1e-5)
+    return r3
+
+
+def tte_summary(r3):
+    """The headline figures of tte_lvc3d."""
+    b = r3.get("fp64_best") or {}
+    f32 = r3["fp32_batched"]["schemes"]
+    cand = [(v["time_to_1e-5_s_per_member"], k) for k, v in f32.items()
+            if v["time_to_1e-5_s_per_member"] is not None]
+    out = {"workload": "lvc3d_32cube_x3, t_f = 500 a.u.",
+           "fp64_1e-10": {"best": b.get("scheme"), "seconds": b.get("seconds"),
+                          "strang_seconds": b.get("strang_seconds"),
+                          "strang_extrapolated": b.get("strang_extrapolated"),
+                          "speedup_vs_strang": b.get("speedup_vs_strang"),
+                          "reference": r3["reference"]},
+           "fp32_batched_1e-5": {"members": r3["fp32_batched"]["members"],
+                                 "worst_member_floor": {k: v["floor_max_error"]
+                                                        for k, v in f32.items()}}}
+    fs = r3.get("fp64_strang_batched_time_to_1e-5_s_per_member")
+    f1 = r3.get("fp64_strang_single_time_to_1e-5_s")
+    if cand:
+        t, k = min(cand)
+        out["fp32_batched_1e-5"].update({
+            "best": k, "seconds_per_member": t,
+            "fp64_strang_batched_seconds_per_member": fs,
+            "fp64_strang_single_seconds": f1,
+            "speedup_vs_fp64_strang_batched": fs / t if fs else None,
+            "speedup_vs_fp64_strang_single": f1 / t if f1 else None})
+    return out
+
+
+def time_to_error(torch, soprop, members=256):
+    """The full sweeps: tte_lvc3d(full=True), plus the configured 1D
+    two-surface sweep (dt = 2^-1 .. 2^-10 to t = 10 against TJ-10 at 2^-12)
+    as measured, and the same model with its V22 wall clipped."""
+    from paper_1903_04946_amd import synth
+
+    res = {"lvc3d_32cube": tte_lvc3d(torch, soprop, members, full=True)}
     # ----------------------------------------------------------- configured 1D
     m1 = synth.two_surface_1d(n=1024)
     run1 = _Runner(torch, soprop, m1)
@@ -694,18 +794,18 @@ def run_trapezoid(a, torch, soprop):
         H = O.dense_hamiltonian_1d(n, m.lo[0], m.hi[0], 2, m.inv_mass, m.vtable, m.hbar)
         g = O.gammas(1, 4)
         t1 = time.perf_counter()
-        O.propagate_trapezoid(H, states[0], g, dt, 1, m.hbar)  # forms the stage matrices
+        maps = O.trapezoid_stage_maps(H, g, dt, m.hbar)  # dense direct solves, once
         setup = time.perf_counter() - t1
         k = 200
         t1 = time.perf_counter()
         for i in range(4):
-            O.propagate_trapezoid(H, states[i], g, dt, k, m.hbar)
-        csec = time.perf_counter() - t1 - 4 * setup
-        cpu = {"value": m.nsurf * n * M * k * 4 / max(csec, 1e-9), "unit": UNIT,
+            O.propagate_trapezoid(H, states[i], g, dt, k, m.hbar, maps=maps)
+        csec = time.perf_counter() - t1
+        cpu = {"value": m.nsurf * n * M * k * 4 / csec, "unit": UNIT,
                "host": _host_cpu(), "cores": os.cpu_count(), "kind": "oracle",
-               "sample": f"4 states x {k} steps of the oracle's dense direct solves "
-                         f"(stage matrices formed per call, {setup:.2f} s each, excluded; "
-                         f"numpy's threads)"}
+               "sample": f"4 states x {k} steps of the oracle's trapezoidal rule with its "
+                         f"dense stage maps ({csec:.2f} s; the maps, formed once by dense "
+                         f"solves in {setup:.2f} s, excluded; numpy's threads)"}
     tte = _trapezoid_vs_split(torch, soprop, m, states[:64]) if a.time_to_error else None
     return {
         "metric": METRIC, "value": units / sec, "unit": UNIT, "n_gpus": 1,
@@ -725,6 +825,27 @@ def run_trapezoid(a, torch, soprop):
         "checks": {"norm_after": plan.observables(psi[0])["norm"], "wall_s_timed": sec},
         "kernel_source_hash": kernel_source_hash(),
     }
+
+
+def run_gridconv(a, torch, soprop):
+    """The grid-convergence study (paper_1903_04946_amd.gridconv), timed."""
+    from paper_1903_04946_amd import gridconv
+    ns = GRIDCONV[a.workload]
+    gridconv.grid_convergence(torch, ns=ns[:2], nsteps=2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = gridconv.grid_convergence(torch, ns=ns)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    units = sum(3 * n**3 * 25 * res["nsteps"] for n in ns)
+    return {"metric": METRIC, "value": units / sec, "unit": UNIT, "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": 1e3 * sec, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": a.workload, "grids": list(ns), "scheme": res["scheme"],
+                       "t_final": res["t_final"], "nsteps": res["nsteps"]},
+            "study": res,
+            "note": "value = the members' propagation units over the wall time of the whole "
+                    "study (propagation, interpolations and distances; host-timed)"}
 
 
 def run_adjoint(a, torch, soprop):
@@ -950,12 +1071,17 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS)
-                    + sorted(DRIVEN) + sorted(INTERPS) + sorted(TRAPS))
+                    + sorted(DRIVEN) + sorted(INTERPS) + sorted(TRAPS) + sorted(GRIDCONV))
     ap.add_argument("--fd-check", action="store_true",
                     help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-to-error", action="store_true",
-                    help="also run the time-to-error sweeps (about two minutes)")
+                    help="the full time-to-error sweeps, 1D models included (several "
+                         "minutes); without it the default workload runs the trimmed 3D "
+                         "sweeps")
+    ap.add_argument("--no-time-to-error", action="store_true")
+    ap.add_argument("--no-mall-check", action="store_true",
+                    help="default workload: skip the 256^3 z-pass figure beside the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -991,6 +1117,9 @@ def main(argv=None) -> int:
         return 0
     if a.workload in TRAPS:
         print(json.dumps(run_trapezoid(a, torch, soprop)))
+        return 0
+    if a.workload in GRIDCONV:
+        print(json.dumps(run_gridconv(a, torch, soprop)))
         return 0
     ndim, n, comp, order, dt, dts = WORKLOADS[a.workload]
     dtype = torch.complex128 if dts == "c128" else torch.complex64
@@ -1084,10 +1213,18 @@ def main(argv=None) -> int:
                       "lower_bound_frac": lb / sec / 1e9 / HBM_PEAK_GBS}
 
     copy_gbps = stream_copy_gbps(torch) if ndim == 3 else None
+    no_mall = None
+    if a.workload == DEFAULT and not a.no_mall_check:
+        no_mall = zpass_beyond_cache(torch, soprop, comp, order, dt)
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(model, comp, order, dt, M)
-    tte = time_to_error(torch, soprop) if a.time_to_error else None
+    tte = None
+    if a.time_to_error:
+        full = time_to_error(torch, soprop)
+        tte = tte_summary(full["lvc3d_32cube"]) | {"full": full}
+    elif a.workload == DEFAULT and not a.no_time_to_error:
+        tte = tte_summary(tte_lvc3d(torch, soprop))
 
     out = {
         "metric": METRIC,
@@ -1113,7 +1250,8 @@ def main(argv=None) -> int:
                      "traffic_frac": None if traffic is None
                      else traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch,
-                     "stream_copy_GBps": copy_gbps},
+                     "stream_copy_GBps": copy_gbps}
+        | ({} if no_mall is None else {"beyond_last_level_cache": no_mall}),
         "kernels": kernels,
         "step_bytes": step_bytes,
         "cpu_baseline": cpu,

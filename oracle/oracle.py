@@ -269,27 +269,42 @@ def dense_hamiltonian_1d(n, lo, hi, nsurf, inv_mass, vtable, hbar=1.0) -> np.nda
     return H
 
 
+def trapezoid_stage_maps(H: np.ndarray, gammas, dt: float, hbar: float = 1.0) -> dict:
+    """The stage maps (1 + i tau H)^-1 (1 - i tau H) of the trapezoidal rule,
+    tau = g dt / (2 hbar), one per distinct coefficient g, by dense direct
+    solves."""
+    eye = np.eye(H.shape[0])
+    maps = {}
+    for g in np.ravel(gammas):
+        tau = float(g) * dt / (2 * hbar)
+        if tau not in maps:
+            maps[tau] = np.linalg.solve(eye + 1j * tau * H, eye - 1j * tau * H)
+    return maps
+
+
 def propagate_trapezoid(H: np.ndarray, psi: np.ndarray, gammas, dt: float, nsteps: int,
-                        hbar: float = 1.0, per_stage: bool = False) -> np.ndarray:
+                        hbar: float = 1.0, per_stage: bool = False,
+                        maps: dict | None = None) -> np.ndarray:
     """nsteps steps of the composition of the trapezoidal rule with the
     coefficients gammas: each stage solves (1 + i tau H) x = (1 - i tau H) psi,
     tau = g dt / (2 hbar), by a dense direct solve.  By default the stage
-    matrix (1 + i tau H)^-1 (1 - i tau H) is formed once per distinct tau;
-    per_stage=True solves for the one right-hand side at every stage instead
-    (the cheaper choice on large grids with few stages)."""
+    maps are formed once per distinct tau (trapezoid_stage_maps, or `maps`
+    when given); per_stage=True solves for the one right-hand side at every
+    stage instead (the cheaper choice on large grids with few stages)."""
     shape = np.shape(psi)
     x = np.ascontiguousarray(psi, dtype=np.complex128).ravel().copy()
-    eye = np.eye(H.shape[0])
-    cache = {}
+    if per_stage:
+        eye = np.eye(H.shape[0])
+        for _ in range(int(nsteps)):
+            for g in np.ravel(gammas):
+                tau = float(g) * dt / (2 * hbar)
+                x = np.linalg.solve(eye + 1j * tau * H, x - 1j * tau * (H @ x))
+        return x.reshape(shape)
+    if maps is None:
+        maps = trapezoid_stage_maps(H, gammas, dt, hbar)
     for _ in range(int(nsteps)):
         for g in np.ravel(gammas):
-            tau = float(g) * dt / (2 * hbar)
-            if per_stage:
-                x = np.linalg.solve(eye + 1j * tau * H, x - 1j * tau * (H @ x))
-                continue
-            if tau not in cache:
-                cache[tau] = np.linalg.solve(eye + 1j * tau * H, eye - 1j * tau * H)
-            x = cache[tau] @ x
+            x = maps[float(g) * dt / (2 * hbar)] @ x
     return x.reshape(shape)
 
 

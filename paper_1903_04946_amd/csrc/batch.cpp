@@ -439,7 +439,7 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
       }
       b->fams[it->second].members.push_back(i);
     } else if (sop::k3b_supported(d.n[0], d.S) && vtv_m(d) > 0 &&
-               d.eig == sop::eig_form(3, d.S, d.f64)) {
+               d.eig == sop::eig_form(3, d.S)) {
       const std::string k = std::to_string(d.n[0]) + "/" + std::to_string(d.S) + "/" +
                             dtype_name(d.f64);
       auto it = gidx.find(k);

@@ -74,20 +74,18 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
       const int idx = code & 0xffff;
       const int t = guard<GUARD>(t0);
       if ((code >> 16) == OP_V) {
-        const cx<T>* U = vexp + (size_t)idx * NE * N;
+        // table entries are (rounded, residue) pairs in FP32
+        const cx<T>* U = vexp + (size_t)idx * NE * N * Split<T>::rep;
 #pragma unroll
         for (int q = 0; q < E; ++q) {
           const int x = own_idx<N, E, SC::RF>(t, q);
-          cx<T> u[NE];
+          Fac<T> u[NE];
 #pragma unroll
-          for (int e = 0; e < NE; ++e) {
-            u[e] = U[e * N + x];
-            u[e].im *= csign;
-          }
+          for (int e = 0; e < NE; ++e) u[e] = load_fac(U, e * N + x, csign);
           cx<T> w[S];
 #pragma unroll
           for (int s = 0; s < S; ++s) w[s] = v[s][q];
-          apply_u<T, S>(w, u);
+          apply_u_fac<T, S>(w, u);
 #pragma unroll
           for (int s = 0; s < S; ++s) v[s][q] = w[s];
         }

@@ -298,6 +298,23 @@ template <typename T>
 __device__ __forceinline__ cx<T> ld(__amdgpu_buffer_rsrc_t r, uint32_t idx) {
   return bld(r, idx, (cx<T>*)nullptr);
 }
+// Entry idx of a factor table (Split<T>::rep complex values per entry: in
+// FP32 the pair (rounded, residue), 16 bytes read by one load), conjugated
+// when csign = -1.
+template <typename T>
+__device__ __forceinline__ Fac<T> ldfac(__amdgpu_buffer_rsrc_t r, uint32_t idx, T csign) {
+  Fac<T> F;
+  if constexpr (std::is_same<T, float>::value) {
+    sop_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(idx * 16u), 0, 0);
+    const sop_f32x4 q = __builtin_bit_cast(sop_f32x4, v);
+    F.w = {q.x, csign * q.y};
+    F.lo = {q.z, csign * q.w};
+  } else {
+    F.w = bld(r, idx, (cx<T>*)nullptr);
+    F.w.im *= csign;
+  }
+  return F;
+}
 __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t idx, cx<double> v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(sop_u32x4, v), r, (int)(idx * 16u), 0, 0);
 }
@@ -472,6 +489,45 @@ __device__ __forceinline__ void apply_u(cx<T> (&w)[S], const cx<T> (&u)[S * (S +
       acc = cadd(acc, cmul(u[e], in[j]));
     }
     w[i] = acc;
+  }
+}
+
+// w = U v for the complex-symmetric U given by its packed upper triangle
+// (S(S+1)/2 entries, row-major) of factors read from a (split) table.  In
+// FP32 the matvec runs in FP64 on U = rounded + residue (exact to about
+// 1e-15) and each output is rounded to FP32 once.  An FP32 matvec would
+// round its partial sums, and with a coupling the potential action is a
+// near-identity unitary whose departure from the identity per step (the
+// population moved between surfaces) is a few parts in 1e8: those roundings
+// then lose norm at every action (measured on the two-surface model, 1000
+// Strang steps: norm 1.9e-5 low; with one rounding per output the norm only
+// wanders at the 1e-7 level).
+template <typename T, int S>
+__device__ __forceinline__ void apply_u_fac(cx<T> (&w)[S], const Fac<T> (&u)[S * (S + 1) / 2]) {
+  if constexpr (!std::is_same<T, float>::value) {
+    cx<T> uw[S * (S + 1) / 2];
+#pragma unroll
+    for (int e = 0; e < S * (S + 1) / 2; ++e) uw[e] = u[e].w;
+    apply_u<T, S>(w, uw);
+  } else {
+    cx<double> ud[S * (S + 1) / 2];
+#pragma unroll
+    for (int e = 0; e < S * (S + 1) / 2; ++e)
+      ud[e] = cx<double>{(double)u[e].w.re + (double)u[e].lo.re,
+                         (double)u[e].w.im + (double)u[e].lo.im};
+    cx<double> in[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) in[s] = cx<double>{(double)w[s].re, (double)w[s].im};
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      cx<double> acc = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int a = i < j ? i : j, b = i < j ? j : i;
+        acc = cadd(acc, cmul(ud[a * S - (a * (a - 1)) / 2 + (b - a)], in[j]));
+      }
+      w[i] = cx<float>{(float)acc.re, (float)acc.im};
+    }
   }
 }
 

@@ -102,8 +102,8 @@ struct DevView {
   int64_t npts = 1;
   bool f64 = true;
   hipStream_t stream = nullptr;
-  // [n_vtab][S(S+1)/2][npts] complex; when `eig`, the one compact
-  // eigen-form table instead
+  // [n_vtab][S(S+1)/2][npts] complex (FP32: (rounded, residue) pairs); when
+  // `eig`, the one compact FP64 eigen-form table instead
   const void* vexp = nullptr;
   bool eig = false;
   const double* vtaus = nullptr;  // device c dt / hbar of each potential coefficient
@@ -178,12 +178,13 @@ hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj);
 bool k3d_plane(int n, bool f64);  // the xy plane of an n^3 grid fits in LDS
 hipError_t k3d_fft_forward(const DevView& d, void* psi);
 
-// Complex slots per point of the compact eigen form (3D FP64, S = 2, 3).
+// Complex double slots per point of the compact eigen form (3D, S = 2, 3).
 constexpr int eig_slots(int S) { return S == 3 ? 4 : 2; }
 // Whether a plan of this kind can store the eigen form instead of
 // per-coefficient tables (it does when every phase tau lam stays within
-// kPhaseMax).
-constexpr bool eig_form(int ndim, int S, bool f64) { return ndim == 3 && f64 && S >= 2; }
+// kPhaseMax).  The form is FP64 in both precisions; FP32 plans apply it in
+// FP64 and round the state once.
+constexpr bool eig_form(int ndim, int S) { return ndim == 3 && S >= 2; }
 
 // kernels_trap.hip: compositions of the trapezoidal rule on 1D FP64 plans,
 // one workgroup per state (count states of S x N, consecutive).
@@ -269,7 +270,7 @@ struct BMember1 {
 // c = cycles its closing potential action.
 struct BMember3 {
   void* psi;          // [S][n^3]
-  const void* vexp;   // tile-layout potential tables (or the eigen form, FP64 S >= 2)
+  const void* vexp;   // tile-layout potential tables (or the FP64 eigen form, S >= 2)
   const double* vtaus;  // c dt / hbar of each potential coefficient (eigen form)
   const void* kin;    // [n_ttab][3][kin_stride]
   const void* tw;     // [3][n] twiddles (z, y, x blocks)

@@ -62,10 +62,10 @@ constexpr int zcols() {
 
 // ---------------------------------------------------------------- z-pass
 // grid (N / C, N, states); fz = the z factor of the kinetic set (AX_KIN)
-// EQ: the potential comes from the compact eigen form (FP64, S >= 2).
+// EQ: the potential comes from the compact eigen form (FP64 table, S >= 2).
 template <typename T, class SC, int S, int C, int AX, bool EQ>
 __global__ void __launch_bounds__(C * SC::TPC)
-    k3d_zpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp, int nv, int iv0, int iv1,
+    k3d_zpass(cx<T>* __restrict__ psi, const void* __restrict__ vexp, int nv, int iv0, int iv1,
               int conj, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fz,
               const double* __restrict__ taus) {
   extern __shared__ char smem_raw[];
@@ -368,15 +368,17 @@ struct Passes {
 
   // the potential may come from the compact eigen form (one table for every
   // coefficient; plans whose phases stay within kPhaseMax)
-  static constexpr bool EQ = eig_form(3, S, std::is_same<T, double>::value);
+  static constexpr bool EQ = eig_form(3, S);
 
   // algorithmic bytes of one pass: psi read + written (d.S pencil sets: the
   // adjoint's y- and x-passes run on the stacked 2S), plus tables read (the
-  // eigen form is read once for up to two actions)
+  // FP64 eigen form is read once for up to two actions; FP32 table entries
+  // are (rounded, residue) pairs)
   static double pass_bytes(const DevView& d, int ntables) {
-    const double tab = (EQ && d.eig) ? (ntables > 0 ? eig_slots(S) : 0)
-                                     : ntables * S * (S + 1) / 2.0;
-    return (2.0 * d.S + tab) * (double)d.npts * sizeof(cx<T>) * d.count;
+    const double tab = (EQ && d.eig) ? (ntables > 0 ? eig_slots(S) * sizeof(cx<double>) : 0.0)
+                                     : ntables * S * (S + 1) / 2.0 * sizeof(cx<T>) *
+                                           Split<T>::rep;
+    return (2.0 * d.S * sizeof(cx<T>) + tab) * (double)d.npts * d.count;
   }
   // axis factor a (0 z, 1 y, 2 x) of kinetic set tidx
   static const cx<T>* kfac(const DevView& d, int tidx, int a) {
@@ -400,7 +402,7 @@ struct Passes {
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
     hipLaunchKernelGGL(k, dim3(N / CZ, N, d.count), dim3(CZ * SC::TPC), lds, d.stream, psi,
-                       (const cx<T>*)d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0],
+                       d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0],
                        AX == AX_KIN ? kfac(d, tidx, 0) : nullptr, d.vtaus);
     return hipGetLastError();
   }

@@ -123,7 +123,14 @@ __global__ void __launch_bounds__(256)
             re += rr * ere[l];
             im += rr * eim[l];
           }
-          out[table_index(npts, NE, tile, n, u, ee, x)] = cx<T>{(T)re, (T)im};
+          const int64_t o = table_index(npts, NE, tile, n, u, ee, x);
+          if constexpr (sizeof(T) == 8) {
+            out[o] = cx<T>{(T)re, (T)im};
+          } else {  // FP32: the pair (rounded, residue) at index 2 o
+            const float hr = (float)re, hi = (float)im;
+            out[2 * o] = cx<float>{hr, hi};
+            out[2 * o + 1] = cx<float>{(float)(re - (double)hr), (float)(im - (double)hi)};
+          }
           ++ee;
         }
     }

@@ -40,9 +40,9 @@ __global__ void __launch_bounds__(C * SC::TPC)
   if (m.cycles <= 0 || c > m.cycles) return;
   const int M = m.M;
   cx<T>* psi = (cx<T>*)m.psi;
-  const cx<T>* vexp = (const cx<T>*)m.vexp;
+  const void* vexp = m.vexp;
   const cx<T>* tw = (const cx<T>*)m.tw;
-  constexpr bool EQ = eig_form(3, S, sizeof(T) == 8);
+  constexpr bool EQ = eig_form(3, S);
   if (c == m.cycles) {  // closing potential action
     zpass_body<T, SC, S, C, kTableCols, AX_NONE, EQ>(psi, vexp, 1, prog_index(m.prog[2 * M]),
                                                      0, m.conj, tw, nullptr, lds, blockIdx.x,

@@ -99,12 +99,18 @@ __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __res
 // of row y = by.  `psi` is one state [S][N^3]; `fz` the z factor of the
 // kinetic set (AX_KIN only).
 //
-// EQ (FP64, S = 2, 3): `vexp` is instead the one compact eigen-form table
-// (eig_slots(S) slots per point, same tile layout) and `taus` the tau of
-// each coefficient; a potential action is psi <- R exp(-i tau lam) R^T psi
-// in registers, and the two actions at a step boundary share one load, one
-// pair of rotations and one phase (psi <- R exp(-i (tau_1 + tau_2) lam) R^T
-// psi: the same operator, rounded once).
+// Table entries are cx<T>, in FP32 the pairs (rounded, residue) of
+// Split<float> (each entry's index doubled).
+//
+// EQ (S = 2, 3): `vexp` is instead the one compact eigen-form table, FP64 in
+// both precisions (eig_slots(S) complex double slots per point, same tile
+// layout), and `taus` the tau of each coefficient; a potential action is
+// psi <- R exp(-i tau lam) R^T psi in registers, and the two actions at a
+// step boundary share one load, one pair of rotations and one phase
+// (psi <- R exp(-i (tau_1 + tau_2) lam) R^T psi: the same operator, rounded
+// once).  The action is computed in FP64 in both precisions: an FP32 state
+// is widened, rotated and phased in FP64 and rounded once, so the FP32 form
+// carries no rounded potential operator.
 template <typename T, int S>
 __device__ __forceinline__ void rotation_from_slots(const cx<T>* q, T (&R)[S][S]) {
   if constexpr (S == 2) {
@@ -129,12 +135,12 @@ __device__ __forceinline__ void rotation_from_slots(const cx<T>* q, T (&R)[S][S]
 
 template <typename T, class SC, int S, int C, int TC, int AX, bool EQ = false>
 __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
-                                           const cx<T>* __restrict__ vexp, int nv, int iv0,
+                                           const void* __restrict__ vexp, int nv, int iv0,
                                            int iv1, int conj, const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fz, cx<T>* lds, int bx,
                                            int by, const double* __restrict__ taus = nullptr) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
-  static_assert(!EQ || (sizeof(T) == 8 && S >= 2), "eigen form: FP64, two or three surfaces");
+  static_assert(!EQ || S >= 2, "eigen form: two or three surfaces");
   constexpr int N = SC::N, E = SC::E, NE = EQ ? eig_slots(S) : S * (S + 1) / 2;
   const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
@@ -157,57 +163,58 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
   const T csign = conj ? (T)-1 : (T)1;
   if constexpr (EQ) {
     if (nv >= 1) {
-      const auto rq = rsrc(vexp + tbase, tile);
+      const auto rq = rsrc((const cx<double>*)vexp + tbase, tile);
       // two actions at a step boundary: exp(-i tau_2 lam) exp(-i tau_1 lam)
       // = exp(-i (tau_1 + tau_2) lam), one phase per eigenvalue
-      const double tab = csign * (taus[iv0] + (nv >= 2 ? taus[iv1] : 0.0));
+      const double tab = (double)csign * (taus[iv0] + (nv >= 2 ? taus[iv1] : 0.0));
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
-        cx<T> sl[NE];
+        cx<double> sl[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) sl[e] = ld<T>(rq, pt + e * TC);
-        T R[S][S];
-        rotation_from_slots<T, S>(sl, R);
-        const T lam[3] = {sl[S == 3 ? 2 : 1].re, sl[S == 3 ? 2 : 1].im,
-                          S == 3 ? sl[NE - 1].re : (T)0};
+        for (int e = 0; e < NE; ++e) sl[e] = ld<double>(rq, pt + e * TC);
+        double R[S][S];
+        rotation_from_slots<double, S>(sl, R);
+        const double lam[3] = {sl[S == 3 ? 2 : 1].re, sl[S == 3 ? 2 : 1].im,
+                               S == 3 ? sl[NE - 1].re : 0.0};
         // gamma = R^T psi, gamma_k *= exp(-i tau lam_k) per action, psi = R gamma
-        cx<T> g[S];
+        cx<double> g[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-          g[k] = cx<T>{(T)0, (T)0};
+          g[k] = cx<double>{0.0, 0.0};
 #pragma unroll
           for (int i = 0; i < S; ++i)
-            g[k] = cx<T>{g[k].re + R[i][k] * v[i][q].re, g[k].im + R[i][k] * v[i][q].im};
+            g[k] = cx<double>{g[k].re + R[i][k] * (double)v[i][q].re,
+                              g[k].im + R[i][k] * (double)v[i][q].im};
           double sn, cs;
           sincos_phase(tab * lam[k], &sn, &cs);
-          g[k] = cmul(g[k], cx<T>{cs, -sn});
+          g[k] = cmul(g[k], cx<double>{cs, -sn});
         }
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-          cx<T> a = {(T)0, (T)0};
+          cx<double> a = {0.0, 0.0};
 #pragma unroll
-          for (int k = 0; k < S; ++k) a = cx<T>{a.re + R[i][k] * g[k].re, a.im + R[i][k] * g[k].im};
-          v[i][q] = a;
+          for (int k = 0; k < S; ++k)
+            a = cx<double>{a.re + R[i][k] * g[k].re, a.im + R[i][k] * g[k].im};
+          v[i][q] = cx<T>{(T)a.re, (T)a.im};
         }
       }
     }
   } else {
+    constexpr int REP = Split<T>::rep;
     auto vact = [&](int iv) {
-      const auto ru = rsrc(vexp + (size_t)iv * NE * npts + tbase, tile);
+      const auto ru = rsrc((const cx<T>*)vexp + ((size_t)iv * NE * npts + tbase) * REP,
+                           tile * REP);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
-        cx<T> u[NE];
+        Fac<T> u[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-          u[e] = ld<T>(ru, pt + e * TC);
-          u[e].im *= csign;
-        }
+        for (int e = 0; e < NE; ++e) u[e] = ldfac<T>(ru, pt + e * TC, csign);
         cx<T> w[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) w[s] = v[s][q];
-        apply_u<T, S>(w, u);
+        apply_u_fac<T, S>(w, u);
 #pragma unroll
         for (int s = 0; s < S; ++s) v[s][q] = w[s];
       }

@@ -555,19 +555,19 @@ sop_status sop_plan_create_with_allocator(const sop_plan_desc* desc, void* hip_s
 
   // device buffers
   const size_t vbytes = (size_t)NE * p->npts * sizeof(double);
-  // 3D FP64 plans of two or three surfaces store the compact eigen form of
+  // 3D plans of two or three surfaces store the compact FP64 eigen form of
   // V (one table for every coefficient) instead of one exp(-i tau V) table
-  // per unique coefficient
-  if (sop::eig_form(p->ndim, S, f64)) {
+  // per unique coefficient; FP32 tables hold (rounded, residue) pairs
+  const int rep = f64 ? 1 : 2;
+  if (sop::eig_form(p->ndim, S)) {
     p->vbound = gershgorin_bound(desc->vtable, S, p->npts);
     for (int k = 0; k < desc->nparams; ++k)
       p->dvbound.push_back(gershgorin_bound(desc->dvtables + (size_t)k * NE * p->npts, S, p->npts));
     p->eig_form = phases_fit(p, p->vbound);
   }
   const size_t tbytes = p->eig_form ? (size_t)sop::eig_slots(S) * p->npts * 2 * sizeof(double)
-                                    : vc.size() * NE * p->npts * p->csize;
+                                    : vc.size() * NE * p->npts * p->csize * rep;
   const int nax = p->ndim == 1 ? 1 : 3;
-  const int rep = f64 ? 1 : 2;  // FP32 factor blocks carry their residues
   const size_t kbytes = tc.size() * nax * p->n[0] * p->csize * rep;
   const size_t wbytes = (size_t)nax * p->n[0] * p->csize * rep;
   if (dalloc(p, &p->d_vraw, vbytes) != hipSuccess || dalloc(p, &p->d_vexp, tbytes) != hipSuccess ||
@@ -1055,7 +1055,8 @@ sop_status sop_apply_action(sop_plan* p, void* psi, int op, double coef) {
       d.hprog = {sop::prog_entry(sop::OP_V, (int)p->vtaus.size())};
     } else {
       d.eig = false;
-      if (!p->d_atab) HIPTRY(dalloc(p, &p->d_atab, (size_t)NE * p->npts * p->csize));
+      if (!p->d_atab)
+        HIPTRY(dalloc(p, &p->d_atab, (size_t)NE * p->npts * p->csize * (d.f64 ? 1 : 2)));
       HIPTRY(sop::form_vexp(d, p->d_vraw, p->d_taus + p->vtaus.size(), 1, p->tile, p->d_atab));
       d.vexp = p->d_atab;
       d.prog = p->d_prog1;
@@ -1157,7 +1158,8 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
   sop::DevView d = p->dv;
   d.graphs = nullptr;
   d.nact = 1;
-  const size_t tab = (size_t)(p->S * (p->S + 1) / 2) * p->npts * p->csize;
+  const size_t tab =
+      (size_t)(p->S * (p->S + 1) / 2) * p->npts * p->csize * (p->dtype == SOP_C128 ? 1 : 2);
   // formation bytes per potential action: V0 and D read, the table written
   const double fbytes =
       (2.0 * (p->S * (p->S + 1) / 2) * sizeof(double) +

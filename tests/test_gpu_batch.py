@@ -191,8 +191,8 @@ def test_batch_changed_steps_and_reverse_direction(torch_cuda):
 
 
 def test_batch_fp32(torch_cuda, orc):
-    """FP32 members against the FP64 oracle; same 2e-5 bar as the short
-    single-plan FP32 runs (error ~ actions x 2^-24)."""
+    """FP32 members against the FP64 oracle: measured at most 8.1e-7 (per
+    surface and element 7.7e-7); stated bounds 2e-6 and 4e-6."""
     torch = torch_cuda
     from paper_1903_04946_amd import soprop
     mix = [r for r in MIX if r[7] > 0 and r[3] == "VTV"]
@@ -204,8 +204,8 @@ def test_batch_fp32(torch_cuda, orc):
     for i, ((kind, n, S, split, comp, order, dt, k, off), m) in enumerate(zip(mix, models)):
         P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.hbar)
         ref = orc.propagate(P, m.psi0, SPLIT_ID[split], COMP_ID[comp], order, dt, k)
-        assert_parity(psis[i].cpu().numpy().astype(np.complex128), ref, 2e-5,
-                      f"batch fp32 member {i} {kind} n={n} {comp}-{order}", elem_tol=8e-5)
+        assert_parity(psis[i].cpu().numpy().astype(np.complex128), ref, 2e-6,
+                      f"batch fp32 member {i} {kind} n={n} {comp}-{order}", elem_tol=4e-6)
 
 
 def test_batch_tuning_cache(torch_cuda, tmp_path):

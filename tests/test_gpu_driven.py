@@ -107,8 +107,8 @@ def test_driven_3d_vs_oracle(torch_cuda, orc, c64):
     drive = f((np.arange(ns)[:, None] + c[None, :]) * dt)
     P = orc.Problem(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, v0, m.hbar)
     ref = orc.propagate_driven(P, d, m.psi0, 0, 1, 4, dt, ns, drive)
-    assert_parity(psi.cpu().numpy().astype(np.complex128), ref, 1e-5 if c64 else 1e-12,
-                  f"driven 3d {'FP32' if c64 else 'FP64'}", elem_tol=4e-5 if c64 else None)
+    assert_parity(psi.cpu().numpy().astype(np.complex128), ref, 2e-6 if c64 else 1e-12,
+                  f"driven 3d {'FP32' if c64 else 'FP64'}", elem_tol=4e-6 if c64 else None)
     # the ground surface stays (numerically) empty: the theta = 0 table keeps
     # couplings to it at the rounding level of lvc_vtable_theta's subtraction
     assert np.abs(psi.cpu().numpy()[0]).max() < 1e-12

@@ -269,20 +269,20 @@ def test_argument_checks(torch_cuda):
 
 # ------------------------------------------------------------------ FP32 form
 def test_fp32_1d_config1(torch_cuda, orc):
-    """complex64 state with FP64-formed tables rounded once to FP32.  The
-    rounded tables are a fixed perturbation of each step's unitary of relative
-    size ~eps32 = 6e-8, so the error grows coherently, about nsteps * eps32:
-    the stated bound after 1000 Strang steps is 1e-4."""
+    """complex64 state; tables formed in FP64 and kept as FP32 (rounded,
+    residue) pairs, the potential matvec done in FP64 with one rounding per
+    output, twiddles and kinetic factors with their residues.  What remains
+    are unbiased roundings, so the error grows like a random walk: measured
+    5.1e-6 after 1000 Strang steps, norm change -4.8e-7; stated bounds 1e-5
+    (relative L2), 2e-5 (per surface and per element) and 2e-6 (norm)."""
     torch = torch_cuda
     m = synth.two_surface_1d()
     got, plan = gpu_run(torch, m, "VTV", "strang", 2, 0.01, 1000, dtype=torch.complex64)
     ref = oracle_run(orc, m, "VTV", "strang", 2, 0.01, 1000)
-    assert_parity(got, ref, 1e-4, "fp32 1D two-surface, 1000 Strang steps", elem_tol=4e-4)
+    assert_parity(got, ref, 1e-5, "fp32 1D two-surface, 1000 Strang steps", elem_tol=2e-5)
     ob = plan.observables(torch.from_numpy(got.astype(np.complex64)).cuda())
-    # the FP32 unitaries are unitary to ~eps32 each, coherently over the
-    # 3000 actions: stated norm bound 2e-4
     print(f"[fp32] 1D two-surface, 1000 Strang steps: norm - 1 = {ob['norm'] - 1:.3e}")
-    assert abs(ob["norm"] - 1) < 2e-4
+    assert abs(ob["norm"] - 1) < 2e-6
 
 
 # ------------------------------------------------------------------ 3D
@@ -359,7 +359,7 @@ def test_3d_64_fp32(torch_cuda, orc):
     m = synth.lvc_3d(n=64)
     got, _ = gpu_run(torch, m, "VTV", "triple_jump", 8, 10.0, 2, dtype=torch.complex64)
     ref = oracle_run(orc, m, "VTV", "triple_jump", 8, 10.0, 2)
-    assert_parity(got, ref, 1e-5, "fp32 64^3 TJ-8, 2 steps", elem_tol=4e-5)
+    assert_parity(got, ref, 3e-6, "fp32 64^3 TJ-8, 2 steps", elem_tol=6e-6)
 
 
 def test_3d_64_tj8_100_steps(torch_cuda, orc):
@@ -372,7 +372,7 @@ def test_3d_64_tj8_100_steps(torch_cuda, orc):
     got, _ = gpu_run(torch, m, "VTV", "triple_jump", 8, 10.0, 100)
     assert_parity(got, ref, FP64_TOL, "64^3 TJ-8, 100 steps, FP64")
     got32, _ = gpu_run(torch, m, "VTV", "triple_jump", 8, 10.0, 100, dtype=torch.complex64)
-    assert_parity(got32, ref, 5e-5, "64^3 TJ-8, 100 steps, FP32", elem_tol=2e-4)
+    assert_parity(got32, ref, 2e-5, "64^3 TJ-8, 100 steps, FP32", elem_tol=4e-5)
 
 
 def test_fp32_error_growth_32cube_sf4(torch_cuda, orc):
@@ -388,10 +388,10 @@ def test_fp32_error_growth_32cube_sf4(torch_cuda, orc):
     m = synth.lvc_3d(n=32)
     got, plan = gpu_run(torch, m, "VTV", "suzuki", 4, 500.0 / 128, 128, dtype=torch.complex64)
     ref = oracle_run(orc, m, "VTV", "suzuki", 4, 500.0 / 128, 128)
-    err, _, _ = assert_parity(got, ref, 1e-5, "fp32 32^3 SF-4, 640 substeps", elem_tol=4e-5)
+    err, _, _ = assert_parity(got, ref, 1e-5, "fp32 32^3 SF-4, 640 substeps", elem_tol=1.5e-5)
     drift = np.linalg.norm(got) / np.linalg.norm(ref) - 1
     print(f"[fp32] 32^3 SF-4, 640 substeps: error {err:.3e}, norm change {drift:.3e}")
-    assert abs(drift) < 1e-6
+    assert abs(drift) < 2e-6
 
 
 def test_3d_reversibility(torch_cuda):
