@@ -77,6 +77,8 @@ GRIDCONV = {"gridconv_lvc3d_32to256_sf6_c128": (32, 64, 128, 256)}
 # Compositions of the trapezoidal rule (the implicit comparison integrator):
 # count independent 1D two-surface states, one workgroup each.
 TRAPS = {"trapezoid_random1d_1024_x2_tj4_c128": (1024, 512)}
+# ... and on the 3D LVC model (one state; the iteration driven from the host)
+TRAPS3 = {"trapezoid_lvc3d_32cube_x3_tj4_c128": 32}
 KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/passes_3d.hpp",
                   "paper_1903_04946_amd/csrc/kernels_1d.hip",
@@ -827,6 +829,106 @@ def run_trapezoid(a, torch, soprop):
     }
 
 
+def _trapezoid3d_vs_split(torch, soprop, m, tf=500.0, eps=1e-6):
+    """Time to a final-time error eps on the 32^3 LVC model: compositions of
+    the trapezoidal rule (Strang, TJ-4) against the split-operator Suzuki-6
+    and Strang, over halving dt, all against the split-operator reference
+    (TJ-10 at t_f/2^12; both integrators converge to the same exact
+    evolution of the grid Hamiltonian)."""
+    run = _Runner(torch, soprop, m)
+    ref, _ = run(m.psi0, "triple_jump", 10, 2**12, tf, torch.complex128, label="reference")
+    out = {}
+    for name, comp, order, trap, ks in (("trapezoid-strang", "strang", 2, True, range(6, 13)),
+                                        ("trapezoid-tj4", "triple_jump", 4, True, range(4, 11)),
+                                        ("split-strang", "strang", 2, False, range(8, 14)),
+                                        ("split-sf6", "suzuki", 6, False, range(3, 9))):
+        pts = []
+        for k in ks:
+            ns = 2**k
+            plan = soprop.Plan.from_model(m, comp=comp, order=order, dt=tf / ns)
+            psi = torch.from_numpy(m.psi0.copy()).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if trap:
+                it = plan.propagate_trapezoid(psi, ns, tol=1e-13, max_iter=100000)
+            else:
+                it = None
+                plan.propagate(psi, ns)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            err = _l2(psi.cpu().numpy(), ref, m.dV)
+            pts.append({"dt": f"t_f/2^{k}", "seconds": sec, "error": err, "iterations": it})
+            print(f"[tte3d] {name} k={k} err={err:.2e} {sec:.3f} s", file=sys.stderr, flush=True)
+            plan.close()
+            if err < eps / 10:
+                break
+        out[name] = {"runs": pts, "seconds_to_eps": _interp_time(
+            [(p["seconds"], p["error"]) for p in pts], eps)}
+    out["eps"] = eps
+    out["t_f"] = tf
+    return out
+
+
+def run_trapezoid3d(a, torch, soprop):
+    """sop_propagate_trapezoid on the 32^3 LVC model (one state, TJ-4,
+    dt = 10 a.u., solver tolerance 1e-13)."""
+    from paper_1903_04946_amd import synth
+    n = TRAPS3[a.workload]
+    m = synth.lvc_3d(n=n)
+    dt, tol = 10.0, 1e-13
+    plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=dt)
+    M = plan.info.M
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    plan.propagate_trapezoid(psi, a.warmup, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = plan.propagate_trapezoid(psi, a.steps, tol=tol)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    units = m.nsurf * m.npts * M * a.steps
+    stages = M * a.steps
+    # algorithmic bytes of one iteration (state-sized vectors of 16 B per
+    # grid point and surface): three copies of p and the three one-axis passes
+    # (each read + written), A p (reads the three terms and p, writes A p),
+    # the update of x and r (reads x, r, p, A p, writes x, r) and of p
+    # (reads r, p, writes p): 26 vectors, plus the V-table (48 B a point)
+    vec = 16.0 * m.nsurf * m.npts
+    bytes_iter = 26 * vec + 48.0 * m.npts
+    it_s = sec / max(iters + stages, 1)
+    achieved = bytes_iter / it_s / 1e9
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        g = O.gammas(1, 4)
+        t1 = time.perf_counter()
+        O.propagate_trapezoid_krylov(m.n, m.lo, m.hi, m.nsurf, m.inv_mass, m.vtable, m.psi0, g,
+                                     dt, 1, m.hbar, tol=1e-13)
+        csec = time.perf_counter() - t1
+        cpu = {"value": m.nsurf * m.npts * M / csec, "unit": UNIT, "host": _host_cpu(),
+               "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"1 step (3 stages) of the oracle's matrix-free trapezoidal rule "
+                         f"(GMRES, numpy FFT; {csec:.2f} s; numpy's threads)"}
+    tte = _trapezoid3d_vs_split(torch, soprop, synth.lvc_3d(n=32)) if a.time_to_error else None
+    return {
+        "metric": METRIC, "value": units / sec, "unit": UNIT, "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * sec / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "ndim": 3, "grid": [n] * 3, "nsurf": m.nsurf,
+                   "integrator": "trapezoidal rule", "composition": "triple_jump", "order": 4,
+                   "substeps_per_step": M, "dt": dt, "solver_tol": tol},
+        "roofline": {"bound": "hbm", "kernel": "one COCG iteration (12 launches, 2 host syncs)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_iteration": bytes_iter, "us_per_iteration": 1e6 * it_s},
+        "time_to_error": tte,
+        "solver": {"iterations": iters, "iterations_per_stage": iters / stages},
+        "cpu_baseline": cpu,
+        "checks": {"norm_after": plan.observables(psi)["norm"], "wall_s_timed": sec},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+
+
 def run_gridconv(a, torch, soprop):
     """The grid-convergence study (paper_1903_04946_amd.gridconv), timed."""
     from paper_1903_04946_amd import gridconv
@@ -1071,7 +1173,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(ENSEMBLES) + sorted(ADJOINTS)
-                    + sorted(DRIVEN) + sorted(INTERPS) + sorted(TRAPS) + sorted(GRIDCONV))
+                    + sorted(DRIVEN) + sorted(INTERPS) + sorted(TRAPS) + sorted(TRAPS3)
+                    + sorted(GRIDCONV))
     ap.add_argument("--fd-check", action="store_true",
                     help="adjoint workloads: also central finite differences (h = 1e-5 eV)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1117,6 +1220,9 @@ def main(argv=None) -> int:
         return 0
     if a.workload in TRAPS:
         print(json.dumps(run_trapezoid(a, torch, soprop)))
+        return 0
+    if a.workload in TRAPS3:
+        print(json.dumps(run_trapezoid3d(a, torch, soprop)))
         return 0
     if a.workload in GRIDCONV:
         print(json.dumps(run_gridconv(a, torch, soprop)))

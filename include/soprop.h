@@ -364,14 +364,18 @@ sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
  * 1 + i tau H, started from psi, stopped when the residual's norm falls to
  * tol times the right-hand side's (the error of psi' is then at most that
  * residual), at most max_iter iterations per stage.
- * 1D SOP_C128 plans of 512..8192 points (SOP_ERR_UNSUPPORTED otherwise);
- * VT/TV plans have no composition (SOP_ERR_INVALID).  psi: device
- * [count][S][N], count (1..65535) independent states, one workgroup each,
- * advanced in place by nsteps steps.  *iterations (may be NULL) receives the
- * total iteration count over all states.  Synchronises the plan's stream;
+ * SOP_C128 plans only (SOP_ERR_UNSUPPORTED otherwise): 1D of 512..8192
+ * points, each state in one workgroup for the whole call; or 3D, one state
+ * after another, the iteration driven from the host with H u = the three
+ * one-axis kinetic terms F_d^-1 T_d F_d u (the propagator's pass kernels)
+ * plus V u, every reduction in a fixed order (two synchronisations per
+ * iteration).  VT/TV plans have no composition (SOP_ERR_INVALID).  psi:
+ * device [count][S][grid], count (1..65535) independent states, advanced in
+ * place by nsteps steps.  *iterations (may be NULL) receives the total
+ * iteration count over all states.  Synchronises the plan's stream;
  * SOP_ERR_STATE if a stage did not reach tol (psi then holds the last
- * iterate).  Keeps a workspace of count S N complex values (grown on
- * demand) in the plan. */
+ * iterate).  Keeps a workspace (1D: count S N complex values; 3D: six
+ * state-sized vectors) grown on demand in the plan. */
 sop_status sop_propagate_trapezoid(sop_plan* plan, void* psi, int count, int64_t nsteps,
                                    double tol, int max_iter, int64_t* iterations);
 
@@ -381,11 +385,12 @@ sop_status sop_propagate_trapezoid(sop_plan* plan, void* psi, int count, int64_t
  * device array of SOP_TRAP_SCRATCH_BYTES (32 MiB) that every GPU the library
  * runs on holds until the process ends, instead of plan memory grown on
  * demand.  The call allocates nothing (no hipMalloc, hipFree or allocating
- * library routine); it needs count * nsurf * N * 16 bytes of residuals plus
- * 24 bytes of statistics per state (rounded up to 256) and 8 bytes per
- * composition stage, and returns SOP_ERR_INVALID, before any device work, if
- * that exceeds the array (e.g. at most 1023 states of 1024 points and two
- * surfaces).  Every call on one GPU shares that GPU's array: calls that
+ * library routine); it needs (1D) count * nsurf * N * 16 bytes of residuals
+ * plus 24 bytes of statistics per state (rounded up to 256) and 8 bytes per
+ * composition stage, or (3D) six vectors of nsurf * npts * 16 bytes plus
+ * about 33 KB, and returns SOP_ERR_INVALID, before any device work, if that
+ * exceeds the array (e.g. at most 1023 states of 1024 points and two
+ * surfaces; 3D grids up to 32^3 x 3).  Every call on one GPU shares that GPU's array: calls that
  * overlap on one GPU (other streams, other host threads) race and must be
  * serialised by the caller.  Nothing in the array needs clearing between
  * calls.  Synchronises the plan's stream. */

@@ -308,6 +308,65 @@ def propagate_trapezoid(H: np.ndarray, psi: np.ndarray, gammas, dt: float, nstep
     return x.reshape(shape)
 
 
+def apply_hamiltonian(n, lo, hi, nsurf, inv_mass, vtable, u, hbar: float = 1.0) -> np.ndarray:
+    """H u on a periodic grid of any dimension (Eq. diab_mol_ham with the
+    Fourier grid of Sec. "Dynamic Fourier method"): the kinetic energy as
+    sum_d F_d^-1 diag(T_d) F_d along each axis d (numpy's FFT), T_d(k) =
+    (hbar kappa_k)^2 inv_mass_d / 2, kappa_k = 2 pi k / L_d over the signed
+    frequencies (Nyquist as +n/2), plus the S x S matvec with the real
+    symmetric V(x).  u: [S][n_0]..[n_{D-1}]."""
+    n = [int(v) for v in n]
+    S = int(nsurf)
+    u = np.asarray(u, dtype=np.complex128).reshape(S, *n)
+    out = np.zeros_like(u)
+    for d in range(len(n)):
+        L = float(hi[d]) - float(lo[d])
+        m = np.arange(n[d])
+        ks = np.where(m <= n[d] // 2, m, m - n[d]).astype(float)
+        Tk = (hbar * 2 * np.pi * ks / L) ** 2 * float(inv_mass[d]) / 2
+        shape = [1] * (len(n) + 1)
+        shape[d + 1] = n[d]
+        out += np.fft.ifft(Tk.reshape(shape) * np.fft.fft(u, axis=d + 1), axis=d + 1)
+    vt = np.asarray(vtable, dtype=float).reshape(-1, *n)
+    pk = 0
+    for i in range(S):
+        for j in range(i, S):
+            out[i] += vt[pk] * u[j]
+            if j != i:
+                out[j] += vt[pk] * u[i]
+            pk += 1
+    return out
+
+
+def propagate_trapezoid_krylov(n, lo, hi, nsurf, inv_mass, vtable, psi, gammas, dt: float,
+                               nsteps: int, hbar: float = 1.0, tol: float = 1e-15) -> np.ndarray:
+    """The trapezoidal-rule composition of propagate_trapezoid on grids too
+    large for dense matrices: every stage solves (1 + i tau H) x =
+    (1 - i tau H) psi, tau = g dt / (2 hbar), with H applied matrix-free
+    (apply_hamiltonian) by restarted GMRES (scipy) to a relative residual
+    tol, started from psi.  Since |1 + i tau lambda| >= 1 for real lambda,
+    the error of x is at most the residual."""
+    import scipy.sparse.linalg as sla
+    shape = np.shape(psi)
+    x = np.ascontiguousarray(psi, dtype=np.complex128).ravel().copy()
+    N = x.size
+
+    def H(u):
+        return apply_hamiltonian(n, lo, hi, nsurf, inv_mass, vtable, u, hbar).ravel()
+
+    for _ in range(int(nsteps)):
+        for g in np.ravel(gammas):
+            tau = float(g) * dt / (2 * hbar)
+            A = sla.LinearOperator((N, N), matvec=lambda u, t=tau: u + 1j * t * H(u),
+                                   dtype=np.complex128)
+            b = x - 1j * tau * H(x)
+            y, info = sla.gmres(A, b, x0=x, rtol=tol, atol=0.0, restart=60, maxiter=400)
+            if info != 0:
+                raise RuntimeError(f"oracle GMRES did not reach {tol} (info {info})")
+            x = y
+    return x.reshape(shape)
+
+
 def set_threads(n: int) -> int:
     """Threads of the oracle's OpenMP loops; returns the count now in use."""
     if lib().orc_set_threads(int(n)) != 0:

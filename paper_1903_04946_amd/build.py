@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsoprop.so")
 SOURCES = ["kernels_3d.hip", "kernels_batch3d.hip", "kernels_batch1d.hip", "kernels_1d.hip",
-           "kernels_aux.hip", "kernels_interp.hip", "kernels_trap.hip", "plan.cpp", "batch.cpp"]
+           "kernels_aux.hip", "kernels_interp.hip", "kernels_trap.hip", "kernels_trap3d.hip",
+           "plan.cpp", "batch.cpp"]
 HEADERS = ["fft_core.hpp", "internal.hpp", "body_1d.hpp", "passes_3d.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++20", "-O3", "--offload-arch=gfx950", "-fPIC",

@@ -203,6 +203,37 @@ struct TrapArgs {
 };
 bool k1d_trap_supported(int n, int S);
 hipError_t k1d_trapezoid(const DevView& d, const TrapArgs& g);
+// kernels_trap3d.hip: the trapezoidal rule on 3D FP64 plans (one state at a
+// time).  x is the iterate (the state itself), r the residual, p the search
+// direction, ap = A p; qz, qy, qx the three one-axis kinetic terms of H u
+// (computed by the pass kernels, k3d_axis_kinetic, on copies of u);
+// partials [kReduceBlocks][4] and sums [4] the reductions.
+struct Trap3Bufs {
+  void* x = nullptr;
+  void* r = nullptr;
+  void* p = nullptr;
+  void* ap = nullptr;
+  void* qz = nullptr;
+  void* qy = nullptr;
+  void* qx = nullptr;
+  double* partials = nullptr;
+  double* sums = nullptr;
+};
+// From x: r = p = -2 i tau H x; sums = {|b|^2, |r|^2, Re r^T r, Im r^T r}.
+hipError_t t3_init(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
+                   hipStream_t st);
+// ap = p + i tau H p; sums = {Re p^T ap, Im p^T ap}.
+hipError_t t3_ap(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
+                 hipStream_t st);
+// x += alpha p, r -= alpha ap over n = S npts values; sums = {|r|^2, r^T r}.
+hipError_t t3_update(const Trap3Bufs& b, int64_t n, double are, double aim, hipStream_t st);
+// p = r + beta p.
+hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, double bre, double bim, hipStream_t st);
+// One one-axis pass (axis 0 = slowest ("z"), 1, 2) of every surface of psi:
+// F_a^-1 f_a F_a with the factor block of d.kin's set 0 for that axis (the
+// propagator's pass kernels; no potential action).
+hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis);
+
 // The allocation-free trapezoid call's static device scratch: its size, and
 // its device address on the GPU of `stream` (NULL: the current device),
 // looked up once per device and kept.

@@ -678,6 +678,20 @@ hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) 
   });
 }
 
+hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis) {
+  if (d.timer) d.timer->break_chain();
+  return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() -> hipError_t {
+    using P = Passes<T, SC, S>;
+    cx<T>* v = (cx<T>*)psi;
+    switch (axis) {
+      case 0: return P::template z<AX_KIN>(d, v, 0, 0, 0, 0, 0);
+      case 1: return P::template ypass<AX_KIN>(d, v, 0, 0);
+      case 2: return P::template xpass<AX_KIN>(d, v, 0, 0);
+      default: return hipErrorInvalidValue;
+    }
+  });
+}
+
 bool k3d_adjoint_supported(int n, int S, bool f64) {
   return f64 && S >= 1 && S <= 3 && (n == 32 || n == 64 || n == 128 || n == 256);
 }

@@ -783,11 +783,16 @@ sop_status sop_distance(sop_plan* p, const void* psi, const void* phi, double* o
 
 namespace {
 
-// Device workspace of the trapezoidal rule: count S N complex residuals, the
-// per-state statistics (three int64 each) and the stage coefficients.
+// Device workspace of the trapezoidal rule.  1D: count S N complex
+// residuals, the per-state statistics (three int64 each) and the stage
+// coefficients.  3D (one state at a time): six state-sized vectors (r, p,
+// A p and the three one-axis kinetic terms), the reduction partials and
+// sums, and the factor block T_d(k)/n_d of the three axes.
 struct TrapLayout {
   size_t vec = 0, sbytes = 0, need = 0;
   int nst = 0;
+  bool three_d = false;
+  size_t one = 0;  // 3D: bytes of one state-sized vector
 };
 
 sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nsteps, double tol,
@@ -797,15 +802,129 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
   if (nsteps < 0) return fail(SOP_ERR_INVALID, "nsteps must be >= 0");
   if (!(tol > 0) || !(tol < 1)) return fail(SOP_ERR_INVALID, "tol must be in (0, 1)");
   if (max_iter < 1) return fail(SOP_ERR_INVALID, "max_iter must be >= 1");
-  if (p->ndim != 1 || p->dtype != SOP_C128 || !sop::k1d_trap_supported(p->n[0], p->S))
+  if (p->dtype != SOP_C128 ||
+      !(p->ndim == 3 || (p->ndim == 1 && sop::k1d_trap_supported(p->n[0], p->S))))
     return fail(SOP_ERR_UNSUPPORTED,
-                "the trapezoidal rule runs on 1D SOP_C128 plans of 512..8192 points");
+                "the trapezoidal rule runs on SOP_C128 plans: 1D of 512..8192 points, or 3D");
   if (p->seq.g.empty())
     return fail(SOP_ERR_INVALID, "the plan's splitting has no composition (VT/TV)");
   lay->nst = (int)p->seq.g.size();
+  if (p->ndim == 3) {
+    lay->three_d = true;
+    lay->one = ((size_t)p->S * p->npts * sizeof(double2) + 255) / 256 * 256;
+    lay->need = 6 * lay->one + ((size_t)sop::kReduceBlocks * 4 + 4) * sizeof(double) +
+                (size_t)3 * p->n[0] * sizeof(double2);
+    return SOP_OK;
+  }
   lay->vec = (size_t)count * p->S * p->n[0] * sizeof(double2);
   lay->sbytes = ((size_t)count * 3 * sizeof(long long) + 255) / 256 * 256;
   lay->need = lay->vec + lay->sbytes + (size_t)lay->nst * sizeof(double);
+  return SOP_OK;
+}
+
+// The trapezoidal rule on a 3D plan: for every state and stage, conjugate
+// orthogonal CG on (1 + i tau H) x = (1 - i tau H) psi started from x = psi,
+// H u = sum_d F_d^-1 T_d(k) F_d u + V u, the kinetic terms computed by the
+// propagator's one-axis passes on copies of u.  The host runs the
+// iteration; every device reduction is in a fixed order.  Synchronises.
+sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double tol,
+                      int max_iter, char* base, const TrapLayout& lay, int64_t* iterations) {
+  const DevView& d = p->dv;
+  hipStream_t st = d.stream;
+  const int S = p->S, n = p->n[0];
+  const int64_t npts = p->npts, nall = (int64_t)S * npts;
+  const size_t one = lay.one;
+  sop::Trap3Bufs b;
+  b.r = base;
+  b.p = base + one;
+  b.ap = base + 2 * one;
+  b.qz = base + 3 * one;
+  b.qy = base + 4 * one;
+  b.qx = base + 5 * one;
+  b.partials = (double*)(base + 6 * one);
+  b.sums = b.partials + (size_t)sop::kReduceBlocks * 4;
+  double2* hfac = (double2*)(b.sums + 4);
+  // T_d(k) / n_d on the signed frequencies of each axis (the 1/n_d of the
+  // unnormalised inverse transform folded in, as in the kinetic factors)
+  std::vector<double2> hf((size_t)3 * n);
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < n; ++k) {
+      const int kk = k < n / 2 ? k : k - n;
+      const ld kap = kTwoPi * (ld)kk / ((ld)p->n[a] * (ld)p->dx[a]);
+      hf[(size_t)a * n + k] = {(double)((ld)p->hbar * p->hbar * kap * kap *
+                                        (ld)p->inv_mass[a] / 2.0L / (ld)p->n[a]),
+                               0.0};
+    }
+  HIPTRY(hipMemcpyAsync(hfac, hf.data(), hf.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  DevView dh = d;
+  dh.kin = hfac;
+  dh.kin_stride = n;
+  dh.count = 1;
+  dh.graphs = nullptr;
+  const size_t bytes = (size_t)nall * sizeof(double2);
+  // the three one-axis kinetic terms of H u
+  auto kinetic = [&](const void* u) -> sop_status {
+    void* q[3] = {b.qz, b.qy, b.qx};
+    for (int a = 0; a < 3; ++a) {
+      HIPTRY(hipMemcpyAsync(q[a], u, bytes, hipMemcpyDeviceToDevice, st));
+      HIPTRY(sop::k3d_axis_kinetic(dh, q[a], a));
+    }
+    return SOP_OK;
+  };
+  double sums[4];
+  auto read = [&](int nv) -> sop_status {
+    HIPTRY(hipMemcpyAsync(sums, b.sums, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return SOP_OK;
+  };
+  int64_t total = 0, failed = 0;
+  sop_status sts;
+  for (int c = 0; c < count; ++c) {
+    b.x = (char*)psi + (size_t)c * bytes;
+    for (int64_t step = 0; step < nsteps; ++step)
+      for (int j = 0; j < lay.nst; ++j) {
+        const double tau = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
+        if ((sts = kinetic(b.x)) != SOP_OK) return sts;
+        HIPTRY(sop::t3_init(b, S, p->d_vraw, npts, tau, st));
+        if ((sts = read(4)) != SOP_OK) return sts;
+        const double bb = sums[0];
+        double rr = sums[1];
+        double rre = sums[2], rim = sums[3];
+        const double tol2 = tol * tol;
+        int it = 0;
+        bool ok = rr <= tol2 * bb;
+        while (!ok && it < max_iter) {
+          if ((sts = kinetic(b.p)) != SOP_OK) return sts;
+          HIPTRY(sop::t3_ap(b, S, p->d_vraw, npts, tau, st));
+          if ((sts = read(2)) != SOP_OK) return sts;
+          const double mre = sums[0], mim = sums[1];
+          const double mabs = std::fabs(mre) + std::fabs(mim);
+          if (!(mabs > 0.0) || !(mabs < 1e300)) break;  // breakdown: not converged
+          const double den = mre * mre + mim * mim;
+          const double are = (rre * mre + rim * mim) / den, aim = (rim * mre - rre * mim) / den;
+          HIPTRY(sop::t3_update(b, nall, are, aim, st));
+          if ((sts = read(3)) != SOP_OK) return sts;
+          ++it;
+          rr = sums[0];
+          ok = rr <= tol2 * bb;
+          if (!ok) {
+            const double nre = sums[1], nim = sums[2];
+            const double dd = rre * rre + rim * rim;
+            const double bre = (nre * rre + nim * rim) / dd, bim = (nim * rre - nre * rim) / dd;
+            rre = nre;
+            rim = nim;
+            HIPTRY(sop::t3_pupdate(b, nall, bre, bim, st));
+          }
+        }
+        total += it;
+        if (!ok) ++failed;
+      }
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  if (iterations) *iterations = total;
+  if (failed > 0)
+    return fail(SOP_ERR_STATE, std::to_string(failed) + " of the linear solves did not reach tol in " +
+                                   std::to_string(max_iter) + " iterations");
   return SOP_OK;
 }
 
@@ -814,6 +933,7 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
 // written before it is read).  Synchronises the plan's stream.
 sop_status trap_run(sop_plan* p, void* psi, int count, int64_t nsteps, double tol, int max_iter,
                     char* base, const TrapLayout& lay, int64_t* iterations) {
+  if (lay.three_d) return trap3d_run(p, psi, count, nsteps, tol, max_iter, base, lay, iterations);
   const int nst = lay.nst;
   std::vector<double> taus(nst);
   for (int j = 0; j < nst; ++j) taus[j] = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
