@@ -409,7 +409,7 @@ struct Passes {
   template <int AX>
   static hipError_t ypass(const DevView& d, cx<T>* psi, int tidx, int conj) {
     auto k = k3d_ypass<T, XS, C, AX>;
-    const size_t lds = (size_t)C * N * sizeof(cx<T>);
+    const size_t lds = y_lds_elems<T, N>(C) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
@@ -420,7 +420,7 @@ struct Passes {
   template <int AX>
   static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj) {
     auto k = k3d_xpass<T, XS, ROWS, AX>;
-    const size_t lds = (size_t)ROWS * (N + N / 16) * sizeof(cx<T>);
+    const size_t lds = x_lds_elems<T, N>(ROWS) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));

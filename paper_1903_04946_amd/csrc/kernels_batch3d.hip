@@ -148,7 +148,7 @@ hipError_t launch_y(int S, const BMember3* mem, int count, int64_t c, hipStream_
   if constexpr (!valid_width<SC>(C)) {
     return hipErrorInvalidValue;
   } else {
-    const size_t lds = (size_t)C * SC::N * sizeof(cx<T>);
+    const size_t lds = y_lds_elems<T, SC::N>(C) * sizeof(cx<T>);
     auto k = k3b_ypass<T, SC, C>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
@@ -165,7 +165,7 @@ hipError_t launch_x(int S, const BMember3* mem, int count, int64_t c, hipStream_
     return hipErrorInvalidValue;
   } else {
     auto k = k3b_xpass<T, SC, R>;
-    const size_t lds = (size_t)R * (SC::N + SC::N / 16) * sizeof(cx<T>);
+    const size_t lds = x_lds_elems<T, SC::N>(R) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(SC::N / R, SC::N, S * count), dim3(R * SC::TPC), lds, st, mem, S,

@@ -71,6 +71,45 @@ constexpr int kTableCols = 16;
 
 }  // namespace s3d
 
+// Complex entries of one axis block of the twiddle and factor tables (in FP32
+// the (rounded, residue) pairs of Split<float>).
+template <typename T, int N>
+constexpr int axis_block() {
+  return N * Split<T>::rep;
+}
+
+// LDS of the y-pass tiles (C columns) and of the x-pass tiles (ROWS rows):
+// the exchange area and two staged axis blocks (twiddles, factor).  The
+// z-pass reads its twiddles and factor from global memory: with the
+// potential's table reads in flight, staging them measured slower (57.2
+// against 54.8 us a pass for 128^3 x 3 FP64), while it saves 4-5% on the
+// y-, x- and plane passes.
+template <typename T, int N>
+constexpr size_t y_lds_elems(int C) {
+  return (size_t)C * N + 2 * axis_block<T, N>();
+}
+template <typename T, int N>
+constexpr size_t x_lds_elems(int ROWS) {
+  return (size_t)ROWS * (N + N / 16) + 2 * axis_block<T, N>();
+}
+
+// Copies nb axis blocks (src[b], axis_block entries each) into LDS at dst,
+// every thread of the block striding over them.  The y-, x- and plane passes
+// stage their twiddles and kinetic factors this way before loading their
+// pencils: every later read of them is an LDS read instead of a dependent
+// global load in the middle of the transform.  Every transform starts with a
+// stage that uses no twiddles, followed by an LDS exchange whose barrier
+// orders these writes before the first read.
+template <typename T, int N, int NB>
+__device__ __forceinline__ void stage_blocks(cx<T>* dst, const cx<T>* const (&src)[NB]) {
+  constexpr int A = axis_block<T, N>();
+  const int nt = (int)(blockDim.x * blockDim.y);
+  for (int i = (int)threadIdx.x; i < A; i += nt) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dst[b * A + i] = src[b][i];
+  }
+}
+
 // What a pass does along its axis after its pointwise work:
 //   AX_NONE: nothing (z-pass carrying only potential actions);
 //   AX_KIN : forward FFT -> per-axis kinetic factor -> inverse FFT;
@@ -255,13 +294,19 @@ __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
   constexpr int64_t plane = (int64_t)N * N;
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
   const LayStrided lay{col, 0, C};
+  cx<T>* const tws = lds + C * N;  // staged twiddles and y factor
+  if constexpr (AX == AX_KIN) {
+    stage_blocks<T, N, 2>(tws, {tw, fy});
+  } else {
+    stage_blocks<T, N, 1>(tws, {tw});
+  }
   cx<T> v[1][E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) * N + x);
-  fft_forward<SC, 1>(v, lds, lay, tw, t);
+  fft_forward<SC, 1>(v, lds, lay, tws, t);
   if constexpr (AX == AX_KIN) {
-    axis_phase<T, SC, 1>(v, fy, conj ? (T)-1 : (T)1, t);
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+    axis_phase<T, SC, 1>(v, tws + axis_block<T, N>(), conj ? (T)-1 : (T)1, t);
+    fft_inverse<SC, 1>(v, lds, lay, tws, t);
   }
   constexpr int ROUT = AX == AX_FWD ? SC::RL : SC::RF;
 #pragma unroll
@@ -284,13 +329,19 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
   const uint32_t yo = (uint32_t)y * N;
   const LayPadded lay{row * (N + N / 16), 0};
+  cx<T>* const tws = lds + ROWS * (N + N / 16);  // staged twiddles and x factor
+  if constexpr (AX == AX_KIN) {
+    stage_blocks<T, N, 2>(tws, {tw, fx});
+  } else {
+    stage_blocks<T, N, 1>(tws, {tw});
+  }
   cx<T> v[1][E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) + yo);
-  fft_forward<SC, 1>(v, lds, lay, tw, t);
+  fft_forward<SC, 1>(v, lds, lay, tws, t);
   if constexpr (AX == AX_KIN) {
-    axis_phase<T, SC, 1>(v, fx, conj ? (T)-1 : (T)1, t);
-    fft_inverse<SC, 1>(v, lds, lay, tw, t);
+    axis_phase<T, SC, 1>(v, tws + axis_block<T, N>(), conj ? (T)-1 : (T)1, t);
+    fft_inverse<SC, 1>(v, lds, lay, tws, t);
   }
   constexpr int ROUT = AX == AX_FWD ? SC::RL : SC::RF;
 #pragma unroll
@@ -307,7 +358,7 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
 // factors as in the separate passes, so the values are identical.
 template <typename T, class SC>
 constexpr size_t plane_lds_elems() {
-  return (size_t)SC::N * (SC::N + SC::N / 16);
+  return (size_t)SC::N * (SC::N + SC::N / 16) + 4 * axis_block<T, SC::N>();
 }
 template <typename T, class SC>
 constexpr bool plane_fits() {
@@ -327,9 +378,11 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   const int tr = lane % TPC, row = lane / TPC;  // row layout
   constexpr int64_t plane = (int64_t)N * N;
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
-  constexpr int AS = N * Split<T>::rep;  // axis stride of the twiddle and factor blocks
-  const cx<T>* twy = tw + AS;
-  const cx<T>* twx = tw + 2 * AS;
+  constexpr int AS = axis_block<T, N>();  // axis stride of the twiddle and factor blocks
+  // staged [twiddles y | twiddles x | f_y | f_x] after the plane
+  cx<T>* const twy = lds + N * P;
+  cx<T>* const twx = twy + AS;
+  stage_blocks<T, N, 4>(twy, {tw + AS, tw + 2 * AS, kin + AS, kin + 2 * AS});
   const LayStrided lcol{col, 0, N};
   const LayPadded lrow{row * P, 0};
   const T csign = conj ? (T)-1 : (T)1;
@@ -338,7 +391,7 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
 #pragma unroll
   for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(tc, q) * N + col);
   fft_forward<SC, 1>(v, lds, lcol, twy, tc);
-  axis_phase<T, SC, 1>(v, kin + AS, csign, tc);
+  axis_phase<T, SC, 1>(v, twy + 2 * AS, csign, tc);
   fft_inverse<SC, 1>(v, lds, lcol, twy, tc);
   // columns -> rows
 #pragma unroll
@@ -349,7 +402,7 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   __syncthreads();
   // x round trip (rows)
   fft_forward<SC, 1>(v, lds, lrow, twx, tr);
-  axis_phase<T, SC, 1>(v, kin + 2 * AS, csign, tr);
+  axis_phase<T, SC, 1>(v, twy + 3 * AS, csign, tr);
   fft_inverse<SC, 1>(v, lds, lrow, twx, tr);
 #pragma unroll
   for (int q = 0; q < E; ++q) st(base, row * N + own_idx<N, E, SC::RF>(tr, q), v[0][q]);
