@@ -1079,28 +1079,35 @@ def run_ensemble(a, torch, soprop):
     ns = [e["nsteps"] for e in man]
     Ms = [p.info.M for p in plans]
     units = sum(m.nsurf * m.npts * M * k for m, M, k in zip(models, Ms, ns))
+    queue = a.queue
     t0 = time.perf_counter()
     batch = soprop.Batch(plans)
+    batch.set_queue(queue)
     create_s = time.perf_counter() - t0
     psis = [torch.from_numpy(m.psi0).to(dtype).cuda() for m in models]
     t0 = time.perf_counter()
     ms = _time_batch(torch, batch, psis, ns, a.steps, a.warmup)
     wall = time.perf_counter() - t0
+    batch.check()
     desc = batch.describe()
-    # the 1D members alone and the 3D members alone
+    # the 1D members alone and the 3D members alone (these also in the other
+    # 3D mode, for comparison)
     parts = {}
-    for kind in ("1d", "3d"):
-        idx = [i for i, e in enumerate(man) if e["kind"] == kind]
+    for kind in ("1d", "3d", "3d_other_mode"):
+        idx = [i for i, e in enumerate(man) if e["kind"] == kind[:2]]
         sub = soprop.Batch([plans[i] for i in idx])
+        sub.set_queue(queue if kind != "3d_other_mode" else not queue)
         sp = [psis[i] for i in idx]
         parts[kind] = {"members": len(idx),
                        "ms": _time_batch(torch, sub, sp, [ns[i] for i in idx], a.steps, 1),
                        "units": sum(models[i].nsurf * models[i].npts * Ms[i] * ns[i]
                                     for i in idx)}
+        sub.check()
         sub.close()
-    # algorithmic HBM bytes of the 3D lockstep passes: every pass reads and
-    # writes the state (a z-pass and a plane pass per cycle, or a z-, y- and
-    # x-pass, plus the closing z-pass); each potential action reads one table
+    parts["3d_other_mode"]["mode"] = "lockstep" if queue else "work queue"
+    # algorithmic HBM bytes of the 3D passes: every pass reads and writes the
+    # state (a z-pass and a plane pass per cycle, or a z-, y- and x-pass, plus
+    # the closing z-pass); each potential action reads one table
     plane = {g["n"]: g.get("plane", False) for g in desc["groups"]}
     b3 = 0.0
     for i, e in enumerate(man):
@@ -1147,18 +1154,22 @@ def run_ensemble(a, torch, soprop):
         "config": {"workload": a.workload, "members": len(man), "grids": counts,
                    "t_final": 0.5, "dt_range": [0.005, 0.05], "orders": [2, 4, 6, 8],
                    "substep_units_per_call": units, "state_dtype": dts},
-        "roofline": {"bound": "hbm", "kernel": "3d lockstep passes (all kinds)",
+        "roofline": {"bound": "hbm", "kernel": "3d work-queue launch (z, y, x tiles)" if queue
+                     else "3d lockstep passes (all kinds)",
                      "achieved": ach3, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach3 / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_call": b3},
         "parts": {k: {"members": v["members"], "ms_per_call": v["ms"],
-                      "value": v["units"] / (v["ms"] / 1e3)} for k, v in parts.items()},
+                      "value": v["units"] / (v["ms"] / 1e3)}
+                  | ({"mode": v["mode"]} if "mode" in v else {}) for k, v in parts.items()},
         "batch": {"create_s": create_s, "graph": desc["graph"],
                   "graph_nodes": desc["graph_nodes"], "branches": desc["branches"],
                   "families": [{k: f[k] for k in ("n", "S", "variant", "schedule", "tuned_ms")}
                                | {"members": len(f["members"])} for f in desc["families"]],
-                  "groups": [{k: g[k] for k in ("n", "S", "z_cols", "y_cols", "x_rows",
-                                                "tuned_ms", "max_cycles", "chains")}
+                  "groups": [{k: g[k] for k in ("n", "S", "queue", "rounds", "tickets",
+                                                "queue_grid", "max_cycles")}
+                             | ({} if queue else {k: g[k] for k in ("z_cols", "y_cols", "x_rows",
+                                                                    "tuned_ms", "chains")})
                              | {"members": len(g["members"])} for g in desc["groups"]]},
         "cpu_baseline": cpu,
         "checks": {"norm_max_dev": max(abs(x - 1) for x in norms), "wall_s_timed": wall}
@@ -1183,6 +1194,9 @@ def main(argv=None) -> int:
                          "minutes); without it the default workload runs the trimmed 3D "
                          "sweeps")
     ap.add_argument("--no-time-to-error", action="store_true")
+    ap.add_argument("--queue", action="store_true",
+                    help="ensemble: run the 3D groups as one work-queue launch per group "
+                         "instead of lockstep pass launches")
     ap.add_argument("--no-mall-check", action="store_true",
                     help="default workload: skip the 256^3 z-pass figure beside the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -349,8 +349,10 @@ sop_status sop_adjoint(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int
  * 0 launches every pass eagerly.  SOP_OPT_PLANE_PASS: on 3D grids whose xy
  * plane fits in LDS (n <= 64 in FP64, n <= 128 in FP32) the y- and x-passes
  * of a kinetic action run as one plane pass; default 1 for n <= 64, 0 for
- * larger grids.  Every setting gives bitwise identical results. */
-enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2 };
+ * larger grids.  Every setting gives bitwise identical results.
+ * SOP_OPT_QUEUE and SOP_OPT_QUEUE_SPIN are options of batches only
+ * (sop_batch_set_option); a plan refuses them. */
+enum { SOP_OPT_GRAPHS = 1, SOP_OPT_PLANE_PASS = 2, SOP_OPT_QUEUE = 3, SOP_OPT_QUEUE_SPIN = 4 };
 sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
 
 /* Compositions of the trapezoidal rule (the implicit, unitary and
@@ -439,9 +441,18 @@ sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* 
  * launch per call.  Members are grouped by the kernel that runs them
  * together: 1D members of one (grid length, surfaces, precision) family run
  * in one persistent launch, one workgroup per member for its whole run;
- * 3D members on 32^3, 48^3 or 64^3 grids with a VTV program run in lockstep
- * passes shared by every member of one (n, surfaces, precision) group, each
- * member taking its own tables, coefficients and step count; any other
+ * 3D members on 32^3, 48^3 or 64^3 grids with a VTV program form one
+ * (n, surfaces, precision) group each, run as lockstep pass launches (one
+ * launch per pass and cycle over the members still running, each member
+ * with its own tables, coefficients and step count; the members cut into
+ * chains of similar cycle counts on separate branches) or, with
+ * SOP_OPT_QUEUE, as one persistent work-queue launch per group: its
+ * workgroups (four waves each, about occupancy x compute units of them)
+ * take items of four z-, y- or x-pass tiles of one member in an order fixed
+ * on the host (pass by pass, the longest-running members first), and an
+ * item starts once its member's counter of finished items shows the
+ * member's previous pass complete (Sec. "Dynamic Fourier method": each pass
+ * transforms whole pencils of the state the previous pass wrote); any other
  * member runs its own plan's executor in a branch of the same graph.  The
  * per-member arithmetic is that of sop_propagate (3D members: bitwise the
  * same result; 1D members: the same DFTs, possibly in another radix order,
@@ -466,8 +477,22 @@ sop_status sop_timing_read(sop_plan* plan, double* ms, int64_t* counts, double* 
  * Runs longer than 200000 kernel launches are enqueued without a graph.
  *
  * sop_batch_set_option(SOP_OPT_GRAPHS, 0) enqueues the branches directly;
- * SOP_OPT_PLANE_PASS 0 keeps separate y- and x-passes in the lockstep groups
- * (same results either way).
+ * SOP_OPT_QUEUE 1 runs the 3D groups as work-queue launches (default 0:
+ * lockstep launches, which measure faster on the ensembles tried: every
+ * claim and completion of a queue item is an atomic on one address and
+ * every item pays an L2 write-back and invalidation to make its stores
+ * visible across the chip's L2 caches); SOP_OPT_PLANE_PASS 0 keeps separate
+ * y- and x-passes in the lockstep launches (the queue always runs y- and
+ * x-passes); SOP_OPT_QUEUE_SPIN (value >= 1, default 2^21) bounds the polls
+ * of one wait in a queue launch.  Every setting gives the same results: 3D
+ * members bitwise those of sop_propagate.
+ *
+ * sop_batch_check synchronises the batch's stream and returns
+ * SOP_ERR_STATE if a queue launch since the last check ran a wait out of
+ * polls (every workgroup then leaves and the members' states are left
+ * part-propagated; a wait normally lasts microseconds, so only a fault
+ * elsewhere or a tiny SOP_OPT_QUEUE_SPIN makes one run out), SOP_OK
+ * otherwise.
  *
  * sop_batch_describe writes a NUL-terminated JSON description (families,
  * groups, chosen variants, tuning times in ms, branch count, whether the
@@ -480,6 +505,7 @@ sop_status sop_batch_destroy(sop_batch* batch);
 sop_status sop_batch_propagate(sop_batch* batch, void* const* psi_devs, const int64_t* nsteps,
                                int direction);
 sop_status sop_batch_set_option(sop_batch* batch, int option, int value);
+sop_status sop_batch_check(sop_batch* batch);
 sop_status sop_batch_describe(const sop_batch* batch, char* buf, size_t len, size_t* needed);
 
 #ifdef __cplusplus

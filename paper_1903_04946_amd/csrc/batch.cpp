@@ -86,7 +86,43 @@ struct Group3 {
   // similar counts, each launched on its own branch
   std::vector<int64_t> cycles;
   std::vector<std::pair<int, int>> chains;
+  // work-queue launch: round table (device copy and capacity in rounds),
+  // ticket count, control block
+  sop::QRound* d_rounds = nullptr;
+  size_t rounds_cap = 0;
+  int64_t nrounds = 0, tickets = 0;
+  unsigned long long* d_ctrl = nullptr;
 };
+
+// Round table of a work-queue launch (sop::QRound) over the members of a
+// group with cycle counts cyc[] in decreasing order (0: not running): z
+// rounds hold the members with c <= cycles, y and x rounds those with
+// c < cycles; tz and tyx are one member's tiles in a z and in a y or x
+// round.  Appends the sentinel round and returns the ticket count.
+int64_t build_rounds(const std::vector<int64_t>& cyc, int tz, int tyx,
+                     std::vector<sop::QRound>& out) {
+  out.clear();
+  int nz = 0;
+  while (nz < (int)cyc.size() && cyc[nz] > 0) ++nz;
+  int nyx = nz;
+  const int64_t cmax = nz > 0 ? cyc[0] : 0;
+  int64_t start = 0, need = 0;
+  auto push = [&](int64_t c, int kind, int k, int tiles) {
+    out.push_back(sop::QRound{start, need, c, kind, k});
+    start += (int64_t)k * tiles;
+    need += tiles;
+  };
+  for (int64_t c = 0; nz > 0 && c <= cmax; ++c) {
+    while (nz > 0 && cyc[nz - 1] < c) --nz;
+    push(c, sop::B3_Z, nz, tz);
+    if (c == cmax) break;
+    while (nyx > 0 && cyc[nyx - 1] <= c) --nyx;
+    push(c, sop::B3_Y, nyx, tyx);
+    push(c, sop::B3_X, nyx, tyx);
+  }
+  out.push_back(sop::QRound{start, need, cmax + 1, -1, 0});
+  return start;
+}
 
 // Steps of the pruned VTV program V T V ... T V: M = number of T actions, or
 // -1 if the program has another shape.
@@ -178,6 +214,8 @@ struct sop_batch {
   std::vector<hipEvent_t> joins;
   bool use_graphs = true;
   bool use_plane = true;
+  bool use_queue = false;            // 3D groups as one work-queue launch
+  long long spin_limit = 1LL << 21;  // polls of one queue wait
   hipGraphExec_t exec = nullptr;
   int64_t graph_nodes = 0;
   bool last_graph = false;
@@ -191,8 +229,11 @@ struct sop_batch {
     if (exec) (void)hipGraphExecDestroy(exec);
     for (auto& f : fams)
       if (f.d_mem) (void)hipFree(f.d_mem);
-    for (auto& g : groups)
+    for (auto& g : groups) {
       if (g.d_mem) (void)hipFree(g.d_mem);
+      if (g.d_rounds) (void)hipFree(g.d_rounds);
+      if (g.d_ctrl) (void)hipFree(g.d_ctrl);
+    }
     for (hipStream_t s : branches) (void)hipStreamDestroy(s);
     if (capture) (void)hipStreamDestroy(capture);
     if (fork) (void)hipEventDestroy(fork);
@@ -328,6 +369,13 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
     if (e != hipSuccess) return e;
   }
   for (Group3& g : b->groups) {
+    if (b->use_queue) {
+      if (g.tickets <= 0) continue;
+      hipError_t e = sop::k3q_launch(g.n, g.S, g.f64, g.d_mem, (int)g.members.size(),
+                                     g.d_rounds, g.tickets, g.d_ctrl, b->spin_limit, next());
+      if (e != hipSuccess) return e;
+      continue;
+    }
     for (const auto& ch : g.chains) {
       hipStream_t st = next();
       const int lo = ch.first, hi = ch.second;
@@ -388,6 +436,10 @@ hipError_t fork_join(sop_batch* b, hipStream_t origin, const std::vector<int64_t
 int64_t count_nodes(const sop_batch* b, const std::vector<int64_t>& nsteps) {
   int64_t n = (int64_t)b->fams.size();
   for (const Group3& g : b->groups) {
+    if (b->use_queue) {
+      n += 2;
+      continue;
+    }
     const int per = (b->use_plane && sop::k3b_plane(g.n, g.f64)) ? 2 : 3;
     for (const auto& ch : g.chains) n += per * g.cycles[ch.first] + 1;
   }
@@ -461,11 +513,19 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
       (void)hipGetLastError();
       return fail(SOP_ERR_NOMEM, "device allocation failed for batch descriptors");
     }
-  for (Group3& g : b->groups)
-    if (hipMalloc((void**)&g.d_mem, sizeof(BMember3) * g.members.size()) != hipSuccess) {
+  for (Group3& g : b->groups) {
+    const size_t cb = sop::q_ctrl_words((int)g.members.size()) * sizeof(unsigned long long);
+    if (hipMalloc((void**)&g.d_mem, sizeof(BMember3) * g.members.size()) != hipSuccess ||
+        hipMalloc((void**)&g.d_ctrl, cb) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SOP_ERR_NOMEM, "device allocation failed for batch descriptors");
     }
+    HIPTRY(hipMemset(g.d_ctrl, 0, cb));
+  }
+
+  // persistent grid sizes of the work-queue launches (an occupancy query,
+  // made here rather than while a propagate call is being captured)
+  for (const Group3& g : b->groups) (void)sop::k3q_grid(g.n, g.S, g.f64);
 
   // streams and events
   const int nbranch = std::max<int>(
@@ -622,6 +682,23 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
           g.chains.back().second = (int)i + 1;
       }
       HIPTRY(hipMemcpy(g.d_mem, h.data(), sizeof(BMember3) * h.size(), hipMemcpyHostToDevice));
+      std::vector<sop::QRound> rounds;
+      g.tickets = build_rounds(g.cycles, sop::k3q_tiles(sop::B3_Z, g.n, g.S, g.f64),
+                               sop::k3q_tiles(sop::B3_Y, g.n, g.S, g.f64), rounds);
+      g.nrounds = (int64_t)rounds.size() - 1;
+      if (rounds.size() > g.rounds_cap) {
+        if (g.d_rounds) (void)hipFree(g.d_rounds);
+        g.d_rounds = nullptr;
+        g.rounds_cap = 0;
+        if (hipMalloc((void**)&g.d_rounds, rounds.size() * sizeof(sop::QRound)) != hipSuccess) {
+          (void)hipGetLastError();
+          b->key_valid = false;
+          return fail(SOP_ERR_NOMEM, "device allocation failed for the work-queue rounds");
+        }
+        g.rounds_cap = rounds.size();
+      }
+      HIPTRY(hipMemcpy(g.d_rounds, rounds.data(), rounds.size() * sizeof(sop::QRound),
+                       hipMemcpyHostToDevice));
     }
     b->key_psi.assign(psi, psi + count);
     b->key_n = ns;
@@ -659,17 +736,44 @@ sop_status sop_batch_propagate(sop_batch* b, void* const* psi, const int64_t* ns
 
 sop_status sop_batch_set_option(sop_batch* b, int option, int value) {
   if (!b) return fail(SOP_ERR_INVALID, "batch is NULL");
-  if (option != SOP_OPT_GRAPHS && option != SOP_OPT_PLANE_PASS)
+  if (option != SOP_OPT_GRAPHS && option != SOP_OPT_PLANE_PASS && option != SOP_OPT_QUEUE &&
+      option != SOP_OPT_QUEUE_SPIN)
     return fail(SOP_ERR_INVALID, "unknown option");
+  if (option == SOP_OPT_QUEUE_SPIN && value < 1)
+    return fail(SOP_ERR_INVALID, "the queue's poll limit must be >= 1");
   HIPTRY(hipStreamSynchronize(b->stream));
   if (option == SOP_OPT_GRAPHS)
     b->use_graphs = value != 0;
-  else
+  else if (option == SOP_OPT_PLANE_PASS)
     b->use_plane = value != 0;
+  else if (option == SOP_OPT_QUEUE)
+    b->use_queue = value != 0;
+  else
+    b->spin_limit = value;
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
   }
+  return SOP_OK;
+}
+
+sop_status sop_batch_check(sop_batch* b) {
+  if (!b) return fail(SOP_ERR_INVALID, "batch is NULL");
+  HIPTRY(hipStreamSynchronize(b->stream));
+  int aborted = 0;
+  for (Group3& g : b->groups) {
+    unsigned long long flag = 0;
+    HIPTRY(hipMemcpy(&flag, g.d_ctrl + 2 * sop::kQSlot, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag != 0) {
+      ++aborted;
+      const unsigned long long zero = 0;
+      HIPTRY(hipMemcpy(g.d_ctrl + 2 * sop::kQSlot, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    }
+  }
+  if (aborted > 0)
+    return fail(SOP_ERR_STATE, std::to_string(aborted) +
+                                   " work-queue launch(es) ran a wait out of polls and left "
+                                   "their members unfinished");
   return SOP_OK;
 }
 
@@ -713,7 +817,11 @@ sop_status sop_batch_describe(const sop_batch* b, char* buf, size_t len, size_t*
     o << ", \"z_cols\": " << sop::k3b_variant_width(sop::B3_Z, g.n, g.f64, g.vz)
       << ", \"y_cols\": " << sop::k3b_variant_width(sop::B3_Y, g.n, g.f64, g.vy)
       << ", \"x_rows\": " << sop::k3b_variant_width(sop::B3_X, g.n, g.f64, g.vx)
-      << ", \"plane\": " << ((b->use_plane && sop::k3b_plane(g.n, g.f64)) ? "true" : "false")
+      << ", \"plane\": "
+      << ((!b->use_queue && b->use_plane && sop::k3b_plane(g.n, g.f64)) ? "true" : "false")
+      << ", \"queue\": " << (b->use_queue ? "true" : "false") << ", \"rounds\": " << g.nrounds
+      << ", \"tickets\": " << g.tickets << ", \"queue_grid\": "
+      << sop::k3q_grid(g.n, g.S, g.f64)
       << ", \"from_cache\": " << (g.from_cache ? "true" : "false") << ", \"tuned_ms\": {\"z\": ";
     arr(g.ms_z);
     o << ", \"y\": ";

@@ -14,6 +14,8 @@
 // device, and members whose run is shorter than c leave at once.  The pass
 // bodies are those of the single-plan kernels, so a member's result equals
 // its single-plan run.
+#include <algorithm>
+
 #include "passes_3d.hpp"
 
 namespace sop {
@@ -103,6 +105,207 @@ __global__ void __launch_bounds__(SC::N * SC::TPC)
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
   plane_body<T, SC>((cx<T>*)m.psi + s * npts, (const cx<T>*)m.tw, cycle_kin<T>(m, c, 0),
                     m.conj, lds, blockIdx.x);
+}
+
+// ---------------------------------------------------------------- work queue
+// One persistent launch runs every pass of every member of a group.  The
+// pass tiles are one wave each: a z-pass tile of W columns, a y-pass tile
+// of W columns or an x-pass tile of W rows of one surface plane,
+// W = 64 / (threads per pencil).  A work item is kQWaves consecutive tiles
+// of one member's pass, run side by side by the waves of one workgroup.
+// Tickets order the items as the host's round table says (QRound): round
+// by round, member-major, the longest-running members first.  A workgroup
+// takes the next ticket from a global counter, waits until its member has
+// finished every item of the earlier rounds (the member's counter reaches
+// the round's `need`), runs its tiles with the same pass bodies as the
+// lockstep kernels, and adds one to the counter after its stores.  It takes
+// its next ticket before working on the current one, so the counter's
+// latency hides behind the item.  Items of several tiles keep the counter
+// traffic down: every claim and every completion is an atomic on one
+// address, and same-address atomics are served one at a time.
+//
+// Progress: a workgroup holds tickets only while it runs, works on them in
+// increasing order, and waits only for smaller tickets, so the holder of the
+// smallest unfinished ticket never waits; nothing assumes that the grid is
+// resident at once.  Every wave leaves when the tickets are exhausted.
+// Waits are bounded by spin_limit polls: a wait that runs out raises the
+// abort flag, and every wave that sees it leaves (the host reports it).
+constexpr int kQWaves = 4;
+constexpr int kQThreads = 64 * kQWaves;
+
+template <class SC>
+constexpr int qwidth() {
+  return 64 / SC::TPC;
+}
+// LDS elements of one tile (the largest pass kind)
+template <typename T, class SC>
+constexpr size_t q_tile_elems() {
+  constexpr int W = qwidth<SC>(), N = SC::N;
+  constexpr size_t z = (size_t)W * N, y = y_lds_elems<T, N>(W), x = x_lds_elems<T, N>(W);
+  return z > y ? (z > x ? z : x) : (y > x ? y : x);
+}
+template <typename T, class SC>
+constexpr size_t q_lds_bytes() {
+  return kQWaves * q_tile_elems<T, SC>() * sizeof(cx<T>);
+}
+
+template <typename T, class SC, int S>
+__global__ void __launch_bounds__(kQThreads)
+    k3q_run(const BMember3* __restrict__ mem, const QRound* __restrict__ rounds,
+            long long tickets, unsigned long long* __restrict__ ctrl, long long spin_limit) {
+  static_assert(64 % SC::TPC == 0 && SC::N % qwidth<SC>() == 0, "tile shape");
+  extern __shared__ char smem_raw[];
+  constexpr int N = SC::N, W = qwidth<SC>(), NB = N / W;
+  constexpr int TZ = NB * N, TYX = NB * N * S;  // tiles of one member in a round
+  static_assert(TZ % kQWaves == 0, "items of whole tiles");
+  const int wave = (int)threadIdx.x / 64;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)wave * q_tile_elems<T, SC>();
+  constexpr int64_t npts = (int64_t)N * N * N;
+  constexpr int A = axis_block<T, N>();
+  constexpr bool EQ = eig_form(3, S);
+  const int lane = (int)threadIdx.x % 64;
+  const bool lead = threadIdx.x == 0;
+  __shared__ long long bcast;
+  unsigned long long* const next = ctrl;
+  unsigned long long* const abort_flag = ctrl + kQSlot;
+  unsigned long long* const done = ctrl + kQCtrlHead * kQSlot;  // member m at m * kQSlot
+  // the leader's claim, shared through LDS (every wave needs the ticket)
+  auto claim = [&]() -> unsigned long long {
+    unsigned long long v = 0;
+    if (lead) v = __hip_atomic_fetch_add(next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+  };
+  if (lead) bcast = (long long)claim();
+  __syncthreads();
+  long long t = bcast;
+  __syncthreads();  // every wave has read it before the leader writes again
+  int p = 0;
+  while (t < tickets) {
+    while (t >= rounds[p + 1].start) ++p;
+    const QRound r = rounds[p];
+    const long long o = t - r.start;
+    const int per = (r.kind == B3_Z ? TZ : TYX) / kQWaves;  // items of one member
+    const int mi = (int)(o / per), tile = (int)(o % per) * kQWaves + wave;
+    const unsigned long long tn = claim();  // the leader's next ticket
+    // wait until the member has finished the earlier rounds
+    unsigned ok = 1;
+    unsigned long long* const cnt = done + (size_t)mi * kQSlot;
+    if (lead) {
+      long long polls = 0;
+      int backoff = 1;  // s_sleep(1) units between polls, doubling to 32 (about 1 us)
+      while ((long long)__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             r.need) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            ++polls > spin_limit) {
+          ok = 0;
+          break;
+        }
+        for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
+        backoff = backoff < 32 ? 2 * backoff : 32;
+      }
+      if (!ok) {
+        __hip_atomic_store(abort_flag, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctrl + 2 * kQSlot, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // the member's earlier stores are visible to this workgroup's loads
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      bcast = ok ? (long long)tn : -1;
+    }
+    __syncthreads();
+    const long long tn_all = bcast;
+    if (tn_all < 0) break;
+    const BMember3 m = mem[mi];
+    const int64_t c = r.cycle;
+    const int ln = opaque(lane);  // recomputed each item: see zpass_body
+    cx<T>* psi = (cx<T>*)m.psi;
+    const cx<T>* tw = (const cx<T>*)m.tw;
+    if (r.kind == B3_Z) {
+      const int bx = tile % NB, by = tile / NB;
+      const int M = m.M;
+      if (c == m.cycles) {  // closing potential action
+        zpass_body<T, SC, S, W, kTableCols, AX_NONE, EQ>(psi, m.vexp, 1,
+                                                         prog_index(m.prog[2 * M]), 0, m.conj,
+                                                         tw, nullptr, lds, bx, by, m.vtaus, ln);
+      } else {
+        const int i = (int)(c % M);
+        int nv = 1, iv0 = prog_index(m.prog[2 * i]), iv1 = 0;
+        if (c > 0 && i == 0) {  // step boundary: V(a_{M+1}) then V(a_1)
+          nv = 2;
+          iv0 = prog_index(m.prog[2 * M]);
+          iv1 = prog_index(m.prog[0]);
+        }
+        zpass_body<T, SC, S, W, kTableCols, AX_KIN, EQ>(psi, m.vexp, nv, iv0, iv1, m.conj, tw,
+                                                        cycle_kin<T>(m, c, 0), lds, bx, by,
+                                                        m.vtaus, ln);
+      }
+    } else {
+      const int s = tile / TZ, rem = tile % TZ;
+      const int bx = rem % NB, z = rem / NB;
+      if (r.kind == B3_Y)
+        ypass_body<T, SC, W, AX_KIN>(psi + s * npts, tw + A, cycle_kin<T>(m, c, 1), m.conj, lds,
+                                     bx, z, ln);
+      else
+        xpass_body<T, SC, W, AX_KIN>(psi + s * npts, tw + 2 * A, cycle_kin<T>(m, c, 2), m.conj,
+                                     lds, bx, z, ln);
+    }
+    // every wave's stores are visible device-wide before the counter moves
+    // (workgroup-scope release at the barrier, then the leader's release at
+    // agent scope; the ticket broadcast is read before the barrier, so the
+    // leader may overwrite it afterwards)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (lead) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    t = tn_all;
+  }
+}
+
+__global__ void k3q_clear(unsigned long long* __restrict__ ctrl, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kQCtrlHead + count;
+       i += gridDim.x * blockDim.x)
+    if (i != 2) ctrl[(size_t)i * kQSlot] = 0;  // the sticky flag stays
+}
+
+template <typename T, class SC, int S>
+int q_grid() {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k3q_run<T, SC, S>, kQThreads,
+                                                   q_lds_bytes<T, SC>()) != hipSuccess) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  cached = std::max(1, per) * std::max(1, cus);
+  return cached;
+}
+
+template <typename T, class SC, int S>
+hipError_t q_launch(const BMember3* mem, int count, const QRound* rounds, int64_t tickets,
+                    unsigned long long* ctrl, long long spin_limit, hipStream_t st) {
+  hipLaunchKernelGGL(k3q_clear, dim3(1), dim3(256), 0, st, ctrl, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || tickets <= 0) return e;
+  auto k = k3q_run<T, SC, S>;
+  const int grid = q_grid<T, SC, S>();
+  const size_t lds = q_lds_bytes<T, SC>();
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kQThreads), lds, st, mem, rounds, (long long)tickets,
+                     ctrl, spin_limit);
+  return hipGetLastError();
+}
+
+template <typename T, class SC, class F>
+hipError_t by_surfaces(int S, F&& f) {
+  switch (S) {
+    case 1: return f.template operator()<T, SC, 1>();
+    case 2: return f.template operator()<T, SC, 2>();
+    case 3: return f.template operator()<T, SC, 3>();
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------------- variants
@@ -242,6 +445,40 @@ int width_of(int kind, int v) {
 }
 
 }  // namespace
+
+bool k3q_supported(int n, int S) { return (n == 32 || n == 48 || n == 64) && S >= 1 && S <= 3; }
+
+int k3q_tiles(int kind, int n, int S, bool f64) {
+  int r = 0;
+  (void)by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
+    constexpr int NB = SC::N / qwidth<SC>();
+    r = (kind == B3_Z ? NB * SC::N : NB * SC::N * S) / kQWaves;
+    return hipSuccess;
+  });
+  return r;
+}
+
+int k3q_grid(int n, int S, bool f64) {
+  int r = 0;
+  (void)by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
+    return by_surfaces<T, SC>(S, [&]<typename T2, class SC2, int S2>() -> hipError_t {
+      r = q_grid<T2, SC2, S2>();
+      return hipSuccess;
+    });
+  });
+  return r;
+}
+
+hipError_t k3q_launch(int n, int S, bool f64, const BMember3* mem, int count,
+                      const QRound* rounds, int64_t tickets, unsigned long long* ctrl,
+                      long long spin_limit, hipStream_t stream) {
+  if (!k3q_supported(n, S) || count < 1 || spin_limit < 1) return hipErrorInvalidValue;
+  return by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
+    return by_surfaces<T, SC>(S, [&]<typename T2, class SC2, int S2>() -> hipError_t {
+      return q_launch<T2, SC2, S2>(mem, count, rounds, tickets, ctrl, spin_limit, stream);
+    });
+  });
+}
 
 bool k3b_supported(int n, int S) { return (n == 32 || n == 48 || n == 64) && S >= 1 && S <= 3; }
 

@@ -100,11 +100,13 @@ constexpr size_t x_lds_elems(int ROWS) {
 // global load in the middle of the transform.  Every transform starts with a
 // stage that uses no twiddles, followed by an LDS exchange whose barrier
 // orders these writes before the first read.
+// `lane` and `nt` are the thread's index in the tile and the tile's thread
+// count.
 template <typename T, int N, int NB>
-__device__ __forceinline__ void stage_blocks(cx<T>* dst, const cx<T>* const (&src)[NB]) {
+__device__ __forceinline__ void stage_blocks(cx<T>* dst, const cx<T>* const (&src)[NB], int lane,
+                                             int nt) {
   constexpr int A = axis_block<T, N>();
-  const int nt = (int)(blockDim.x * blockDim.y);
-  for (int i = (int)threadIdx.x; i < A; i += nt) {
+  for (int i = lane; i < A; i += nt) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) dst[b * A + i] = src[b][i];
   }
@@ -139,7 +141,10 @@ __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __res
 // kinetic set (AX_KIN only).
 //
 // Table entries are cx<T>, in FP32 the pairs (rounded, residue) of
-// Split<float> (each entry's index doubled).
+// Split<float> (each entry's index doubled).  `lane` (here and in the y- and
+// x-pass bodies) is the thread's index in the tile, threadIdx.x unless a
+// persistent caller passes it through opaque() so that the compiler does not
+// keep every lane-derived offset live across its work loop.
 //
 // EQ (S = 2, 3): `vexp` is instead the one compact eigen-form table, FP64 in
 // both precisions (eig_slots(S) complex double slots per point, same tile
@@ -177,11 +182,11 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
                                            const void* __restrict__ vexp, int nv, int iv0,
                                            int iv1, int conj, const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fz, cx<T>* lds, int bx,
-                                           int by, const double* __restrict__ taus = nullptr) {
+                                           int by, const double* __restrict__ taus = nullptr,
+                                           int lane = (int)threadIdx.x) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
   static_assert(!EQ || S >= 2, "eigen form: two or three surfaces");
   constexpr int N = SC::N, E = SC::E, NE = EQ ? eig_slots(S) : S * (S + 1) / 2;
-  const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
   const int x = bx * C + col, y = by;
   constexpr uint32_t plane = (uint32_t)N * N;
@@ -286,9 +291,8 @@ template <typename T, class SC, int C, int AX>
 __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fy, int conj, cx<T>* lds,
-                                           int bx, int z) {
+                                           int bx, int z, int lane = (int)threadIdx.x) {
   constexpr int N = SC::N, E = SC::E;
-  const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
   const int x = bx * C + col;
   constexpr int64_t plane = (int64_t)N * N;
@@ -296,9 +300,9 @@ __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
   const LayStrided lay{col, 0, C};
   cx<T>* const tws = lds + C * N;  // staged twiddles and y factor
   if constexpr (AX == AX_KIN) {
-    stage_blocks<T, N, 2>(tws, {tw, fy});
+    stage_blocks<T, N, 2>(tws, {tw, fy}, lane, C * SC::TPC);
   } else {
-    stage_blocks<T, N, 1>(tws, {tw});
+    stage_blocks<T, N, 1>(tws, {tw}, lane, C * SC::TPC);
   }
   cx<T> v[1][E];
 #pragma unroll
@@ -320,9 +324,8 @@ template <typename T, class SC, int ROWS, int AX>
 __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fx, int conj, cx<T>* lds,
-                                           int bx, int z) {
+                                           int bx, int z, int lane = (int)threadIdx.x) {
   constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
-  const int lane = threadIdx.x;
   const int t = lane % TPC, row = lane / TPC;
   const int y = bx * ROWS + row;
   constexpr int64_t plane = (int64_t)N * N;
@@ -331,9 +334,9 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
   const LayPadded lay{row * (N + N / 16), 0};
   cx<T>* const tws = lds + ROWS * (N + N / 16);  // staged twiddles and x factor
   if constexpr (AX == AX_KIN) {
-    stage_blocks<T, N, 2>(tws, {tw, fx});
+    stage_blocks<T, N, 2>(tws, {tw, fx}, lane, ROWS * TPC);
   } else {
-    stage_blocks<T, N, 1>(tws, {tw});
+    stage_blocks<T, N, 1>(tws, {tw}, lane, ROWS * TPC);
   }
   cx<T> v[1][E];
 #pragma unroll
@@ -382,7 +385,7 @@ __device__ __forceinline__ void plane_body(cx<T>* __restrict__ psi_s,
   // staged [twiddles y | twiddles x | f_y | f_x] after the plane
   cx<T>* const twy = lds + N * P;
   cx<T>* const twx = twy + AS;
-  stage_blocks<T, N, 4>(twy, {tw + AS, tw + 2 * AS, kin + AS, kin + 2 * AS});
+  stage_blocks<T, N, 4>(twy, {tw + AS, tw + 2 * AS, kin + AS, kin + 2 * AS}, lane, N * TPC);
   const LayStrided lcol{col, 0, N};
   const LayPadded lrow{row * P, 0};
   const T csign = conj ? (T)-1 : (T)1;

@@ -91,7 +91,7 @@ EXPORTS = ["sop_abi_version", "sop_status_string", "sop_last_error", "sop_suppor
            "sop_adjoint",
            "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
            "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
-           "sop_batch_describe"]
+           "sop_batch_check", "sop_batch_describe"]
 KINDS = ["zpass", "ypass", "xpass", "k1d", "other", "plane", "interp"]
 
 _lib = None
@@ -153,6 +153,7 @@ def lib():
     L.sop_batch_propagate.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int]
     L.sop_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.sop_batch_check.argtypes = [vp]
     L.sop_batch_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
                                      ctypes.POINTER(ctypes.c_size_t)]
     for f in ("sop_scheme_sequence", "sop_plan_create", "sop_plan_create_with_allocator",
@@ -165,7 +166,7 @@ def lib():
               "sop_adjoint_workspace_bytes", "sop_adjoint_forward", "sop_adjoint_backward",
               "sop_propagate_many", "sop_plan_set_option", "sop_batch_create",
               "sop_batch_destroy", "sop_batch_propagate", "sop_batch_set_option",
-              "sop_batch_describe"):
+              "sop_batch_check", "sop_batch_describe"):
         getattr(L, f).restype = ctypes.c_int
     L.sop_supported_length.restype = ctypes.c_int
     _lib = L
@@ -567,6 +568,18 @@ class Batch:
 
     def set_plane_pass(self, enable: bool):
         _check(lib().sop_batch_set_option(self._h, 2, int(bool(enable))), "sop_batch_set_option")
+
+    def set_queue(self, enable: bool):
+        """3D groups as one work-queue launch each, or (default) as lockstep pass launches."""
+        _check(lib().sop_batch_set_option(self._h, 3, int(bool(enable))), "sop_batch_set_option")
+
+    def set_queue_spin(self, polls: int):
+        """Bound on the polls of one wait in a work-queue launch."""
+        _check(lib().sop_batch_set_option(self._h, 4, int(polls)), "sop_batch_set_option")
+
+    def check(self):
+        """Synchronises; raises if a work-queue wait ran out of polls since the last check."""
+        _check(lib().sop_batch_check(self._h), "sop_batch_check")
 
     def describe(self) -> dict:
         import json

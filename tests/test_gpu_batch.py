@@ -2,9 +2,10 @@
 sizes, orders, dt and step counts in one graph launch.
 
 Every member is compared with the FP64 oracle at 1e-12 relative L2 and with
-its own single-plan run: 3D members (lockstep passes share the single-plan
-pass bodies) bitwise, 1D members bitwise when the tuner keeps the
-single-plan schedule and to 1e-12 otherwise (same DFTs, other radix order).
+its own single-plan run: 3D members (the work-queue launch and the lockstep
+passes share the single-plan pass bodies) bitwise, 1D members bitwise when
+the tuner keeps the single-plan schedule and to 1e-12 otherwise (same DFTs,
+other radix order).
 """
 import json
 import os
@@ -133,8 +134,9 @@ def test_batch_fp64_matches_oracle_and_single_runs(torch_cuda, orc):
     assert d["solo"] == [i for i, r in enumerate(MIX) if r[0] == "3d" and r[3] == "TVT"]
     psis = states(torch, models, torch.complex128)
     batch.propagate(psis, ns)
-    torch.cuda.synchronize()
+    batch.check()
     assert batch.describe()["graph"]
+    assert not any(g["queue"] for g in batch.describe()["groups"])
     got = [x.cpu().numpy() for x in psis]
     for i, ((kind, n, S, split, comp, order, dt, k, off), m) in enumerate(zip(MIX, models)):
         if k == 0:
@@ -296,7 +298,7 @@ def test_ensemble_manifest_bench_shape(torch_cuda, orc):
     batch = soprop.Batch(plans)
     psis = states(torch, models, torch.complex128)
     batch.propagate(psis, ns)
-    torch.cuda.synchronize()
+    batch.check()
     d = batch.describe()
     print("[ensemble] " + json.dumps({k: v for k, v in d.items() if k != "families"}))
     # the most expensive member of each kind plus a spread of others
@@ -338,6 +340,8 @@ def test_batch_plane_pass_equals_three_passes(torch_cuda):
     models, plans, ns = build_members(torch, torch.complex128, mix)
     a = soprop.Batch(plans)
     b = soprop.Batch(plans)
+    a.set_queue(False)
+    b.set_queue(False)
     b.set_plane_pass(False)
     assert all(g["plane"] for g in a.describe()["groups"])
     pa = states(torch, models, torch.complex128)
@@ -350,11 +354,92 @@ def test_batch_plane_pass_equals_three_passes(torch_cuda):
         np.testing.assert_array_equal(pa[i].cpu().numpy(), pb[i].cpu().numpy(), err_msg=f"{i}")
 
 
+QUEUE_MIX = [
+    ("3d", 32, 3, "VTV", "triple_jump", 4, 10.0, 3, 0.0),
+    ("3d", 32, 3, "VTV", "strang", 2, 7.0, 5, 0.7),
+    ("3d", 32, 3, "VTV", "suzuki", 4, 4.0, 0, 0.0),           # zero steps
+    ("3d", 32, 3, "VTV", "suzuki", 6, 9.0, 1, -0.3),
+    ("3d", 48, 3, "VTV", "suzuki", 4, 12.0, 2, -0.4),
+    ("3d", 48, 3, "VTV", "strang", 2, 5.0, 7, 0.3),
+    ("3d", 64, 3, "VTV", "triple_jump", 4, 10.0, 1, 0.2),
+    ("3d", 64, 1, "VTV", "strang", 2, 0.05, 3, 0.0),
+    ("3d", 32, 2, "VTV", "triple_jump", 4, 0.05, 2, 0.0),
+    ("3d", 48, 1, "VTV", "triple_jump", 4, 0.05, 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_queue_equals_lockstep(torch_cuda, dtype):
+    """The work-queue launch of the 3D groups (one persistent launch per
+    group, tiles ordered round by round) gives bitwise the states of the
+    lockstep pass launches and of the single-plan runs, and its round table
+    has the shape the step counts imply."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    models, plans, ns = build_members(torch, dt, QUEUE_MIX)
+    q = soprop.Batch(plans)
+    q.set_queue(True)
+    lk = soprop.Batch(plans)
+    pq = states(torch, models, dt)
+    pl = states(torch, models, dt)
+    q.propagate(pq, ns)
+    q.check()
+    lk.propagate(pl, ns)
+    lk.check()
+    d = q.describe()
+    print("[queue] " + json.dumps(d["groups"]), flush=True)
+    Ms = [p.info.M for p in plans]
+    for g in d["groups"]:
+        assert g["queue"]
+        cyc = sorted((ns[i] * Ms[i] for i in g["members"]), reverse=True)
+        assert g["rounds"] == (3 * cyc[0] + 1 if cyc[0] > 0 else 0)
+    assert not any(g["queue"] for g in lk.describe()["groups"])
+    ref = single_runs(torch, plans, models, ns, dt)
+    for i in range(len(ns)):
+        a = pq[i].cpu().numpy()
+        np.testing.assert_array_equal(a, pl[i].cpu().numpy(), err_msg=f"member {i} vs lockstep")
+        np.testing.assert_array_equal(a, ref[i], err_msg=f"member {i} vs single run")
+    # a second call replays the captured graph
+    q.propagate(pq, ns)
+    q.check()
+    ref2 = single_runs(torch, plans, models, ns, dt, reps=2)
+    for i in range(len(ns)):
+        np.testing.assert_array_equal(pq[i].cpu().numpy(), ref2[i], err_msg=f"replay {i}")
+
+
+def test_batch_queue_spin_limit_reports(torch_cuda):
+    """A poll limit of one makes the queue's first dependency wait run out:
+    the launch leaves early, sop_batch_check reports it once, and the next
+    launch with the default limit propagates correctly."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    mix = [r for r in QUEUE_MIX if r[7] > 0][:4]
+    models, plans, ns = build_members(torch, torch.complex128, mix)
+    b = soprop.Batch(plans)
+    b.set_queue(True)
+    b.set_queue_spin(1)
+    psis = states(torch, models, torch.complex128)
+    b.propagate(psis, ns)
+    with pytest.raises(soprop.SopError, match="ran a wait out of polls"):
+        b.check()
+    b.check()  # reported once
+    b.set_queue_spin(1 << 21)
+    psis = states(torch, models, torch.complex128)
+    b.propagate(psis, ns)
+    b.check()
+    ref = single_runs(torch, plans, models, ns, torch.complex128)
+    for i in range(len(ns)):
+        np.testing.assert_array_equal(psis[i].cpu().numpy(), ref[i], err_msg=f"member {i}")
+    with pytest.raises(soprop.SopError):
+        b.set_queue_spin(0)
+
+
 @pytest.mark.timeout(600)
 def test_ensemble_manifest_full_final_time(torch_cuda, orc):
     """The 256-member manifest with every member run to t_f = 10 a.u.
-    (200 to 2000 steps of up to 125 substeps): the longest runs exceed the
-    graph's launch budget, so this covers the batch's eager path too.
+    (200 to 2000 steps of up to 125 substeps): the lockstep chains exceed
+    the graph's launch budget, so this covers the batch's eager path too.
     Sampled members (the most expensive of each kind and a spread) equal
     their single-plan runs (3D bitwise, 1D to the FP64 bar); the cheapest 1D
     and 3D members match the oracle; every member keeps its norm."""
@@ -369,7 +454,7 @@ def test_ensemble_manifest_full_final_time(torch_cuda, orc):
     batch = soprop.Batch(plans)
     psis = states(torch, models, torch.complex128)
     batch.propagate(psis, ns)
-    torch.cuda.synchronize()
+    batch.check()
     d = batch.describe()
     print("[ensemble t_f=10] " + json.dumps({k: v for k, v in d.items() if k != "families"}),
           flush=True)
