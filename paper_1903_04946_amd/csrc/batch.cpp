@@ -372,7 +372,8 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
     if (b->use_queue) {
       if (g.tickets <= 0) continue;
       hipError_t e = sop::k3q_launch(g.n, g.S, g.f64, g.d_mem, (int)g.members.size(),
-                                     g.d_rounds, g.tickets, g.d_ctrl, b->spin_limit, next());
+                                     g.d_rounds, (int)g.nrounds, g.tickets, g.d_ctrl,
+                                     b->spin_limit, next());
       if (e != hipSuccess) return e;
       continue;
     }

@@ -340,11 +340,14 @@ hipError_t k3b_launch(int kind, int n, int S, bool f64, int variant, const BMemb
 // 3D groups as one work-queue launch (kernels_batch3d.hip).  Round p of a
 // group is pass number p of every member still running then: p = 3c the
 // z-pass of cycle c (the closing one where c = cycles), 3c + 1 and 3c + 2
-// its y- and x-passes.  The members, in decreasing order of cycles, run in
-// round p while their index is below `members`; the round's tickets are
-// [start, start + members * tiles) (member-major), and a tile of round p may
-// start once its member has finished `need` tiles (all of rounds 0..p-1).
-// rounds[nrounds].start is the ticket count (a sentinel round).
+// its y- and x-passes.  Every member's work items are numbered by its own
+// ticket counter, round after round: round p's items are tickets
+// [need, next round's need), and an item of round p may start once its
+// member has finished `need` items (all of rounds 0..p-1); a member with c
+// cycles runs rounds 0..3c.  The members, in decreasing order of cycles,
+// run in round p while their index is below `members`, and start counts
+// the group's items before round p (both for the description only).
+// rounds[nrounds] is a sentinel round.
 struct QRound {
   int64_t start;
   int64_t need;
@@ -354,12 +357,14 @@ struct QRound {
 };
 // Control block of a queue launch, one 64-bit word per 256-byte slot (the
 // counters that many waves poll or add to do not share a cache line):
-// slot 0 the next ticket, slot 1 the abort flag (a wait ran out of polls;
-// every wave leaves), slot 2 a sticky copy of the abort flag (cleared only
-// by the host), slot 3 + m the tiles finished by member m.
+// slot 1 the abort flag (a wait ran out of polls; every wave leaves), slot 2
+// a sticky copy of it (cleared only by the host), slot 3 + m the items
+// member m has finished, slot 3 + members + m its next ticket.
 constexpr int kQCtrlHead = 3;
 constexpr int kQSlot = 32;  // words per slot
-constexpr size_t q_ctrl_words(int members) { return (size_t)(kQCtrlHead + members) * kQSlot; }
+constexpr size_t q_ctrl_words(int members) {
+  return (size_t)(kQCtrlHead + 2 * members) * kQSlot;
+}
 bool k3q_supported(int n, int S);
 int k3q_tiles(int kind, int n, int S, bool f64);  // work items of one member in a round
 // Persistent workgroups a queue launch uses (occupancy x compute units).
@@ -367,8 +372,8 @@ int k3q_grid(int n, int S, bool f64);
 // Clears the control block (all but the sticky flag), then runs the queue.
 // The control block must hold q_ctrl_words(count) words.
 hipError_t k3q_launch(int n, int S, bool f64, const BMember3* mem, int count,
-                      const QRound* rounds, int64_t tickets, unsigned long long* ctrl,
-                      long long spin_limit, hipStream_t stream);
+                      const QRound* rounds, int nrounds, int64_t tickets,
+                      unsigned long long* ctrl, long long spin_limit, hipStream_t stream);
 
 constexpr int kMaxParams = 8;
 constexpr int kReduceBlocks = 1024;

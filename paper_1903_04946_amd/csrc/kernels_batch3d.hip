@@ -113,21 +113,24 @@ __global__ void __launch_bounds__(SC::N * SC::TPC)
 // of W columns or an x-pass tile of W rows of one surface plane,
 // W = 64 / (threads per pencil).  A work item is kQWaves consecutive tiles
 // of one member's pass, run side by side by the waves of one workgroup.
-// Tickets order the items as the host's round table says (QRound): round
-// by round, member-major, the longest-running members first.  A workgroup
-// takes the next ticket from a global counter, waits until its member has
-// finished every item of the earlier rounds (the member's counter reaches
-// the round's `need`), runs its tiles with the same pass bodies as the
-// lockstep kernels, and adds one to the counter after its stores.  It takes
-// its next ticket before working on the current one, so the counter's
-// latency hides behind the item.  Items of several tiles keep the counter
-// traffic down: every claim and every completion is an atomic on one
-// address, and same-address atomics are served one at a time.
+// Every member numbers its items with its own ticket counter, round after
+// round (QRound).  A workgroup serves one member at a time, starting with
+// member blockIdx.x mod count: it takes the member's next ticket, waits
+// until the member has finished every item of the earlier rounds (the
+// member's completion counter reaches the round's `need`), runs its tiles
+// with the same pass bodies as the lockstep kernels, and adds one to the
+// completion counter after its stores.  It takes the member's next ticket
+// before working on the current one, so the counter's latency hides behind
+// the item; once the member's tickets run out it finishes the item, then
+// moves on to the next member with tickets left, and leaves when none has
+// any.  Items
+// of several tiles and one counter pair per member keep the counter traffic
+// down: same-address atomics are served one at a time.
 //
-// Progress: a workgroup holds tickets only while it runs, works on them in
-// increasing order, and waits only for smaller tickets, so the holder of the
-// smallest unfinished ticket never waits; nothing assumes that the grid is
-// resident at once.  Every wave leaves when the tickets are exhausted.
+// Progress: a workgroup holds tickets only while it runs, all of one member,
+// works on them in increasing order, and waits only for smaller tickets of
+// that member, so the holder of a member's smallest unfinished ticket never
+// waits; nothing assumes that the grid is resident at once.
 // Waits are bounded by spin_limit polls: a wait that runs out raises the
 // abort flag, and every wave that sees it leaves (the host reports it).
 constexpr int kQWaves = 4;
@@ -151,8 +154,8 @@ constexpr size_t q_lds_bytes() {
 
 template <typename T, class SC, int S>
 __global__ void __launch_bounds__(kQThreads)
-    k3q_run(const BMember3* __restrict__ mem, const QRound* __restrict__ rounds,
-            long long tickets, unsigned long long* __restrict__ ctrl, long long spin_limit) {
+    k3q_run(const BMember3* __restrict__ mem, int count, const QRound* __restrict__ rounds,
+            int nrounds, unsigned long long* __restrict__ ctrl, long long spin_limit) {
   static_assert(64 % SC::TPC == 0 && SC::N % qwidth<SC>() == 0, "tile shape");
   extern __shared__ char smem_raw[];
   constexpr int N = SC::N, W = qwidth<SC>(), NB = N / W;
@@ -165,28 +168,54 @@ __global__ void __launch_bounds__(kQThreads)
   constexpr bool EQ = eig_form(3, S);
   const int lane = (int)threadIdx.x % 64;
   const bool lead = threadIdx.x == 0;
-  __shared__ long long bcast;
-  unsigned long long* const next = ctrl;
+  __shared__ long long bcast[2];
   unsigned long long* const abort_flag = ctrl + kQSlot;
-  unsigned long long* const done = ctrl + kQCtrlHead * kQSlot;  // member m at m * kQSlot
-  // the leader's claim, shared through LDS (every wave needs the ticket)
-  auto claim = [&]() -> unsigned long long {
-    unsigned long long v = 0;
-    if (lead) v = __hip_atomic_fetch_add(next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return v;
+  unsigned long long* const done = ctrl + kQCtrlHead * kQSlot;            // member m at m * kQSlot
+  unsigned long long* const next = ctrl + (kQCtrlHead + count) * kQSlot;  // likewise
+  // the leader takes member mi's next ticket (tickets past the member's
+  // last item mean none)
+  auto claim = [&](int mi) -> long long {
+    return (long long)__hip_atomic_fetch_add(next + (size_t)mi * kQSlot, 1ull, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
   };
-  if (lead) bcast = (long long)claim();
+  auto last = [&](int mi) -> long long {  // the member's ticket count
+    const int64_t cy = mem[mi].cycles;
+    return cy > 0 ? rounds[3 * cy + 1].need : 0;
+  };
+  // find a member with tickets left, starting at mi; -1: none left
+  auto find = [&](int mi, long long* tk) -> int {
+    for (int k = 0; k < count; ++k, mi = (mi + 1) % count) {
+      const long long v = claim(mi);
+      if (v < last(mi)) {
+        *tk = v;
+        return mi;
+      }
+    }
+    return -1;
+  };
+  if (lead) {
+    long long t0 = 0;
+    const int m0 = find((int)(blockIdx.x % (unsigned)count), &t0);
+    bcast[0] = m0;
+    bcast[1] = t0;
+  }
   __syncthreads();
-  long long t = bcast;
-  __syncthreads();  // every wave has read it before the leader writes again
+  int mi = (int)bcast[0];
+  long long t = bcast[1];
+  __syncthreads();  // every wave has read them before the leader writes again
   int p = 0;
-  while (t < tickets) {
-    while (t >= rounds[p + 1].start) ++p;
+  while (mi >= 0) {
+    while (t >= rounds[p + 1].need) ++p;
     const QRound r = rounds[p];
-    const long long o = t - r.start;
-    const int per = (r.kind == B3_Z ? TZ : TYX) / kQWaves;  // items of one member
-    const int mi = (int)(o / per), tile = (int)(o % per) * kQWaves + wave;
-    const unsigned long long tn = claim();  // the leader's next ticket
+    const int tile = (int)(t - r.need) * kQWaves + wave;
+    // the leader's next ticket of this member (-1: none left; another
+    // member's ticket is taken only once this item is done, so a workgroup
+    // never holds tickets of two members)
+    long long tn = 0;
+    if (lead) {
+      tn = claim(mi);
+      if (tn >= last(mi)) tn = -1;
+    }
     // wait until the member has finished the earlier rounds
     unsigned ok = 1;
     unsigned long long* const cnt = done + (size_t)mi * kQSlot;
@@ -209,11 +238,13 @@ __global__ void __launch_bounds__(kQThreads)
       }
       // the member's earlier stores are visible to this workgroup's loads
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      bcast = ok ? (long long)tn : -1;
+      bcast[0] = ok;
+      bcast[1] = tn;
     }
     __syncthreads();
-    const long long tn_all = bcast;
-    if (tn_all < 0) break;
+    const bool go = bcast[0] != 0;
+    long long tn_all = bcast[1];
+    if (!go) break;
     const BMember3 m = mem[mi];
     const int64_t c = r.cycle;
     const int ln = opaque(lane);  // recomputed each item: see zpass_body
@@ -250,20 +281,45 @@ __global__ void __launch_bounds__(kQThreads)
     }
     // every wave's stores are visible device-wide before the counter moves
     // (workgroup-scope release at the barrier, then the leader's release at
-    // agent scope; the ticket broadcast is read before the barrier, so the
-    // leader may overwrite it afterwards)
+    // agent scope; the broadcast was read before this barrier, so the
+    // leader may write it again afterwards)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (lead) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (tn_all >= 0) {
+      t = tn_all;
+      continue;
+    }
+    // this member has no tickets left: the next member that has
+    if (lead) {
+      long long t1 = 0;
+      bcast[0] = find((mi + 1) % count, &t1);
+      bcast[1] = t1;
+    }
+    __syncthreads();
+    const int mn = (int)bcast[0];
+    tn_all = bcast[1];
+    __syncthreads();  // read before the leader writes again
+    if (mn < 0) break;
+    int lo = 0, hi = nrounds;  // the ticket's round: rounds[lo].need <= t < rounds[hi].need
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (rounds[mid].need <= tn_all)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    p = lo;
+    mi = mn;
     t = tn_all;
   }
 }
 
 __global__ void k3q_clear(unsigned long long* __restrict__ ctrl, int count) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kQCtrlHead + count;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kQCtrlHead + 2 * count;
        i += gridDim.x * blockDim.x)
     if (i != 2) ctrl[(size_t)i * kQSlot] = 0;  // the sticky flag stays
 }
@@ -285,16 +341,17 @@ int q_grid() {
 }
 
 template <typename T, class SC, int S>
-hipError_t q_launch(const BMember3* mem, int count, const QRound* rounds, int64_t tickets,
-                    unsigned long long* ctrl, long long spin_limit, hipStream_t st) {
+hipError_t q_launch(const BMember3* mem, int count, const QRound* rounds, int nrounds,
+                    int64_t tickets, unsigned long long* ctrl, long long spin_limit,
+                    hipStream_t st) {
   hipLaunchKernelGGL(k3q_clear, dim3(1), dim3(256), 0, st, ctrl, count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tickets <= 0) return e;
   auto k = k3q_run<T, SC, S>;
   const int grid = q_grid<T, SC, S>();
   const size_t lds = q_lds_bytes<T, SC>();
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kQThreads), lds, st, mem, rounds, (long long)tickets,
-                     ctrl, spin_limit);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kQThreads), lds, st, mem, count, rounds, nrounds, ctrl,
+                     spin_limit);
   return hipGetLastError();
 }
 
@@ -470,12 +527,13 @@ int k3q_grid(int n, int S, bool f64) {
 }
 
 hipError_t k3q_launch(int n, int S, bool f64, const BMember3* mem, int count,
-                      const QRound* rounds, int64_t tickets, unsigned long long* ctrl,
-                      long long spin_limit, hipStream_t stream) {
+                      const QRound* rounds, int nrounds, int64_t tickets,
+                      unsigned long long* ctrl, long long spin_limit, hipStream_t stream) {
   if (!k3q_supported(n, S) || count < 1 || spin_limit < 1) return hipErrorInvalidValue;
   return by_grid(n, f64, [&]<typename T, class SC>() -> hipError_t {
     return by_surfaces<T, SC>(S, [&]<typename T2, class SC2, int S2>() -> hipError_t {
-      return q_launch<T2, SC2, S2>(mem, count, rounds, tickets, ctrl, spin_limit, stream);
+      return q_launch<T2, SC2, S2>(mem, count, rounds, nrounds, tickets, ctrl, spin_limit,
+                                   stream);
     });
   });
 }
