@@ -345,8 +345,10 @@ sop_status sop_adjoint(sop_plan* plan, const void* psi0_dev, int64_t nsteps, int
 
 /* Plan options.  SOP_OPT_GRAPHS (default 1): on 3D grids, runs of 4 or more
  * steps launch the first step, the steady step (replayed) and the final
- * pass as HIP graphs captured once per state pointer, direction and count;
- * 0 launches every pass eagerly.  SOP_OPT_PLANE_PASS: on 3D grids whose xy
+ * pass as HIP graphs captured once per state pointer, direction and count,
+ * and the trapezoidal rule launches its iterations in captured blocks of
+ * four (once per state pointer and stage coefficient); 0 launches every
+ * pass eagerly.  SOP_OPT_PLANE_PASS: on 3D grids whose xy
  * plane fits in LDS (n <= 64 in FP64, n <= 128 in FP32) the y- and x-passes
  * of a kinetic action run as one plane pass; default 1 for n <= 64, 0 for
  * larger grids.  Every setting gives bitwise identical results.
@@ -368,10 +370,13 @@ sop_status sop_plan_set_option(sop_plan* plan, int option, int value);
  * residual), at most max_iter iterations per stage.
  * SOP_C128 plans only (SOP_ERR_UNSUPPORTED otherwise): 1D of 512..8192
  * points, each state in one workgroup for the whole call; or 3D, one state
- * after another, the iteration driven from the host with H u = the three
- * one-axis kinetic terms F_d^-1 T_d F_d u (the propagator's pass kernels)
- * plus V u, every reduction in a fixed order (two synchronisations per
- * iteration).  VT/TV plans have no composition (SOP_ERR_INVALID).  psi:
+ * after another, the iterations enqueued from the host with H u = the
+ * three one-axis kinetic terms F_d^-1 T_d F_d u (the propagator's pass
+ * kernels) plus V u, every reduction in a fixed order, the method's scalars
+ * kept on the device and read back every few iterations (the iterate stays
+ * frozen from the iteration that meets tol, so the result does not depend
+ * on when the host looks).  VT/TV plans have no composition
+ * (SOP_ERR_INVALID).  psi:
  * device [count][S][grid], count (1..65535) independent states, advanced in
  * place by nsteps steps.  *iterations (may be NULL) receives the total
  * iteration count over all states.  Synchronises the plan's stream;
@@ -392,7 +397,8 @@ sop_status sop_propagate_trapezoid(sop_plan* plan, void* psi, int count, int64_t
  * composition stage, or (3D) six vectors of nsurf * npts * 16 bytes plus
  * about 33 KB, and returns SOP_ERR_INVALID, before any device work, if that
  * exceeds the array (e.g. at most 1023 states of 1024 points and two
- * surfaces; 3D grids up to 32^3 x 3).  Every call on one GPU shares that GPU's array: calls that
+ * surfaces; 3D grids up to 32^3 x 3).  Every call on one GPU shares that
+ * GPU's array: calls that
  * overlap on one GPU (other streams, other host threads) race and must be
  * serialised by the caller.  Nothing in the array needs clearing between
  * calls.  Synchronises the plan's stream. */

@@ -217,18 +217,24 @@ struct Trap3Bufs {
   void* qy = nullptr;
   void* qx = nullptr;
   double* partials = nullptr;
-  double* sums = nullptr;
+  double* sums = nullptr;  // the status block, kT3Status doubles (T3_*)
 };
-// From x: r = p = -2 i tau H x; sums = {|b|^2, |r|^2, Re r^T r, Im r^T r}.
+// Status block of the 3D trapezoidal iteration (doubles): |b|^2, rho =
+// r^T r (re, im), mu = p^T A p (re, im), |r|^2, rho after the last update
+// (re, im), the stop flag (converged, broken down or out of iterations),
+// the iteration count, the breakdown flag, tol^2 and the iteration limit.
+enum { T3_BB = 0, T3_RHO = 1, T3_MU = 3, T3_RR = 5, T3_RHO_NEW = 6, T3_STOP = 8, T3_ITER = 9,
+       T3_FAIL = 10, T3_TOL2 = 11, T3_MAXIT = 12, kT3Status = 13 };
+// From x: r = p = -2 i tau H x; the status for a new stage.
 hipError_t t3_init(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
-                   hipStream_t st);
-// ap = p + i tau H p; sums = {Re p^T ap, Im p^T ap}.
+                   double tol2, int max_iter, hipStream_t st);
+// ap = p + i tau H p; mu (rho takes the last update's value).
 hipError_t t3_ap(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
                  hipStream_t st);
-// x += alpha p, r -= alpha ap over n = S npts values; sums = {|r|^2, r^T r}.
-hipError_t t3_update(const Trap3Bufs& b, int64_t n, double are, double aim, hipStream_t st);
+// x += alpha p, r -= alpha ap over n = S npts values; |r|^2, rho_new, the test.
+hipError_t t3_update(const Trap3Bufs& b, int64_t n, hipStream_t st);
 // p = r + beta p.
-hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, double bre, double bim, hipStream_t st);
+hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, hipStream_t st);
 // One one-axis pass (axis 0 = slowest ("z"), 1, 2) of every surface of psi:
 // F_a^-1 f_a F_a with the factor block of d.kin's set 0 for that axis (the
 // propagator's pass kernels; no potential action).

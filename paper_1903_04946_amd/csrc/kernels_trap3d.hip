@@ -11,6 +11,13 @@
 // the S x S matvec with V(x), form A p = p + i tau H p, update the iterates,
 // and reduce the inner products the method needs (u^T v without conjugation,
 // and |u|^2) in a fixed order: block partials, then one final block.
+//
+// The iteration's scalars live on the device (the status block `st`, see
+// T3 below): the final blocks form rho, mu, |r|^2 and the convergence test,
+// and the update kernels read alpha = rho / mu and beta = rho_new / rho from
+// it, so the host only reads the status every few iterations.  Once the
+// residual test holds (or mu breaks down) the status freezes the iterate:
+// later iterations of the block use alpha = beta = 0 and leave x unchanged.
 #include "fft_core.hpp"
 #include "internal.hpp"
 
@@ -118,12 +125,20 @@ __global__ void __launch_bounds__(kTB)
   tsum<2>(acc, partials + (size_t)blockIdx.x * 2);
 }
 
-// x += alpha p, r -= alpha ap.  Partials: |r|^2, r^T r (re, im).
+// x += alpha p, r -= alpha ap with alpha = rho / mu from the status (0 once
+// it is frozen).  Partials: |r|^2, r^T r (re, im).
+__device__ __forceinline__ cd_t cdiv(double are, double aim, double bre, double bim) {
+  const double den = bre * bre + bim * bim;
+  return {(are * bre + aim * bim) / den, (aim * bre - are * bim) / den};
+}
+
 __global__ void __launch_bounds__(kTB)
     k_t3_update(cd_t* __restrict__ x, cd_t* __restrict__ r, const cd_t* __restrict__ p,
-                const cd_t* __restrict__ ap, int64_t n, double are, double aim,
+                const cd_t* __restrict__ ap, int64_t n, const double* __restrict__ st,
                 double* __restrict__ partials) {
-  const cd_t alpha = {are, aim};
+  const cd_t alpha = st[T3_STOP] != 0.0 ? cd_t{0.0, 0.0}
+                                        : cdiv(st[T3_RHO], st[T3_RHO + 1], st[T3_MU],
+                                               st[T3_MU + 1]);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kTB) {
@@ -137,43 +152,100 @@ __global__ void __launch_bounds__(kTB)
   tsum<3>(acc, partials + (size_t)blockIdx.x * 3);
 }
 
-// p = r + beta p.
+// p = r + beta p with beta = rho_new / rho from the status (0 once frozen).
 __global__ void __launch_bounds__(kTB)
-    k_t3_pupdate(const cd_t* __restrict__ r, cd_t* __restrict__ p, int64_t n, double bre,
-                 double bim) {
-  const cd_t beta = {bre, bim};
+    k_t3_pupdate(const cd_t* __restrict__ r, cd_t* __restrict__ p, int64_t n,
+                 const double* __restrict__ st) {
+  const cd_t beta = st[T3_STOP] != 0.0 ? cd_t{0.0, 0.0}
+                                       : cdiv(st[T3_RHO_NEW], st[T3_RHO_NEW + 1], st[T3_RHO],
+                                              st[T3_RHO + 1]);
   for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kTB)
     p[i] = cadd(r[i], cmul(beta, p[i]));
 }
 
-// out[v] = sum over the kNB blocks of partials[b][v], in a fixed order.
-__global__ void __launch_bounds__(kTB)
-    k_t3_final(const double* __restrict__ partials, int nv, double* __restrict__ out) {
+// out[v] = sum over the kNB blocks of partials[b][v], in a fixed order (in
+// thread 0), then thread 0 applies `post` to the status with the sums.
+template <int NV, class Post>
+__device__ void final_sum(const double* __restrict__ partials, Post post) {
   __shared__ double red[kTB];
-  for (int v = 0; v < nv; ++v) {
+  double out[NV];
+  for (int v = 0; v < NV; ++v) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < kNB; b += kTB) acc += partials[(size_t)b * nv + v];
+    for (int b = threadIdx.x; b < kNB; b += kTB) acc += partials[(size_t)b * NV + v];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kTB / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[v] = red[0];
+    out[v] = red[0];
     __syncthreads();
   }
+  if (threadIdx.x == 0) post(out);
+}
+
+// Start of a stage: |b|^2, |r|^2 and rho = r^T r; converged at once if
+// |r|^2 <= tol^2 |b|^2.
+__global__ void __launch_bounds__(kTB)
+    k_t3_final_init(const double* __restrict__ partials, double tol2, int max_iter,
+                    double* __restrict__ st) {
+  final_sum<4>(partials, [&](const double* o) {
+    st[T3_MAXIT] = (double)max_iter;
+    st[T3_BB] = o[0];
+    st[T3_RR] = o[1];
+    st[T3_RHO] = st[T3_RHO_NEW] = o[2];
+    st[T3_RHO + 1] = st[T3_RHO_NEW + 1] = o[3];
+    st[T3_TOL2] = tol2;
+    st[T3_STOP] = o[1] <= tol2 * o[0] ? 1.0 : 0.0;
+    st[T3_ITER] = 0.0;
+    st[T3_FAIL] = 0.0;
+  });
+}
+
+// mu = p^T A p for this iteration, after rho takes the value of the last
+// update; a zero or non-finite mu is a breakdown (stop, failed).
+__global__ void __launch_bounds__(kTB)
+    k_t3_final_ap(const double* __restrict__ partials, double* __restrict__ st) {
+  final_sum<2>(partials, [&](const double* o) {
+    if (st[T3_STOP] != 0.0) return;
+    st[T3_RHO] = st[T3_RHO_NEW];
+    st[T3_RHO + 1] = st[T3_RHO_NEW + 1];
+    const double mabs = fabs(o[0]) + fabs(o[1]);
+    if (!(mabs > 0.0) || !(mabs < 1e300)) {
+      st[T3_FAIL] = 1.0;
+      st[T3_STOP] = 1.0;
+      return;
+    }
+    st[T3_MU] = o[0];
+    st[T3_MU + 1] = o[1];
+  });
+}
+
+// After the update: one more iteration, |r|^2, rho_new, the test, and the
+// iteration limit (stop there; the host sees |r|^2 above the bar).
+__global__ void __launch_bounds__(kTB)
+    k_t3_final_update(const double* __restrict__ partials, double* __restrict__ st) {
+  final_sum<3>(partials, [&](const double* o) {
+    if (st[T3_STOP] != 0.0) return;
+    st[T3_ITER] += 1.0;
+    st[T3_RR] = o[0];
+    st[T3_RHO_NEW] = o[1];
+    st[T3_RHO_NEW + 1] = o[2];
+    if (o[0] <= st[T3_TOL2] * st[T3_BB] || st[T3_ITER] >= st[T3_MAXIT]) st[T3_STOP] = 1.0;
+  });
 }
 
 template <int S>
 hipError_t init_impl(const Trap3Bufs& b, const double* vraw, int64_t npts, double tau,
-                     hipStream_t st) {
+                     double tol2, int max_iter, hipStream_t st) {
   hipLaunchKernelGGL(k_t3_init<S>, dim3(kNB), dim3(kTB), 0, st, (const cd_t*)b.qz,
                      (const cd_t*)b.qy, (const cd_t*)b.qx, (const cd_t*)b.x, vraw, npts, tau,
                      (cd_t*)b.r, (cd_t*)b.p, b.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t3_final, dim3(1), dim3(kTB), 0, st, b.partials, 4, b.sums);
+  hipLaunchKernelGGL(k_t3_final_init, dim3(1), dim3(kTB), 0, st, b.partials, tol2, max_iter,
+                     b.sums);
   return hipGetLastError();
 }
 
@@ -185,18 +257,18 @@ hipError_t ap_impl(const Trap3Bufs& b, const double* vraw, int64_t npts, double 
                      (cd_t*)b.ap, b.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t3_final, dim3(1), dim3(kTB), 0, st, b.partials, 2, b.sums);
+  hipLaunchKernelGGL(k_t3_final_ap, dim3(1), dim3(kTB), 0, st, b.partials, b.sums);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t t3_init(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
-                   hipStream_t st) {
+                   double tol2, int max_iter, hipStream_t st) {
   switch (S) {
-    case 1: return init_impl<1>(b, vraw, npts, tau, st);
-    case 2: return init_impl<2>(b, vraw, npts, tau, st);
-    case 3: return init_impl<3>(b, vraw, npts, tau, st);
+    case 1: return init_impl<1>(b, vraw, npts, tau, tol2, max_iter, st);
+    case 2: return init_impl<2>(b, vraw, npts, tau, tol2, max_iter, st);
+    case 3: return init_impl<3>(b, vraw, npts, tau, tol2, max_iter, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -211,18 +283,18 @@ hipError_t t3_ap(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, do
   }
 }
 
-hipError_t t3_update(const Trap3Bufs& b, int64_t n, double are, double aim, hipStream_t st) {
+hipError_t t3_update(const Trap3Bufs& b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_t3_update, dim3(kNB), dim3(kTB), 0, st, (cd_t*)b.x, (cd_t*)b.r,
-                     (const cd_t*)b.p, (const cd_t*)b.ap, n, are, aim, b.partials);
+                     (const cd_t*)b.p, (const cd_t*)b.ap, n, (const double*)b.sums, b.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t3_final, dim3(1), dim3(kTB), 0, st, b.partials, 3, b.sums);
+  hipLaunchKernelGGL(k_t3_final_update, dim3(1), dim3(kTB), 0, st, b.partials, b.sums);
   return hipGetLastError();
 }
 
-hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, double bre, double bim, hipStream_t st) {
+hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_t3_pupdate, dim3(kNB), dim3(kTB), 0, st, (const cd_t*)b.r, (cd_t*)b.p, n,
-                     bre, bim);
+                     (const double*)b.sums);
   return hipGetLastError();
 }
 

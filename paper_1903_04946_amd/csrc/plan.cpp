@@ -257,6 +257,19 @@ struct sop_plan {
   double* d_w = nullptr;      // [S] adjoint weights
   sop::GraphCache* graphs = nullptr;
   bool use_graphs = true;
+  // captured blocks of 3D trapezoidal iterations, keyed by state, workspace
+  // and stage coefficient (the kernels' pointers and tau)
+  struct T3Key {
+    const void* x;
+    const void* base;
+    uint64_t tau;
+    bool operator<(const T3Key& o) const {
+      if (x != o.x) return x < o.x;
+      if (base != o.base) return base < o.base;
+      return tau < o.tau;
+    }
+  };
+  std::map<T3Key, hipGraphExec_t> t3graphs;
   sop_allocator hook{};  // device memory hooks (alloc == NULL: hipMalloc/hipFree)
   hipStream_t home = nullptr;  // the creation stream, handed to the hooks
 };
@@ -290,6 +303,7 @@ void free_plan(sop_plan* p) {
                   p->d_scratch, p->d_atab, p->d_akin, p->d_part, p->d_out, p->d_vbase,
                   p->d_dv, p->d_theta, p->d_eig, p->d_w, p->d_drive, p->d_iws, p->d_trap};
   delete p->graphs;
+  for (auto& kv : p->t3graphs) (void)hipGraphExecDestroy(kv.second);
   for (void* b : bufs) {
     if (!b) continue;
     if (p->hook.free)
@@ -812,7 +826,7 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
   if (p->ndim == 3) {
     lay->three_d = true;
     lay->one = ((size_t)p->S * p->npts * sizeof(double2) + 255) / 256 * 256;
-    lay->need = 6 * lay->one + ((size_t)sop::kReduceBlocks * 4 + 4) * sizeof(double) +
+    lay->need = 6 * lay->one + ((size_t)sop::kReduceBlocks * 4 + sop::kT3Status) * sizeof(double) +
                 (size_t)3 * p->n[0] * sizeof(double2);
     return SOP_OK;
   }
@@ -825,10 +839,13 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
 // The trapezoidal rule on a 3D plan: for every state and stage, conjugate
 // orthogonal CG on (1 + i tau H) x = (1 - i tau H) psi started from x = psi,
 // H u = sum_d F_d^-1 T_d(k) F_d u + V u, the kinetic terms computed by the
-// propagator's one-axis passes on copies of u.  The host runs the
-// iteration; every device reduction is in a fixed order.  Synchronises.
+// propagator's one-axis passes on copies of u.  The host enqueues the
+// iterations and reads the device's status block every few of them (the
+// scalars of the method stay on the device); every device reduction is in
+// a fixed order.  Synchronises.
 sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double tol,
-                      int max_iter, char* base, const TrapLayout& lay, int64_t* iterations) {
+                      int max_iter, char* base, const TrapLayout& lay, bool allow_graphs,
+                      int64_t* iterations) {
   const DevView& d = p->dv;
   hipStream_t st = d.stream;
   const int S = p->S, n = p->n[0];
@@ -843,7 +860,7 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
   b.qx = base + 5 * one;
   b.partials = (double*)(base + 6 * one);
   b.sums = b.partials + (size_t)sop::kReduceBlocks * 4;
-  double2* hfac = (double2*)(b.sums + 4);
+  double2* hfac = (double2*)(b.sums + sop::kT3Status);
   // T_d(k) / n_d on the signed frequencies of each axis (the 1/n_d of the
   // unnormalised inverse transform folded in, as in the kinetic factors)
   std::vector<double2> hf((size_t)3 * n);
@@ -861,22 +878,76 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
   dh.kin_stride = n;
   dh.count = 1;
   dh.graphs = nullptr;
+  dh.timer = nullptr;
   const size_t bytes = (size_t)nall * sizeof(double2);
-  // the three one-axis kinetic terms of H u
-  auto kinetic = [&](const void* u) -> sop_status {
+  // the three one-axis kinetic terms of H u, on stream s
+  auto kinetic = [&](const void* u, hipStream_t s) -> sop_status {
     void* q[3] = {b.qz, b.qy, b.qx};
+    dh.stream = s;
     for (int a = 0; a < 3; ++a) {
-      HIPTRY(hipMemcpyAsync(q[a], u, bytes, hipMemcpyDeviceToDevice, st));
+      HIPTRY(hipMemcpyAsync(q[a], u, bytes, hipMemcpyDeviceToDevice, s));
       HIPTRY(sop::k3d_axis_kinetic(dh, q[a], a));
     }
     return SOP_OK;
   };
-  double sums[4];
-  auto read = [&](int nv) -> sop_status {
-    HIPTRY(hipMemcpyAsync(sums, b.sums, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+  // kBlock iterations of stage coefficient tau, on stream s
+  constexpr int kBlock = 4;
+  auto block = [&](double tau, hipStream_t s) -> sop_status {
+    sop_status r;
+    for (int i = 0; i < kBlock; ++i) {
+      if ((r = kinetic(b.p, s)) != SOP_OK) return r;
+      HIPTRY(sop::t3_ap(b, S, p->d_vraw, npts, tau, s));
+      HIPTRY(sop::t3_update(b, nall, s));
+      HIPTRY(sop::t3_pupdate(b, nall, s));
+    }
+    return SOP_OK;
+  };
+  // the block as a graph captured once per (state, workspace, tau): its
+  // launches then cost one graph launch (none for the allocation-free call,
+  // whose contract rules out instantiating graphs)
+  const bool use_graph = allow_graphs && p->use_graphs && p->graphs && p->graphs->capture;
+  auto run_block = [&](double tau) -> sop_status {
+    if (!use_graph) return block(tau, st);
+    uint64_t tb;
+    std::memcpy(&tb, &tau, sizeof(tb));
+    const sop_plan::T3Key key{b.x, base, tb};
+    auto it = p->t3graphs.find(key);
+    if (it == p->t3graphs.end()) {
+      if (p->t3graphs.size() >= 64) {
+        for (auto& kv : p->t3graphs) (void)hipGraphExecDestroy(kv.second);
+        p->t3graphs.clear();
+      }
+      hipStream_t cs = p->graphs->capture;
+      HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      const sop_status bs = block(tau, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(cs, &g);
+      dh.stream = st;
+      if (bs != SOP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return bs;
+      }
+      HIPTRY(ce);
+      hipGraphExec_t x = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPTRY(ie);
+      it = p->t3graphs.emplace(key, x).first;
+    }
+    HIPTRY(hipGraphLaunch(it->second, st));
+    return SOP_OK;
+  };
+  double stat[sop::kT3Status];
+  auto read = [&]() -> sop_status {
+    HIPTRY(hipMemcpyAsync(stat, b.sums, sizeof(stat), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
     return SOP_OK;
   };
+  // iterations of the last solve of each stage: the status is read after
+  // each block once that many are near (the status freezes the iterate once
+  // the test holds, so iterations past it change nothing)
+  std::vector<int> expect(lay.nst, 0);
+  const double tol2 = tol * tol;
   int64_t total = 0, failed = 0;
   sop_status sts;
   for (int c = 0; c < count; ++c) {
@@ -884,40 +955,23 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
     for (int64_t step = 0; step < nsteps; ++step)
       for (int j = 0; j < lay.nst; ++j) {
         const double tau = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
-        if ((sts = kinetic(b.x)) != SOP_OK) return sts;
-        HIPTRY(sop::t3_init(b, S, p->d_vraw, npts, tau, st));
-        if ((sts = read(4)) != SOP_OK) return sts;
-        const double bb = sums[0];
-        double rr = sums[1];
-        double rre = sums[2], rim = sums[3];
-        const double tol2 = tol * tol;
-        int it = 0;
-        bool ok = rr <= tol2 * bb;
-        while (!ok && it < max_iter) {
-          if ((sts = kinetic(b.p)) != SOP_OK) return sts;
-          HIPTRY(sop::t3_ap(b, S, p->d_vraw, npts, tau, st));
-          if ((sts = read(2)) != SOP_OK) return sts;
-          const double mre = sums[0], mim = sums[1];
-          const double mabs = std::fabs(mre) + std::fabs(mim);
-          if (!(mabs > 0.0) || !(mabs < 1e300)) break;  // breakdown: not converged
-          const double den = mre * mre + mim * mim;
-          const double are = (rre * mre + rim * mim) / den, aim = (rim * mre - rre * mim) / den;
-          HIPTRY(sop::t3_update(b, nall, are, aim, st));
-          if ((sts = read(3)) != SOP_OK) return sts;
-          ++it;
-          rr = sums[0];
-          ok = rr <= tol2 * bb;
-          if (!ok) {
-            const double nre = sums[1], nim = sums[2];
-            const double dd = rre * rre + rim * rim;
-            const double bre = (nre * rre + nim * rim) / dd, bim = (nim * rre - nre * rim) / dd;
-            rre = nre;
-            rim = nim;
-            HIPTRY(sop::t3_pupdate(b, nall, bre, bim, st));
+        if ((sts = kinetic(b.x, st)) != SOP_OK) return sts;
+        HIPTRY(sop::t3_init(b, S, p->d_vraw, npts, tau, tol2, max_iter, st));
+        int launched = 0;
+        bool stop = false;
+        while (!stop && launched < max_iter) {
+          if ((sts = run_block(tau)) != SOP_OK) return sts;
+          launched += kBlock;
+          if (launched + kBlock > expect[j] || launched >= max_iter) {
+            if ((sts = read()) != SOP_OK) return sts;
+            stop = stat[sop::T3_STOP] != 0.0;
           }
         }
+        const int it = (int)stat[sop::T3_ITER];
+        expect[j] = it;
         total += it;
-        if (!ok) ++failed;
+        const bool met = stat[sop::T3_RR] <= stat[sop::T3_TOL2] * stat[sop::T3_BB];
+        if (!stop || !met || stat[sop::T3_FAIL] != 0.0) ++failed;
       }
   }
   HIPTRY(hipStreamSynchronize(st));
@@ -932,8 +986,9 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
 // (device, lay.need bytes; nothing in it needs clearing: every element is
 // written before it is read).  Synchronises the plan's stream.
 sop_status trap_run(sop_plan* p, void* psi, int count, int64_t nsteps, double tol, int max_iter,
-                    char* base, const TrapLayout& lay, int64_t* iterations) {
-  if (lay.three_d) return trap3d_run(p, psi, count, nsteps, tol, max_iter, base, lay, iterations);
+                    char* base, const TrapLayout& lay, bool allow_graphs, int64_t* iterations) {
+  if (lay.three_d)
+    return trap3d_run(p, psi, count, nsteps, tol, max_iter, base, lay, allow_graphs, iterations);
   const int nst = lay.nst;
   std::vector<double> taus(nst);
   for (int j = 0; j < nst; ++j) taus[j] = (double)((ld)p->seq.g[j] * (ld)p->dt / (2 * (ld)p->hbar));
@@ -997,7 +1052,7 @@ sop_status sop_propagate_trapezoid(sop_plan* p, void* psi, int count, int64_t ns
       return fail(SOP_ERR_NOMEM, "trapezoid workspace");
     p->trap_bytes = lay.need;
   }
-  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)p->d_trap, lay, iterations);
+  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)p->d_trap, lay, true, iterations);
 }
 
 sop_status sop_propagate_trapezoid_noalloc(sop_plan* p, void* psi, int count, int64_t nsteps,
@@ -1013,7 +1068,7 @@ sop_status sop_propagate_trapezoid_noalloc(sop_plan* p, void* psi, int count, in
                     std::to_string(cap) + " bytes");
   void* base = nullptr;
   HIPTRY(sop::trap_scratch(p->dv.stream, &base));
-  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)base, lay, iterations);
+  return trap_run(p, psi, count, nsteps, tol, max_iter, (char*)base, lay, false, iterations);
 }
 
 sop_status sop_interpolate(const sop_plan* src, const void* psi_src, sop_plan* dst,

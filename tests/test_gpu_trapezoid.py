@@ -170,6 +170,48 @@ def test_3d_against_oracle_krylov(torch_cuda, orc, model, n, S, comp, order, dt,
     assert abs(ob["norm"] - 1.0) < 1e-12
 
 
+def test_3d_graph_blocks_equal_eager_and_noalloc(torch_cuda):
+    """The 3D iteration runs in captured blocks of four iterations with the
+    method's scalars on the device, read back every few blocks; the eager
+    launches (graphs off) and the allocation-free call (never graphs) give
+    bitwise the same states and iteration counts, also on a second call
+    that replays the captured blocks."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32)
+    runs = {}
+    for mode in ("graph", "eager", "noalloc"):
+        plan = soprop.Plan.from_model(m, comp="triple_jump", order=4, dt=10.0)
+        if mode == "eager":
+            plan.set_graphs(False)
+        psi = torch.from_numpy(m.psi0.copy()).cuda()
+        its = [plan.propagate_trapezoid(psi, 1, tol=1e-13, noalloc=mode == "noalloc")
+               for _ in range(2)]
+        runs[mode] = (psi.cpu().numpy(), its)
+        plan.close()
+    print(f"[trap3d] iterations per call {runs['graph'][1]}", flush=True)
+    for mode in ("eager", "noalloc"):
+        np.testing.assert_array_equal(runs[mode][0], runs["graph"][0], err_msg=mode)
+        assert runs[mode][1] == runs["graph"][1], mode
+
+
+def test_3d_iteration_limit_is_exact(torch_cuda):
+    """max_iter bounds every stage's iterations exactly, also where it is not
+    a multiple of the four-iteration blocks: one iteration short of what the
+    solve needs fails, the count it needs succeeds with that count."""
+    torch = torch_cuda
+    from paper_1903_04946_amd import soprop
+    m = synth.lvc_3d(n=32)
+    plan = soprop.Plan.from_model(m, comp="strang", order=2, dt=10.0)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    need = plan.propagate_trapezoid(psi, 1, tol=1e-13)  # Strang: one stage
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    with pytest.raises(soprop.SopError, match="did not reach"):
+        plan.propagate_trapezoid(psi, 1, tol=1e-13, max_iter=need - 1)
+    psi = torch.from_numpy(m.psi0.copy()).cuda()
+    assert plan.propagate_trapezoid(psi, 1, tol=1e-13, max_iter=need) == need
+
+
 def test_3d_refusals_and_non_convergence(torch_cuda):
     torch = torch_cuda
     from paper_1903_04946_amd import soprop
