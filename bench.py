@@ -917,7 +917,7 @@ def run_trapezoid3d(a, torch, soprop):
         "config": {"workload": a.workload, "ndim": 3, "grid": [n] * 3, "nsurf": m.nsurf,
                    "integrator": "trapezoidal rule", "composition": "triple_jump", "order": 4,
                    "substeps_per_step": M, "dt": dt, "solver_tol": tol},
-        "roofline": {"bound": "hbm", "kernel": "one COCG iteration (12 launches, 2 host syncs)",
+        "roofline": {"bound": "hbm", "kernel": "one COCG iteration (11 captured graph nodes; status read every few blocks)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_iteration": bytes_iter, "us_per_iteration": 1e6 * it_s},

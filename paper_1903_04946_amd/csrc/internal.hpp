@@ -216,8 +216,8 @@ struct Trap3Bufs {
   void* qz = nullptr;
   void* qy = nullptr;
   void* qx = nullptr;
-  double* partials = nullptr;
-  double* sums = nullptr;  // the status block, kT3Status doubles (T3_*)
+  double* partials = nullptr;  // kT3Partials doubles
+  double* sums = nullptr;      // the status block, kT3Status doubles (T3_*)
 };
 // Status block of the 3D trapezoidal iteration (doubles): |b|^2, rho =
 // r^T r (re, im), mu = p^T A p (re, im), |r|^2, rho after the last update
@@ -225,20 +225,24 @@ struct Trap3Bufs {
 // the iteration count, the breakdown flag, tol^2 and the iteration limit.
 enum { T3_BB = 0, T3_RHO = 1, T3_MU = 3, T3_RR = 5, T3_RHO_NEW = 6, T3_STOP = 8, T3_ITER = 9,
        T3_FAIL = 10, T3_TOL2 = 11, T3_MAXIT = 12, kT3Status = 13 };
+constexpr int kT3Partials = 9 * 1024;  // 9 x kReduceBlocks
 // From x: r = p = -2 i tau H x; the status for a new stage.
 hipError_t t3_init(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
                    double tol2, int max_iter, hipStream_t st);
-// ap = p + i tau H p; mu (rho takes the last update's value).
+// ap = p + i tau H p with its partial sums of p^T ap.
 hipError_t t3_ap(const Trap3Bufs& b, int S, const double* vraw, int64_t npts, double tau,
                  hipStream_t st);
-// x += alpha p, r -= alpha ap over n = S npts values; |r|^2, rho_new, the test.
-hipError_t t3_update(const Trap3Bufs& b, int64_t n, hipStream_t st);
-// p = r + beta p.
-hipError_t t3_pupdate(const Trap3Bufs& b, int64_t n, hipStream_t st);
-// One one-axis pass (axis 0 = slowest ("z"), 1, 2) of every surface of psi:
-// F_a^-1 f_a F_a with the factor block of d.kin's set 0 for that axis (the
-// propagator's pass kernels; no potential action).
-hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis);
+// x += alpha p, r -= alpha ap (alpha from the sums of t3_ap and of the last
+// update); the iteration count.  parity: the iteration's index mod 2 (0 for
+// the first iteration of a stage).
+hipError_t t3_update(const Trap3Bufs& b, int S, int64_t npts, int parity, hipStream_t st);
+// p = r + beta p; |r|^2 and the residual test, which freezes the status.
+hipError_t t3_pupdate(const Trap3Bufs& b, int S, int64_t npts, int parity, hipStream_t st);
+// One one-axis pass (axis 0 = slowest ("z"), 1, 2) of every surface:
+// psi = F_a^-1 f_a F_a src (src NULL: psi itself) with the factor block of
+// d.kin's set 0 for that axis (the propagator's pass kernels; no potential
+// action).
+hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis, const void* src = nullptr);
 
 // The allocation-free trapezoid call's static device scratch: its size, and
 // its device address on the GPU of `stream` (NULL: the current device),
@@ -383,6 +387,7 @@ hipError_t k3q_launch(int n, int S, bool f64, const BMember3* mem, int count,
 
 constexpr int kMaxParams = 8;
 constexpr int kReduceBlocks = 1024;
+static_assert(kT3Partials == 9 * kReduceBlocks, "trapezoid partial buffers");
 constexpr int kReduceThreads = 256;
 
 }  // namespace sop

@@ -67,12 +67,13 @@ template <typename T, class SC, int S, int C, int AX, bool EQ>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_zpass(cx<T>* __restrict__ psi, const void* __restrict__ vexp, int nv, int iv0, int iv1,
               int conj, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fz,
-              const double* __restrict__ taus) {
+              const double* __restrict__ taus, const cx<T>* src) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  psi += (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member of a batch
-  zpass_body<T, SC, S, C, kTableCols, AX, EQ>(psi, vexp, nv, iv0, iv1, conj, tw, fz, lds,
-                                              blockIdx.x, blockIdx.y, taus);
+  const size_t off = (size_t)blockIdx.z * S * ((size_t)SC::N * SC::N * SC::N);  // member
+  zpass_body<T, SC, S, C, kTableCols, AX, EQ>(psi + off, vexp, nv, iv0, iv1, conj, tw, fz, lds,
+                                              blockIdx.x, blockIdx.y, taus, (int)threadIdx.x,
+                                              src ? src + off : nullptr);
 }
 
 // ---------------------------------------------------------------- adjoint z-pass
@@ -262,11 +263,12 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
 template <typename T, class SC, int C, int AX>
 __global__ void __launch_bounds__(C * SC::TPC)
     k3d_ypass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
-              const cx<T>* __restrict__ fy, int conj) {
+              const cx<T>* __restrict__ fy, int conj, const cx<T>* src) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  ypass_body<T, SC, C, AX>(psi + blockIdx.z * npts, tw, fy, conj, lds, blockIdx.x, blockIdx.y);
+  ypass_body<T, SC, C, AX>(psi + blockIdx.z * npts, tw, fy, conj, lds, blockIdx.x, blockIdx.y,
+                           (int)threadIdx.x, src ? src + blockIdx.z * npts : nullptr);
 }
 
 // ---------------------------------------------------------------- x-pass
@@ -274,12 +276,12 @@ __global__ void __launch_bounds__(C * SC::TPC)
 template <typename T, class SC, int ROWS, int AX>
 __global__ void __launch_bounds__(ROWS * SC::TPC)
     k3d_xpass(cx<T>* __restrict__ psi, const cx<T>* __restrict__ tw,
-              const cx<T>* __restrict__ fx, int conj) {
+              const cx<T>* __restrict__ fx, int conj, const cx<T>* src) {
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int64_t npts = (int64_t)SC::N * SC::N * SC::N;
-  xpass_body<T, SC, ROWS, AX>(psi + blockIdx.z * npts, tw, fx, conj, lds, blockIdx.x,
-                              blockIdx.y);
+  xpass_body<T, SC, ROWS, AX>(psi + blockIdx.z * npts, tw, fx, conj, lds, blockIdx.x, blockIdx.y,
+                              (int)threadIdx.x, src ? src + blockIdx.z * npts : nullptr);
 }
 
 // ---------------------------------------------------------------- xy plane
@@ -387,15 +389,15 @@ struct Passes {
 
   template <int AX>
   static hipError_t z(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int tidx,
-                      int conj) {
+                      int conj, const cx<T>* src = nullptr) {
     if constexpr (EQ) {
-      if (d.eig) return zk<AX, true>(d, psi, nv, iv0, iv1, tidx, conj);
+      if (d.eig) return zk<AX, true>(d, psi, nv, iv0, iv1, tidx, conj, src);
     }
-    return zk<AX, false>(d, psi, nv, iv0, iv1, tidx, conj);
+    return zk<AX, false>(d, psi, nv, iv0, iv1, tidx, conj, src);
   }
   template <int AX, bool Q>
   static hipError_t zk(const DevView& d, cx<T>* psi, int nv, int iv0, int iv1, int tidx,
-                       int conj) {
+                       int conj, const cx<T>* src) {
     auto k = k3d_zpass<T, SC, S, CZ, AX, Q>;
     const size_t lds = (size_t)CZ * N * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
@@ -403,22 +405,25 @@ struct Passes {
     TimedLaunch tl(d, KIND_ZPASS, pass_bytes(d, nv));
     hipLaunchKernelGGL(k, dim3(N / CZ, N, d.count), dim3(CZ * SC::TPC), lds, d.stream, psi,
                        d.vexp, nv, iv0, iv1, conj, (const cx<T>*)d.tw[0],
-                       AX == AX_KIN ? kfac(d, tidx, 0) : nullptr, d.vtaus);
+                       AX == AX_KIN ? kfac(d, tidx, 0) : nullptr, d.vtaus, src);
     return hipGetLastError();
   }
   template <int AX>
-  static hipError_t ypass(const DevView& d, cx<T>* psi, int tidx, int conj) {
+  static hipError_t ypass(const DevView& d, cx<T>* psi, int tidx, int conj,
+                          const cx<T>* src = nullptr) {
     auto k = k3d_ypass<T, XS, C, AX>;
     const size_t lds = y_lds_elems<T, N>(C) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     TimedLaunch tl(d, KIND_YPASS, pass_bytes(d, 0));
     hipLaunchKernelGGL(k, dim3(N / C, N, d.S * d.count), dim3(C * XS::TPC), lds, d.stream, psi,
-                       (const cx<T>*)d.tw[1], AX == AX_KIN ? kfac(d, tidx, 1) : nullptr, conj);
+                       (const cx<T>*)d.tw[1], AX == AX_KIN ? kfac(d, tidx, 1) : nullptr, conj,
+                       src);
     return hipGetLastError();
   }
   template <int AX>
-  static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj) {
+  static hipError_t xpass(const DevView& d, cx<T>* psi, int tidx, int conj,
+                          const cx<T>* src = nullptr) {
     auto k = k3d_xpass<T, XS, ROWS, AX>;
     const size_t lds = x_lds_elems<T, N>(ROWS) * sizeof(cx<T>);
     hipError_t e = set_lds(k, lds);
@@ -426,7 +431,7 @@ struct Passes {
     TimedLaunch tl(d, KIND_XPASS, pass_bytes(d, 0));
     hipLaunchKernelGGL(k, dim3(N / ROWS, N, d.S * d.count), dim3(ROWS * XS::TPC), lds,
                        d.stream, psi, (const cx<T>*)d.tw[2],
-                       AX == AX_KIN ? kfac(d, tidx, 2) : nullptr, conj);
+                       AX == AX_KIN ? kfac(d, tidx, 2) : nullptr, conj, src);
     return hipGetLastError();
   }
 
@@ -678,15 +683,16 @@ hipError_t k3d_propagate(const DevView& d, void* psi, int64_t nsteps, int conj) 
   });
 }
 
-hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis) {
+hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis, const void* src) {
   if (d.timer) d.timer->break_chain();
   return dispatch(d.n[0], d.S, d.f64, [&]<typename T, class SC, int S>() -> hipError_t {
     using P = Passes<T, SC, S>;
     cx<T>* v = (cx<T>*)psi;
+    const cx<T>* u = (const cx<T>*)src;
     switch (axis) {
-      case 0: return P::template z<AX_KIN>(d, v, 0, 0, 0, 0, 0);
-      case 1: return P::template ypass<AX_KIN>(d, v, 0, 0);
-      case 2: return P::template xpass<AX_KIN>(d, v, 0, 0);
+      case 0: return P::template z<AX_KIN>(d, v, 0, 0, 0, 0, 0, u);
+      case 1: return P::template ypass<AX_KIN>(d, v, 0, 0, u);
+      case 2: return P::template xpass<AX_KIN>(d, v, 0, 0, u);
       default: return hipErrorInvalidValue;
     }
   });

@@ -144,7 +144,9 @@ __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __res
 // Split<float> (each entry's index doubled).  `lane` (here and in the y- and
 // x-pass bodies) is the thread's index in the tile, threadIdx.x unless a
 // persistent caller passes it through opaque() so that the compiler does not
-// keep every lane-derived offset live across its work loop.
+// keep every lane-derived offset live across its work loop.  `src` (here and
+// there): where the pass reads the state, psi itself when NULL (in place);
+// the pass always writes psi.
 //
 // EQ (S = 2, 3): `vexp` is instead the one compact eigen-form table, FP64 in
 // both precisions (eig_slots(S) complex double slots per point, same tile
@@ -183,7 +185,8 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
                                            int iv1, int conj, const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fz, cx<T>* lds, int bx,
                                            int by, const double* __restrict__ taus = nullptr,
-                                           int lane = (int)threadIdx.x) {
+                                           int lane = (int)threadIdx.x,
+                                           const cx<T>* src = nullptr) {
   static_assert(TC % C == 0, "pass tile must divide the table tile");
   static_assert(!EQ || S >= 2, "eigen form: two or three surfaces");
   constexpr int N = SC::N, E = SC::E, NE = EQ ? eig_slots(S) : S * (S + 1) / 2;
@@ -198,9 +201,10 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
   const size_t tbase = ((size_t)y * (N / TC) + tx) * tile;
   const LayStrided lay{col, 0, C};  // one surface at a time through LDS
   cx<T> v[S][E];
+  const cx<T>* const in = src ? src : psi;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const auto rs = rsrc(psi + s * npts, (uint32_t)npts);
+    const auto rs = rsrc(in + s * npts, (uint32_t)npts);
 #pragma unroll
     for (int q = 0; q < E; ++q) v[s][q] = ld<T>(rs, own_idx<N, E, SC::RF>(t, q) * plane + off0);
   }
@@ -291,12 +295,14 @@ template <typename T, class SC, int C, int AX>
 __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fy, int conj, cx<T>* lds,
-                                           int bx, int z, int lane = (int)threadIdx.x) {
+                                           int bx, int z, int lane = (int)threadIdx.x,
+                                           const cx<T>* src_s = nullptr) {
   constexpr int N = SC::N, E = SC::E;
   const int col = lane % C, t = lane / C;
   const int x = bx * C + col;
   constexpr int64_t plane = (int64_t)N * N;
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
+  const auto bin = rsrc((src_s ? src_s : psi_s) + z * plane, (uint32_t)plane);
   const LayStrided lay{col, 0, C};
   cx<T>* const tws = lds + C * N;  // staged twiddles and y factor
   if constexpr (AX == AX_KIN) {
@@ -306,7 +312,7 @@ __device__ __forceinline__ void ypass_body(cx<T>* __restrict__ psi_s,
   }
   cx<T> v[1][E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) * N + x);
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(bin, own_idx<N, E, SC::RF>(t, q) * N + x);
   fft_forward<SC, 1>(v, lds, lay, tws, t);
   if constexpr (AX == AX_KIN) {
     axis_phase<T, SC, 1>(v, tws + axis_block<T, N>(), conj ? (T)-1 : (T)1, t);
@@ -324,12 +330,14 @@ template <typename T, class SC, int ROWS, int AX>
 __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
                                            const cx<T>* __restrict__ tw,
                                            const cx<T>* __restrict__ fx, int conj, cx<T>* lds,
-                                           int bx, int z, int lane = (int)threadIdx.x) {
+                                           int bx, int z, int lane = (int)threadIdx.x,
+                                           const cx<T>* src_s = nullptr) {
   constexpr int N = SC::N, E = SC::E, TPC = SC::TPC;
   const int t = lane % TPC, row = lane / TPC;
   const int y = bx * ROWS + row;
   constexpr int64_t plane = (int64_t)N * N;
   const auto base = rsrc(psi_s + z * plane, (uint32_t)plane);
+  const auto bin = rsrc((src_s ? src_s : psi_s) + z * plane, (uint32_t)plane);
   const uint32_t yo = (uint32_t)y * N;
   const LayPadded lay{row * (N + N / 16), 0};
   cx<T>* const tws = lds + ROWS * (N + N / 16);  // staged twiddles and x factor
@@ -340,7 +348,7 @@ __device__ __forceinline__ void xpass_body(cx<T>* __restrict__ psi_s,
   }
   cx<T> v[1][E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(base, own_idx<N, E, SC::RF>(t, q) + yo);
+  for (int q = 0; q < E; ++q) v[0][q] = ld<T>(bin, own_idx<N, E, SC::RF>(t, q) + yo);
   fft_forward<SC, 1>(v, lds, lay, tws, t);
   if constexpr (AX == AX_KIN) {
     axis_phase<T, SC, 1>(v, tws + axis_block<T, N>(), conj ? (T)-1 : (T)1, t);

@@ -826,7 +826,7 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
   if (p->ndim == 3) {
     lay->three_d = true;
     lay->one = ((size_t)p->S * p->npts * sizeof(double2) + 255) / 256 * 256;
-    lay->need = 6 * lay->one + ((size_t)sop::kReduceBlocks * 4 + sop::kT3Status) * sizeof(double) +
+    lay->need = 6 * lay->one + ((size_t)sop::kT3Partials + sop::kT3Status) * sizeof(double) +
                 (size_t)3 * p->n[0] * sizeof(double2);
     return SOP_OK;
   }
@@ -839,7 +839,7 @@ sop_status trap_check(const sop_plan* p, const void* psi, int count, int64_t nst
 // The trapezoidal rule on a 3D plan: for every state and stage, conjugate
 // orthogonal CG on (1 + i tau H) x = (1 - i tau H) psi started from x = psi,
 // H u = sum_d F_d^-1 T_d(k) F_d u + V u, the kinetic terms computed by the
-// propagator's one-axis passes on copies of u.  The host enqueues the
+// propagator's one-axis passes reading u.  The host enqueues the
 // iterations and reads the device's status block every few of them (the
 // scalars of the method stay on the device); every device reduction is in
 // a fixed order.  Synchronises.
@@ -859,7 +859,7 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
   b.qy = base + 4 * one;
   b.qx = base + 5 * one;
   b.partials = (double*)(base + 6 * one);
-  b.sums = b.partials + (size_t)sop::kReduceBlocks * 4;
+  b.sums = b.partials + (size_t)sop::kT3Partials;
   double2* hfac = (double2*)(b.sums + sop::kT3Status);
   // T_d(k) / n_d on the signed frequencies of each axis (the 1/n_d of the
   // unnormalised inverse transform folded in, as in the kinetic factors)
@@ -880,25 +880,24 @@ sop_status trap3d_run(sop_plan* p, void* psi, int count, int64_t nsteps, double 
   dh.graphs = nullptr;
   dh.timer = nullptr;
   const size_t bytes = (size_t)nall * sizeof(double2);
-  // the three one-axis kinetic terms of H u, on stream s
+  // the three one-axis kinetic terms of H u, on stream s (each pass reads u
+  // and writes its own term)
   auto kinetic = [&](const void* u, hipStream_t s) -> sop_status {
     void* q[3] = {b.qz, b.qy, b.qx};
     dh.stream = s;
-    for (int a = 0; a < 3; ++a) {
-      HIPTRY(hipMemcpyAsync(q[a], u, bytes, hipMemcpyDeviceToDevice, s));
-      HIPTRY(sop::k3d_axis_kinetic(dh, q[a], a));
-    }
+    for (int a = 0; a < 3; ++a) HIPTRY(sop::k3d_axis_kinetic(dh, q[a], a, u));
     return SOP_OK;
   };
   // kBlock iterations of stage coefficient tau, on stream s
   constexpr int kBlock = 4;
+  static_assert(kBlock % 2 == 0, "iteration parity per block");
   auto block = [&](double tau, hipStream_t s) -> sop_status {
     sop_status r;
-    for (int i = 0; i < kBlock; ++i) {
+    for (int i = 0; i < kBlock; ++i) {  // kBlock is even: the parity restarts
       if ((r = kinetic(b.p, s)) != SOP_OK) return r;
       HIPTRY(sop::t3_ap(b, S, p->d_vraw, npts, tau, s));
-      HIPTRY(sop::t3_update(b, nall, s));
-      HIPTRY(sop::t3_pupdate(b, nall, s));
+      HIPTRY(sop::t3_update(b, S, npts, i & 1, s));
+      HIPTRY(sop::t3_pupdate(b, S, npts, i & 1, s));
     }
     return SOP_OK;
   };
