@@ -888,12 +888,12 @@ def run_trapezoid3d(a, torch, soprop):
     units = m.nsurf * m.npts * M * a.steps
     stages = M * a.steps
     # algorithmic bytes of one iteration (state-sized vectors of 16 B per
-    # grid point and surface): three copies of p and the three one-axis passes
-    # (each read + written), A p (reads the three terms and p, writes A p),
-    # the update of x and r (reads x, r, p, A p, writes x, r) and of p
-    # (reads r, p, writes p): 26 vectors, plus the V-table (48 B a point)
+    # grid point and surface): the three one-axis passes (each reads p and
+    # writes its term), A p (reads the three terms and p, writes A p), the
+    # update of x and r (reads x, r, p, A p, writes x, r) and of p (reads r,
+    # p, writes p): 20 vectors, plus the V-table (48 B a point)
     vec = 16.0 * m.nsurf * m.npts
-    bytes_iter = 26 * vec + 48.0 * m.npts
+    bytes_iter = 20 * vec + 48.0 * m.npts
     it_s = sec / max(iters + stages, 1)
     achieved = bytes_iter / it_s / 1e9
     cpu = None
@@ -917,7 +917,7 @@ def run_trapezoid3d(a, torch, soprop):
         "config": {"workload": a.workload, "ndim": 3, "grid": [n] * 3, "nsurf": m.nsurf,
                    "integrator": "trapezoidal rule", "composition": "triple_jump", "order": 4,
                    "substeps_per_step": M, "dt": dt, "solver_tol": tol},
-        "roofline": {"bound": "hbm", "kernel": "one COCG iteration (11 captured graph nodes; status read every few blocks)",
+        "roofline": {"bound": "hbm", "kernel": "one COCG iteration (6 captured graph nodes; status read every few blocks)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_iteration": bytes_iter, "us_per_iteration": 1e6 * it_s},
