@@ -22,7 +22,13 @@ namespace {
 
 // One sweep set of cyclic Jacobi rotations on a real symmetric S x S matrix.
 // On return A is diagonal (eigenvalues on the diagonal) and R holds the
-// eigenvectors in its columns.
+// eigenvectors in its columns.  Each rotation's cosine and sine come from
+// the smaller root t = tan(theta) of t^2 + 2 zeta t - 1 = 0, zeta =
+// (a_qq - a_pp) / (2 a_pq) (the symmetric Schur step of Golub and Van Loan,
+// Matrix Computations, Sec. 8.5): t = sign(zeta) / (|zeta| + sqrt(1 +
+// zeta^2)), c = 1 / sqrt(1 + t^2), s = t c -- the rotation with
+// tan(2 theta) = 2 a_pq / (a_qq - a_pp), |theta| <= pi/4, without a
+// trigonometric call.
 template <int S>
 __device__ void jacobi_sym(double (&A)[S][S], double (&R)[S][S]) {
 #pragma unroll
@@ -45,10 +51,13 @@ __device__ void jacobi_sym(double (&A)[S][S], double (&R)[S][S]) {
           continue;
         }
         rotated = true;
-        // tan(2 theta) = 2 a_pq / (a_qq - a_pp), |theta| <= pi/4
-        const double th = 0.5 * atan((2.0 * apq) / (A[q][q] - A[p][p]));
-        double sn, cs;
-        sincos(th, &sn, &cs);
+        const double zeta = (A[q][q] - A[p][p]) / (2.0 * apq);
+        // 1 / (|zeta| + sqrt(1 + zeta^2)) without overflow for huge zeta
+        const double az = fabs(zeta);
+        const double tt = az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
+        const double tn = zeta < 0.0 ? -tt : tt;
+        const double cs = 1.0 / sqrt(1.0 + tn * tn);
+        const double sn = tn * cs;
         // A <- A J (columns p, q), J = [[c, s], [-s, c]] on (p, q)
 #pragma unroll
         for (int r = 0; r < S; ++r) {
