@@ -804,7 +804,7 @@ sop_status sop_batch_describe(const sop_batch* b, char* buf, size_t len, size_t*
       << dtype_name(f.f64) << "\", \"members\": ";
     members(f.members);
     o << ", \"variant\": " << f.variant << ", \"schedule\": \""
-      << sop::k1b_variant_name(f.n, f.variant) << "\", \"from_cache\": "
+      << sop::k1b_variant_name(f.n, f.variant, f.f64) << "\", \"from_cache\": "
       << (f.from_cache ? "true" : "false") << ", \"tuned_ms\": ";
     arr(f.tuned_ms);
     o << "}";

@@ -42,8 +42,14 @@ constexpr int lds_pencil() {
 // action, so that twiddles and addresses are recomputed instead of being
 // held for the whole run.  Measured per step on gfx950 (two surfaces, FP64):
 // N = 8192 55 us guarded vs 141 us held (spilled); 512 and 2048 slightly
-// faster guarded; 1024 and 4096 slightly faster without.
-constexpr bool guard_default(int n) { return n == 512 || n == 2048 || n >= 8192; }
+// faster guarded; 1024 slightly faster without.  At N = 4096 the held FP64
+// kernel spills (256 VGPRs and 400 bytes of scratch a lane) and the guarded
+// one does not (178 VGPRs): 17.8 against 20.8 us a substep; in FP32 nothing
+// spills and holding is faster (12.3 against 14.5 us).
+template <typename T>
+constexpr bool guard_default(int n) {
+  return n == 512 || n == 2048 || n >= 8192 || (n == 4096 && sizeof(T) == 8);
+}
 template <bool GUARD>
 __device__ __forceinline__ int guard(int t) {
   if constexpr (GUARD) return opaque(t);
@@ -52,7 +58,7 @@ __device__ __forceinline__ int guard(int t) {
 
 // PL = pencils exchanged through LDS at once (S, or 1 when S pencils do not
 // fit).  `lds` holds PL padded pencils.
-template <typename T, class SC, int S, int PL, bool GUARD = guard_default(SC::N)>
+template <typename T, class SC, int S, int PL, bool GUARD = guard_default<T>(SC::N)>
 __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp,
                                        const cx<T>* __restrict__ kin,
                                        const cx<T>* __restrict__ tw,

@@ -77,14 +77,23 @@ hipError_t launch(const BMember1* mem, int count, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <class SC, bool G = guard_default(SC::N)>
+// twiddle policy of a variant: the single-plan default of the precision,
+// its opposite, or recomputed twiddles
+enum { G_DEFAULT = 0, G_OTHER = 1, G_ON = 2 };
+template <typename T, int N, int GM>
+constexpr bool guard_of() {
+  return GM == G_ON ? true : (GM == G_DEFAULT ? guard_default<T>(N) : !guard_default<T>(N));
+}
+
+template <class SC, int GM = G_DEFAULT>
 hipError_t by_type(int S, bool f64, const BMember1* mem, int count, hipStream_t stream) {
+  constexpr bool GD = guard_of<double, SC::N, GM>(), GF = guard_of<float, SC::N, GM>();
   if (f64) {
-    if (S == 1) return launch<double, SC, 1, G>(mem, count, stream);
-    if (S == 2) return launch<double, SC, 2, G>(mem, count, stream);
+    if (S == 1) return launch<double, SC, 1, GD>(mem, count, stream);
+    if (S == 2) return launch<double, SC, 2, GD>(mem, count, stream);
   } else {
-    if (S == 1) return launch<float, SC, 1, G>(mem, count, stream);
-    if (S == 2) return launch<float, SC, 2, G>(mem, count, stream);
+    if (S == 1) return launch<float, SC, 1, GF>(mem, count, stream);
+    if (S == 2) return launch<float, SC, 2, GF>(mem, count, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -95,13 +104,13 @@ hipError_t by_type(int S, bool f64, const BMember1* mem, int count, hipStream_t 
 template <int N, class DEF>
 hipError_t tuned(int variant, int S, bool f64, const BMember1* mem, int count,
                  hipStream_t stream) {
-  if (variant == 0) return by_type<DEF>(S, f64, mem, count, stream);
+  if (variant == 0) return by_type<DEF, G_DEFAULT>(S, f64, mem, count, stream);
   if constexpr (N <= 4096) {
-    if (variant == 1) return by_type<DEF, !guard_default(N)>(S, f64, mem, count, stream);
-    if (variant == 2) return by_type<typename Alt<N>::E4, true>(S, f64, mem, count, stream);
-    if (variant == 3) return by_type<typename Alt<N>::E16, true>(S, f64, mem, count, stream);
+    if (variant == 1) return by_type<DEF, G_OTHER>(S, f64, mem, count, stream);
+    if (variant == 2) return by_type<typename Alt<N>::E4, G_ON>(S, f64, mem, count, stream);
+    if (variant == 3) return by_type<typename Alt<N>::E16, G_ON>(S, f64, mem, count, stream);
   } else {
-    if (variant == 1) return by_type<typename Alt<N>::E16, true>(S, f64, mem, count, stream);
+    if (variant == 1) return by_type<typename Alt<N>::E16, G_ON>(S, f64, mem, count, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -117,8 +126,8 @@ int k1b_variants(int n) {
   }
 }
 
-const char* k1b_variant_name(int n, int variant) {
-  const bool g = guard_default(n);
+const char* k1b_variant_name(int n, int variant, bool f64) {
+  const bool g = f64 ? guard_default<double>(n) : guard_default<float>(n);
   if (variant == 0 || (variant == 1 && n <= 4096)) {
     const bool guarded = (variant == 0) ? g : !g;
     switch (n) {
