@@ -86,9 +86,16 @@ KERNEL_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
                   "paper_1903_04946_amd/csrc/fft_core.hpp"]
 
 
-def kernel_source_hash() -> str:
+# the sources the 3D pass kernels are built from (the counters of a traffic
+# summary stay valid while these are unchanged)
+PASS3D_SOURCES = ["paper_1903_04946_amd/csrc/kernels_3d.hip",
+                  "paper_1903_04946_amd/csrc/passes_3d.hpp",
+                  "paper_1903_04946_amd/csrc/fft_core.hpp"]
+
+
+def kernel_source_hash(paths=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in (KERNEL_SOURCES if paths is None else paths):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -103,15 +110,15 @@ def make_model(ndim, n):
 
 def traffic_from_profiles(workload: str, kernel_kind: str):
     """HBM bytes per launch of the dominant kernel from a committed rocprofv3
-    counter summary (profiles/traffic_<workload>.json), if its kernel source
-    hash matches the current sources."""
+    counter summary (profiles/traffic_<workload>.json), if the hash of the 3D
+    pass kernels' sources it records matches the current sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             t = json.load(f)
-        if t.get("kernel_source_hash") != kernel_source_hash():
+        if t.get("pass3d_source_hash") != kernel_source_hash(PASS3D_SOURCES):
             return None
         k = t["kernels"][kernel_kind]
         return float(k["hbm_bytes_per_launch"])
