@@ -5,19 +5,24 @@
 // with the conjugate orthogonal conjugate gradient method (H is real
 // symmetric on the grid, so 1 + i tau H is complex symmetric).  On a 3D grid
 // the kinetic part of H p is the sum of three one-axis terms,
-// T p = sum_d F_d^-1 T_d(k) F_d p, each computed by the pass kernels of the
-// propagator on its own copy of p with the factor T_d(k)/n_d in place of the
-// phase (the host sequences them); the kernels here add the three terms and
-// the S x S matvec with V(x), form A p = p + i tau H p, update the iterates,
-// and reduce the inner products the method needs (u^T v without conjugation,
-// and |u|^2) in a fixed order: block partials, then one final block.
+// T p = sum_d F_d^-1 T_d(k) F_d p, each computed by a pass kernel of the
+// propagator that reads p and writes its own term, with the factor
+// T_d(k)/n_d in place of the phase (the host sequences them); the kernels
+// here add the three terms and the S x S matvec with V(x), form
+// A p = p + i tau H p, update the iterates, and reduce the inner products
+// the method needs (u^T v without conjugation, and |u|^2) in a fixed order:
+// block partials, then a tree over the blocks.
 //
-// The iteration's scalars live on the device (the status block `st`, see
-// T3 below): the final blocks form rho, mu, |r|^2 and the convergence test,
-// and the update kernels read alpha = rho / mu and beta = rho_new / rho from
-// it, so the host only reads the status every few iterations.  Once the
-// residual test holds (or mu breaks down) the status freezes the iterate:
-// later iterations of the block use alpha = beta = 0 and leave x unchanged.
+// The iteration's scalars stay on the device.  Each block of the update
+// kernels forms mu, rho and |r|^2 from the partials itself, every block in
+// the same order, so no separate reduction kernel runs; the residual
+// partials of consecutive iterations alternate between two buffers (by the
+// iteration's parity) so that a kernel reads the previous ones while it
+// writes the new ones.  Block 0 keeps the status block (T3_*: iteration
+// count, |r|^2, stop and breakdown flags), which the host reads every few
+// iterations.  Once the residual test holds (or mu breaks down, or the
+// iteration limit is reached) the status freezes the iterate: later
+// iterations use alpha = beta = 0 and leave x unchanged.
 #include "fft_core.hpp"
 #include "internal.hpp"
 
