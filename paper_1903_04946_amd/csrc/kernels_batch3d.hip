@@ -123,9 +123,8 @@ __global__ void __launch_bounds__(SC::N * SC::TPC)
 // before working on the current one, so the counter's latency hides behind
 // the item; once the member's tickets run out it finishes the item, then
 // moves on to the next member with tickets left, and leaves when none has
-// any.  Items
-// of several tiles and one counter pair per member keep the counter traffic
-// down: same-address atomics are served one at a time.
+// any.  Items of several tiles and one counter pair per member keep the
+// counter traffic down: same-address atomics are served one at a time.
 //
 // Progress: a workgroup holds tickets only while it runs, all of one member,
 // works on them in increasing order, and waits only for smaller tickets of
