@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libsoprop.so")
 SOURCES = ["kernels_3d.hip", "kernels_batch3d.hip", "kernels_batch1d.hip", "kernels_1d.hip",
            "kernels_aux.hip", "kernels_interp.hip", "kernels_trap.hip", "kernels_trap3d.hip",
            "plan.cpp", "batch.cpp"]
-HEADERS = ["fft_core.hpp", "internal.hpp", "body_1d.hpp", "passes_3d.hpp"]
+HEADERS = ["fft_core.hpp", "internal.hpp", "body_1d.hpp", "body_1d_w4.hpp", "passes_3d.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++20", "-O3", "--offload-arch=gfx950", "-fPIC",
          # never emit packed FP32 instructions

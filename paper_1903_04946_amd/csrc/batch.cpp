@@ -245,7 +245,7 @@ namespace {
 
 // ---- tuning of one 1D family on scratch states
 sop_status tune_family(sop_batch* b, Family1& f) {
-  const int nv = sop::k1b_variants(f.n);
+  const int nv = sop::k1b_variants(f.n, f.S);
   if (nv <= 1) return SOP_OK;
   const int cnt = std::min<int>((int)f.members.size(), 64);
   const size_t csize = f.f64 ? 16 : 8;
@@ -559,7 +559,7 @@ sop_status sop_batch_create(sop_plan* const* plans, int count, void* hip_stream,
     return true;
   };
   for (Family1& f : b->fams) {
-    const int nv = sop::k1b_variants(f.n);
+    const int nv = sop::k1b_variants(f.n, f.S);
     if (cached(fam_key(f), nv, &f.variant)) {
       f.from_cache = true;
       continue;
@@ -804,7 +804,7 @@ sop_status sop_batch_describe(const sop_batch* b, char* buf, size_t len, size_t*
       << dtype_name(f.f64) << "\", \"members\": ";
     members(f.members);
     o << ", \"variant\": " << f.variant << ", \"schedule\": \""
-      << sop::k1b_variant_name(f.n, f.variant, f.f64) << "\", \"from_cache\": "
+      << sop::k1b_variant_name(f.n, f.S, f.variant, f.f64) << "\", \"from_cache\": "
       << (f.from_cache ? "true" : "false") << ", \"tuned_ms\": ";
     arr(f.tuned_ms);
     o << "}";

@@ -330,8 +330,8 @@ void set_last_error(const std::string& msg);
 
 // 1D families: candidate schedules ("variants") of each length; variant 0 is
 // the schedule of the single-plan kernel.
-int k1b_variants(int n);
-const char* k1b_variant_name(int n, int variant, bool f64);
+int k1b_variants(int n, int S);
+const char* k1b_variant_name(int n, int S, int variant, bool f64);
 // Runs members mem[0..count) (one workgroup each, in order) with the variant.
 hipError_t k1b_launch(int n, int S, bool f64, int variant, const BMember1* mem, int count,
                       hipStream_t stream);

@@ -1,6 +1,7 @@
 // kernels_1d.hip -- one-dimensional grids: the whole composed time step runs
 // inside one persistent workgroup per wavepacket (the step body is run_1d).
 #include "body_1d.hpp"
+#include "body_1d_w4.hpp"
 
 namespace sop {
 namespace {
@@ -17,6 +18,18 @@ __global__ void __launch_bounds__(SC::TPC)
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   psi += (size_t)blockIdx.x * S * SC::N;  // one workgroup per state
   run_1d<T, SC, S, PL>(psi, vexp, kin, tw, prog, nact, nsteps, conj, lds);
+}
+
+// Two surfaces of 1024 points: the four-wave body.
+template <typename T>
+__global__ void __launch_bounds__(w4::kThreads)
+    k1d_w4_kernel(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp,
+                  const cx<T>* __restrict__ kin, const cx<T>* __restrict__ tw,
+                  const int* __restrict__ prog, int nact, int64_t nsteps, int conj) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  psi += (size_t)blockIdx.x * 2 * w4::N;  // one workgroup per state
+  run_1d_w4<T>(psi, vexp, kin, tw, prog, nact, nsteps, conj, lds);
 }
 
 // Forward transform of every surface (natural order in and out), used for
@@ -45,7 +58,16 @@ template <typename T, class SC, int S>
 hipError_t launch_prop(const DevView& d, void* psi, int64_t nsteps, int conj, int count) {
   constexpr size_t one = (size_t)lds_pencil<SC>() * sizeof(cx<T>);
   TimedLaunch tl(d, KIND_1D, 2.0 * S * SC::N * sizeof(cx<T>) * count);
-  if (one * S <= kMaxLds) {
+  if constexpr (SC::N == w4::N && S == 2) {
+    constexpr size_t bytes = w4::lds_bytes<T>();
+    auto k = k1d_w4_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count), dim3(w4::kThreads), bytes, d.stream, (cx<T>*)psi,
+                       (const cx<T>*)d.vexp, (const cx<T>*)d.kin, (const cx<T>*)d.tw[0], d.prog,
+                       d.nact, nsteps, conj);
+  } else if (one * S <= kMaxLds) {
     auto k = k1d_prop_kernel<T, SC, S, S>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(one * S));

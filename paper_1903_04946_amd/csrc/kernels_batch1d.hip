@@ -13,6 +13,7 @@
 // single-plan kernel.  All variants compute the same DFTs, in different
 // radix orders.
 #include "body_1d.hpp"
+#include "body_1d_w4.hpp"
 
 namespace sop {
 namespace {
@@ -58,6 +59,29 @@ __global__ void __launch_bounds__(SC::TPC)
                           (const cx<T>*)m.tw, m.prog, m.nact, m.nsteps, m.conj, lds);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(w4::kThreads) k1b_w4_kernel(const BMember1* __restrict__ mem) {
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const BMember1 m = mem[blockIdx.x];
+  if (m.nsteps <= 0) return;
+  run_1d_w4<T>((cx<T>*)m.psi, (const cx<T>*)m.vexp, (const cx<T>*)m.kin, (const cx<T>*)m.tw,
+               m.prog, m.nact, m.nsteps, m.conj, lds);
+}
+
+// two surfaces of 1024 points on four waves
+hipError_t launch_w4(bool f64, const BMember1* mem, int count, hipStream_t stream) {
+  auto go = [&](auto k, size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(count), dim3(w4::kThreads), bytes, stream, mem);
+    return hipGetLastError();
+  };
+  if (f64) return go(k1b_w4_kernel<double>, w4::lds_bytes<double>());
+  return go(k1b_w4_kernel<float>, w4::lds_bytes<float>());
+}
+
 template <typename T, class SC, int S, bool G>
 hipError_t launch(const BMember1* mem, int count, hipStream_t stream) {
   constexpr size_t one = (size_t)lds_pencil<SC>() * sizeof(cx<T>);
@@ -100,10 +124,15 @@ hipError_t by_type(int S, bool f64, const BMember1* mem, int count, hipStream_t 
 
 // variants of one tuned length N <= 4096: 0 the default E8 schedule, 1 the
 // same with the other twiddle policy, 2 E4 and 3 E16 (recomputed twiddles);
-// N = 8192: 0 E8, 1 E16 (both recomputed).
+// N = 8192: 0 E8, 1 E16 (both recomputed).  Two surfaces of 1024 points: 0
+// the four-wave body (the single-plan kernel there), 4 the default E8.
 template <int N, class DEF>
 hipError_t tuned(int variant, int S, bool f64, const BMember1* mem, int count,
                  hipStream_t stream) {
+  if constexpr (N == w4::N) {
+    if (S == 2 && variant == 0) return launch_w4(f64, mem, count, stream);
+    if (S == 2 && variant == 4) return by_type<DEF, G_DEFAULT>(S, f64, mem, count, stream);
+  }
   if (variant == 0) return by_type<DEF, G_DEFAULT>(S, f64, mem, count, stream);
   if constexpr (N <= 4096) {
     if (variant == 1) return by_type<DEF, G_OTHER>(S, f64, mem, count, stream);
@@ -117,7 +146,8 @@ hipError_t tuned(int variant, int S, bool f64, const BMember1* mem, int count,
 
 }  // namespace
 
-int k1b_variants(int n) {
+int k1b_variants(int n, int S) {
+  if (n == w4::N && S == 2) return 5;
   switch (n) {
     case 512: case 1024: case 2048: case 4096: return 4;
     case 8192: return 2;
@@ -126,8 +156,12 @@ int k1b_variants(int n) {
   }
 }
 
-const char* k1b_variant_name(int n, int variant, bool f64) {
+const char* k1b_variant_name(int n, int S, int variant, bool f64) {
   const bool g = f64 ? guard_default<double>(n) : guard_default<float>(n);
+  if (n == w4::N && S == 2) {
+    if (variant == 0) return "four waves, radix 8.8.4.4 (four-step), wave-local exchanges";
+    if (variant == 4) variant = 0;
+  }
   if (variant == 0 || (variant == 1 && n <= 4096)) {
     const bool guarded = (variant == 0) ? g : !g;
     switch (n) {
@@ -169,7 +203,7 @@ const char* k1b_variant_name(int n, int variant, bool f64) {
 hipError_t k1b_launch(int n, int S, bool f64, int variant, const BMember1* mem, int count,
                       hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  if (variant < 0 || variant >= k1b_variants(n)) return hipErrorInvalidValue;
+  if (variant < 0 || variant >= k1b_variants(n, S)) return hipErrorInvalidValue;
   using namespace s1d;
   switch (n) {
     case 16: return by_type<S16>(S, f64, mem, count, stream);
