@@ -162,7 +162,8 @@ hipError_t k1d_fft_forward(const DevView& d, void* psi);
 struct AdjointView {
   void* stacked = nullptr;      // [2S][npts] complex: psi then lambda
   const void* eig = nullptr;    // R and lam per point, z-pass tile layout, S(S+1)/2 pairs
-  double* qacc = nullptr;       // [S(S+1)/2][npts] packed gradient accumulator
+  double* qacc = nullptr;       // packed gradient accumulator, S(S+1)/2 doubles a point,
+                                // [tile (y, x/C)][z][entry][x % C], C = k3d_adjoint_cols
   const double* taus = nullptr; // c dt / hbar of each potential table
   const void* checkpoints = nullptr;  // [ncp][S][npts] complex, psi at steps 0, K, 2K, ...
 };
@@ -170,6 +171,8 @@ struct AdjointView {
 // kernels_3d.hip
 bool k3d_supported(int n, int S);
 bool k3d_adjoint_supported(int n, int S, bool f64);
+// Columns per tile of the adjoint z-pass and of its gradient accumulator.
+int k3d_adjoint_cols(int n);
 hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps, int K);
 // Columns per z-pass tile; 3D potential tables are stored tile-contiguous
 // ([tile (y, x/C)][z][entry][x % C]) with this C.
@@ -287,8 +290,9 @@ hipError_t set_vparams(const DevView& d, double* vraw, const double* vbase, cons
                        const double* delta_dev, int nparams);
 hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const double* w_dev,
                         double* qacc);
-hipError_t grad_reduce(const DevView& d, const double* qacc, const double* dv, int nparams,
-                       double* partials, double* out_dev);
+// qacc in the accumulator's tile layout with `cols` columns per tile
+hipError_t grad_reduce(const DevView& d, const double* qacc, int cols, const double* dv,
+                       int nparams, double* partials, double* out_dev);
 // out_dev[0..S) = sum |psi_s|^2, out_dev[S] = sum psi^dag V psi (raw sums)
 hipError_t pops_reduce(const DevView& d, const void* psi, const double* vraw_dev,
                        double* partials, double* out_dev);

@@ -91,7 +91,10 @@ __global__ void __launch_bounds__(C * SC::TPC)
 //        = -i tau exp(-i tau (lam_a + lam_b)/2) sinc(tau (lam_a - lam_b)/2),
 // so that d P / d theta_k = 2 dV sum_x sum_ij Q_ij(x) D_k,ij(x) (Daleckii-
 // Krein form of the Frechet derivative of exp(-i tau V(theta))).  Q is kept
-// packed (Q_ii; Q_ij + Q_ji for i < j) in qacc[entry][point].  With KZ the
+// packed (Q_ii; Q_ij + Q_ji for i < j) and tile-contiguous like the tables,
+// qacc[tile (y, x/C)][z][entry][x % C], so that a workgroup's accumulator
+// reads and writes are whole contiguous runs (C * S(S+1)/2 doubles per z)
+// rather than C-double segments of S(S+1)/2 separate arrays.  With KZ the
 // pass then applies the adjoint z factor K_z^dag (conjugated f_z) to all 2S
 // pencils.
 // The pass tile is C columns of the TC-column table tiles (C divides TC).
@@ -117,6 +120,7 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
   const int tcol = (blockIdx.x * C) % TC + col;  // column within the table tile
   const size_t tbase = ((size_t)y * (N / TC) + (blockIdx.x * C) / TC) * tile;
   const LayStrided lay{col, 0, C};
+  double* const qbase = qacc + ((size_t)y * (N / C) + blockIdx.x) * ((size_t)N * NE * C) + col;
   cx<double> v[P][E];
 #pragma unroll
   for (int s = 0; s < P; ++s) {
@@ -131,7 +135,6 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
-      const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * plane + off0;
       double ev[2 * NE];  // R (row-major S x S) then lam (S)
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -207,7 +210,12 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
 #pragma unroll
           for (int i = 0; i < S; ++i) tq[i][b] += ev[i * S + a] * rm;
         }
-      // Q = T R^T, accumulated packed
+      // Q = T R^T, accumulated packed.  The point's accumulator address is
+      // made to depend on T, so that its loads are not issued ahead of the
+      // point's arithmetic (held across it, they cost the pass its registers)
+      uint32_t qo = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * C);
+      asm volatile("" : "+v"(qo) : "v"(tq[0][0]));
+      double* const qp0 = qbase + qo;
       int e = 0;
 #pragma unroll
       for (int i = 0; i < S; ++i)
@@ -219,8 +227,7 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
             qij += tq[i][b] * ev[j * S + b];
             qji += tq[j][b] * ev[i * S + b];
           }
-          double* qp = qacc + (size_t)e * npts + pt;
-          *qp += (i == j) ? qij : qij + qji;
+          qp0[e * C] += (i == j) ? qij : qij + qji;
           ++e;
         }
       // psi_{j-1} = R beta, lambda_{j-1} = R conj(D) alpha
@@ -552,14 +559,20 @@ struct Passes {
   }
 
   // ------------------------------------------------------------ adjoint
+  // Columns per adjoint z-pass tile: 256 threads per block, but at least 8
+  // columns (128-byte row segments; 512 threads at 256^3, two waves per SIMD
+  // as the register budget allows).  The gradient accumulator's tiles have
+  // this width.
+  static constexpr int kAdjCA0 = (256 / AdjSched<SC>::type::TPC < kTableCols)
+                                     ? 256 / AdjSched<SC>::type::TPC
+                                     : kTableCols;
+  static constexpr int kAdjCols = kAdjCA0 < 8 ? 8 : kAdjCA0;
+
   template <bool KZ>
   static hipError_t za(const DevView& d, const AdjointView& a, int nv, int iv0, int iv1,
                        int tidx) {
     using SA = typename AdjSched<SC>::type;
-    // 256 threads per block, but at least 8 columns (128-byte row segments;
-    // 512 threads at 256^3, two waves per SIMD as the register budget allows)
-    constexpr int CA0 = (256 / SA::TPC < kTableCols) ? 256 / SA::TPC : kTableCols;
-    constexpr int CA = CA0 < 8 ? 8 : CA0;
+    constexpr int CA = kAdjCols;
     auto k = k3d_zpass_adj<SA, S, CA, kTableCols, KZ>;
     const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
@@ -700,6 +713,16 @@ hipError_t k3d_axis_kinetic(const DevView& d, void* psi, int axis, const void* s
 
 bool k3d_adjoint_supported(int n, int S, bool f64) {
   return f64 && S >= 1 && S <= 3 && (n == 32 || n == 64 || n == 128 || n == 256);
+}
+
+int k3d_adjoint_cols(int n) {
+  switch (n) {
+    case 32: return Passes<double, Z32, 1>::kAdjCols;
+    case 64: return Passes<double, Z64, 1>::kAdjCols;
+    case 128: return Passes<double, Z128, 1>::kAdjCols;
+    case 256: return Passes<double, Z256, 1>::kAdjCols;
+    default: return 0;
+  }
 }
 
 hipError_t k3d_adjoint_backward(const DevView& d, const AdjointView& a, int64_t nsteps, int K) {

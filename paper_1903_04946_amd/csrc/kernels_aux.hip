@@ -427,18 +427,24 @@ __global__ void __launch_bounds__(256) k_zero(double* __restrict__ p, int64_t n)
     p[i] = 0.0;
 }
 
-// Per block: g_k = sum_x sum_e qacc[e][x] dv[k][e][x], k < NP.
+// Per block: g_k = sum_x sum_e Q_e(x) dv[k][e][x], k < NP, with Q_e(x) read
+// from the accumulator's tile layout [tile (y, x/C)][z][e][x % C] on an n^3
+// grid (point x = (z n + y) n + x0).
 template <int NP>
 __global__ void __launch_bounds__(kReduceThreads)
     k_grad_partials(const double* __restrict__ qacc, const double* __restrict__ dv, int NE,
-                    int64_t npts, double* __restrict__ partials) {
+                    int64_t npts, int n, int cols, double* __restrict__ partials) {
   double acc[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+  const int64_t plane = (int64_t)n * n;
   for (int64_t x = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; x < npts;
        x += (int64_t)gridDim.x * kReduceThreads) {
+    const int64_t z = x / plane, r = x - z * plane;
+    const int64_t y = r / n, x0 = r - y * n;
+    const int64_t qb = ((y * (n / cols) + x0 / cols) * n + z) * (int64_t)NE * cols + x0 % cols;
     for (int e = 0; e < NE; ++e) {
-      const double q = qacc[(int64_t)e * npts + x];
+      const double q = qacc[qb + (int64_t)e * cols];
 #pragma unroll
       for (int k = 0; k < NP; ++k) acc[k] += q * dv[((int64_t)k * NE + e) * npts + x];
     }
@@ -565,14 +571,15 @@ hipError_t adjoint_seed(const DevView& d, void* lam, const void* psi, const doub
   return hipGetLastError();
 }
 
-hipError_t grad_reduce(const DevView& d, const double* qacc, const double* dv, int nparams,
-                       double* partials, double* out_dev) {
+hipError_t grad_reduce(const DevView& d, const double* qacc, int cols, const double* dv,
+                       int nparams, double* partials, double* out_dev) {
+  if (d.ndim != 3 || cols <= 0 || d.n[0] % cols != 0) return hipErrorInvalidValue;
   const int NE = d.S * (d.S + 1) / 2;
   switch (nparams) {
 #define SOP_GRAD_CASE(K)                                                                    \
   case K:                                                                                   \
     hipLaunchKernelGGL(k_grad_partials<K>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,    \
-                       d.stream, qacc, dv, NE, d.npts, partials);                           \
+                       d.stream, qacc, dv, NE, d.npts, d.n[0], cols, partials);             \
     break;
     SOP_GRAD_CASE(1)
     SOP_GRAD_CASE(2)

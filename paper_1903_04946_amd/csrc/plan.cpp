@@ -1480,7 +1480,8 @@ sop_status sop_adjoint_backward(sop_plan* p, int64_t nsteps, int K, const double
   a.taus = p->d_taus;
   a.checkpoints = w + lay.ckpt;
   HIPTRY(sop::k3d_adjoint_backward(p->dv, a, nsteps, K));
-  HIPTRY(sop::grad_reduce(p->dv, a.qacc, p->d_dv, p->nparams, p->d_part, p->d_out));
+  HIPTRY(sop::grad_reduce(p->dv, a.qacc, sop::k3d_adjoint_cols(p->n[0]), p->d_dv, p->nparams,
+                          p->d_part, p->d_out));
   double raw[sop::kMaxParams];
   HIPTRY(hipMemcpyAsync(raw, p->d_out, p->nparams * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPTRY(hipStreamSynchronize(s));
