@@ -161,7 +161,8 @@ hipError_t k1d_fft_forward(const DevView& d, void* psi);
 // Device buffers of an adjoint sweep (FP64 only).
 struct AdjointView {
   void* stacked = nullptr;      // [2S][npts] complex: psi then lambda
-  const void* eig = nullptr;    // R and lam per point, z-pass tile layout, S(S+1)/2 pairs
+  const void* eig = nullptr;    // eigen form per point, z-pass tile layout: S >= 2 the
+                                // compact form (eig_slots(S) slots), S = 1 the pair (1, V)
   double* qacc = nullptr;       // packed gradient accumulator, S(S+1)/2 doubles a point,
                                 // [tile (y, x/C)][z][entry][x % C], C = k3d_adjoint_cols
   const double* taus = nullptr; // c dt / hbar of each potential table

@@ -80,7 +80,9 @@ __global__ void __launch_bounds__(C * SC::TPC)
 // Backward sweep of the adjoint method over the stacked state [psi; lambda]
 // (2S pencils, FP64).  For each potential action j, walked in reverse, the
 // kernel holds psi_j (the state after the action) and lambda_j (the adjoint
-// after it) and, with V(x) = R diag(lam) R^T read from the eigen table and
+// after it) and, with V(x) = R diag(lam) R^T read from the eigen table (for
+// two and three surfaces the compact form: R as a unit quaternion or a
+// rotation angle's (cos, sin), and the eigenvalues; for one surface (1, V)) and
 // D = diag(exp(-i tau lam)), computes in eigen coordinates
 //   psi_{j-1} = U_j^dag psi_j = R conj(D) R^T psi_j,
 //   lambda_{j-1} = U_j^dag lambda_j = R conj(D) R^T lambda_j,
@@ -110,12 +112,13 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
   extern __shared__ char smem_raw[];
   cx<double>* lds = reinterpret_cast<cx<double>*>(smem_raw);
   constexpr int N = SC::N, E = SC::E, NE = S * (S + 1) / 2, P = 2 * S;
+  constexpr int NQ = S >= 2 ? eig_slots(S) : 1;  // eigen-table slots per point
   const int lane = threadIdx.x;
   const int col = lane % C, t = lane / C;
   const int x = blockIdx.x * C + col, y = blockIdx.y;
   constexpr uint32_t plane = (uint32_t)N * N;
   constexpr int64_t npts = (int64_t)plane * N;
-  constexpr uint32_t tile = (uint32_t)N * NE * TC;
+  constexpr uint32_t tile = (uint32_t)N * NQ * TC;
   const uint32_t off0 = (uint32_t)y * N + x;
   const int tcol = (blockIdx.x * C) % TC + col;  // column within the table tile
   const size_t tbase = ((size_t)y * (N / TC) + (blockIdx.x * C) / TC) * tile;
@@ -134,13 +137,26 @@ __global__ void __launch_bounds__(C * SC::TPC) __attribute__((amdgpu_waves_per_e
     const double tau = taus[iv];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
-      double ev[2 * NE];  // R (row-major S x S) then lam (S)
+      const uint32_t tp = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NQ * TC) + tcol;
+      double ev[S * S + S];  // R (row-major S x S) then lam (S)
+      {
+        cx<double> sl[NQ];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const cx<double> w = ld<double>(rg, tp + e * TC);
-        ev[2 * e] = w.re;
-        ev[2 * e + 1] = w.im;
+        for (int e = 0; e < NQ; ++e) sl[e] = ld<double>(rg, tp + e * TC);
+        if constexpr (S == 1) {
+          ev[0] = 1.0;
+          ev[1] = sl[0].im;
+        } else {
+          double R[S][S];
+          rotation_from_slots<double, S>(sl, R);
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int j = 0; j < S; ++j) ev[i * S + j] = R[i][j];
+          ev[S * S] = sl[S == 3 ? 2 : 1].re;
+          ev[S * S + 1] = sl[S == 3 ? 2 : 1].im;
+          if constexpr (S == 3) ev[S * S + 2] = sl[NQ - 1].re;
+        }
       }
       // eigen coordinates: gamma = R^T psi_j, alpha = R^T lambda_j
       cx<double> ga[S], al[S];
@@ -577,10 +593,12 @@ struct Passes {
     const size_t lds = (size_t)CA * N * sizeof(cx<double>);
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
-    // psi, lambda read + written; per action the eigen table (S(S+1)/2
-    // complex) and the gradient accumulator (S(S+1)/2 doubles, read + written)
+    // psi, lambda read + written; per action the eigen table (eig_slots(S)
+    // complex for S >= 2, one for S = 1) and the gradient accumulator
+    // (S(S+1)/2 doubles, read + written)
     constexpr double NE = S * (S + 1) / 2.0;
-    const double bytes = ((4.0 * S + nv * NE) * sizeof(cx<double>) +
+    constexpr double NQ = S >= 2 ? eig_slots(S) : 1;
+    const double bytes = ((4.0 * S + nv * NQ) * sizeof(cx<double>) +
                           nv * 2.0 * NE * sizeof(double)) * (double)d.npts;
     TimedLaunch tl(d, KIND_OTHER, bytes);
     hipLaunchKernelGGL(k, dim3(N / CA, N), dim3(CA * SA::TPC), lds, d.stream,

@@ -362,9 +362,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Eigen-decomposition table for the adjoint: per point R (row-major S x S)
-// then the eigenvalues, as S(S+1)/2 pairs of doubles in the z-pass tile
-// layout (the pair of entry e is stored where a table stores its entry e).
+// Eigen-decomposition table for the adjoint of one surface: per point the pair
+// (R = 1, V) in the z-pass tile layout (two and three surfaces use the compact
+// eigen form of k_form_eigq).  Written for any S: R row-major S x S, then the
+// eigenvalues, as S(S+1)/2 pairs of doubles.
 template <int S>
 __global__ void __launch_bounds__(256)
     k_form_eig(const double* __restrict__ vraw, int64_t npts, int tile, int n,
@@ -545,8 +546,9 @@ hipError_t form_eig(const DevView& d, const double* vraw_dev, int tile, void* ou
   if (blocks > 4096) blocks = 4096;
   switch (d.S) {
     case 1: hipLaunchKernelGGL(k_form_eig<1>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
-    case 2: hipLaunchKernelGGL(k_form_eig<2>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
-    case 3: hipLaunchKernelGGL(k_form_eig<3>, dim3(blocks), dim3(256), 0, d.stream, vraw_dev, d.npts, tile, d.n[0], (cx<double>*)out); break;
+    // two and three surfaces: the compact eigen form (rotation and eigenvalues)
+    case 2:
+    case 3: return form_eigq(d, vraw_dev, tile, out, nullptr, nullptr);
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

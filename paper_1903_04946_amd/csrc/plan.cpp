@@ -663,7 +663,8 @@ sop_status sop_plan_create_with_allocator(const sop_plan_desc* desc, void* hip_s
     HIPTRY(hipMemcpyAsync(p->d_theta, p->theta.data(), p->nparams * sizeof(double),
                           hipMemcpyHostToDevice, stream));
     if (p->ndim == 3 && f64 && sop::k3d_adjoint_supported(p->n[0], S, f64)) {
-      if (dalloc(p, &p->d_eig, (size_t)NE * p->npts * sizeof(double) * 2) != hipSuccess) {
+      const int nslots = S >= 2 ? sop::eig_slots(S) : NE;  // compact eigen form for S >= 2
+      if (dalloc(p, &p->d_eig, (size_t)nslots * p->npts * sizeof(double) * 2) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SOP_ERR_NOMEM, "device allocation failed for the eigen table");
       }

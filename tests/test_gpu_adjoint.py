@@ -201,3 +201,49 @@ def test_populations_autograd(torch_cuda):
     plan.adjoint_forward(psi0, 3, 2, ws)
     ref = plan.adjoint_backward(3, 2, [0.0, -0.3, 1.0], ws)
     np.testing.assert_allclose(theta.grad.numpy(), ref, rtol=0, atol=1e-14)
+
+
+def sub_model(n, surfaces):
+    """The LVC model restricted to the given surfaces (the diabatic block of
+    V and of dV/dtheta), with the initial packet moved onto the last of them
+    and, for one surface, a parameter table of its own (D = q_3 on the
+    diagonal), since the couplings have no diagonal part."""
+    m, theta0, _ = base_model(n)
+    full = synth.lvc_vtable_theta(m, theta0)
+    idx = {(0, 0): 0, (0, 1): 1, (0, 2): 2, (1, 1): 3, (1, 2): 4, (2, 2): 5}
+    pairs = [(a, b) for i, a in enumerate(surfaces) for b in surfaces[i:]]
+    rows = [idx[(min(a, b), max(a, b))] for a, b in pairs]
+    vt = np.ascontiguousarray(full[rows])
+    if len(surfaces) == 1:
+        n2 = m.n[2]
+        x = m.lo[2] + np.arange(n2) * ((m.hi[2] - m.lo[2]) / n2)
+        q3 = np.broadcast_to(x[None, None, :], (m.n[0], m.n[1], n2)).ravel()
+        dv = np.ascontiguousarray(0.01 * q3[None, None, :])
+    else:
+        dv = np.ascontiguousarray(m.dvtables[:, rows, :])
+    psi0 = np.zeros((len(surfaces),) + m.psi0.shape[1:], dtype=np.complex128)
+    psi0[-1] = m.psi0[2]
+    return m, vt, dv, psi0
+
+
+@pytest.mark.parametrize("surfaces", [(1, 2), (0, 2), (2,)])
+def test_adjoint_fewer_surfaces_vs_oracle_tangent(torch_cuda, orc, surfaces):
+    """Two surfaces (the compact eigen form's rotation angle) and one surface
+    against the oracle's tangent-mode gradient."""
+    from paper_1903_04946_amd import soprop
+    torch = torch_cuda
+    m, vt, dv, psi0 = sub_model(32, surfaces)
+    S = len(surfaces)
+    nsteps, K = 3, 2
+    plan = soprop.Plan(m.n, m.lo, m.hi, S, m.inv_mass, vt, comp="triple_jump", order=4, dt=10.0,
+                       dvtables=dv)
+    ws = plan.adjoint_workspace(nsteps, K)
+    w = np.array([0.3, -0.7][:S]) if S == 2 else np.array([1.0])
+    pops, grad = plan.adjoint(torch.from_numpy(psi0).cuda(), nsteps, K, w, ws)
+    P = orc.Problem(m.n, m.lo, m.hi, S, m.inv_mass, vt)
+    opops, ograd = orc.gradient(P, dv, psi0, orc.VTV, 1, 4, 10.0, nsteps, w)
+    print(f"[adjoint S={S}] gpu grad {grad} oracle {ograd}")
+    np.testing.assert_allclose(pops, opops, rtol=0, atol=1e-12)
+    assert np.max(np.abs(grad - ograd)) < 1e-10 * max(1.0, np.max(np.abs(ograd)))
+    if S == 2:
+        assert np.max(np.abs(ograd)) > 1e-6  # the couplings move population
