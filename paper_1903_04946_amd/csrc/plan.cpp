@@ -1344,8 +1344,13 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
   const sop_status run = [&]() -> sop_status {
   for (int64_t n = 0; n < nsteps; ++n) {
     int v = 0;
-    for (int a = 0; a < nact; ++a) {
+    for (int a = 0; a < nact;) {
       const int code = p->dv.hprog[a];
+      // a potential action runs together with the kinetic action after it
+      // (on 3D grids inside that action's z-pass, as in a static step); a
+      // potential action with no kinetic action after it in the step runs
+      // alone
+      int na = 1;
       if ((code >> 16) == sop::OP_V) {
         // V = V0 + s D formed inside the table kernel (no V table written)
         const double* s_dev = p->d_drive + (size_t)n * nv + v++;
@@ -1357,13 +1362,16 @@ sop_status sop_propagate_driven(sop_plan* p, void* psi, int64_t nsteps, const do
           HIPTRY(sop::form_vexp(d, p->d_vbase, p->d_taus + idx, 1, p->tile,
                                 (char*)p->d_vexp + (size_t)idx * tab, p->d_dv, s_dev));
         }
+        if (a + 1 < nact && (p->dv.hprog[a + 1] >> 16) == sop::OP_T) na = 2;
       }
       d.prog = p->d_prog + a;
-      d.hprog = {code};
+      d.nact = na;
+      d.hprog.assign(p->dv.hprog.begin() + a, p->dv.hprog.begin() + a + na);
       if (p->ndim == 1)
         HIPTRY(sop::k1d_propagate(d, psi, 1, 0));
       else
         HIPTRY(sop::k3d_propagate(d, psi, 1, 0));
+      a += na;
     }
   }
   return SOP_OK;
