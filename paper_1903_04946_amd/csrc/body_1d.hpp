@@ -57,7 +57,8 @@ __device__ __forceinline__ int guard(int t) {
 }
 
 // PL = pencils exchanged through LDS at once (S, or 1 when S pencils do not
-// fit).  `lds` holds PL padded pencils.
+// fit).  `lds` holds PL padded pencils.  With one pencil of buffer and two
+// surfaces the two transforms run interleaved (fft_forward_pair).
 template <typename T, class SC, int S, int PL, bool GUARD = guard_default<T>(SC::N)>
 __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __restrict__ vexp,
                                        const cx<T>* __restrict__ kin,
@@ -98,6 +99,8 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
       } else {
         if constexpr (PL == S) {
           fft_forward<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
+        } else if constexpr (S == 2) {
+          fft_forward_pair<SC>(v, lds, lay, tw, guard<GUARD>(t0));
         } else {
 #pragma unroll
           for (int s = 0; s < S; ++s) fft_forward<SC, 1>(v + s, lds, lay, tw, guard<GUARD>(t0));
@@ -111,6 +114,8 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
         }
         if constexpr (PL == S) {
           fft_inverse<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
+        } else if constexpr (S == 2) {
+          fft_inverse_pair<SC>(v, lds, lay, tw, guard<GUARD>(t0));
         } else {
 #pragma unroll
           for (int s = 0; s < S; ++s) fft_inverse<SC, 1>(v + s, lds, lay, tw, guard<GUARD>(t0));

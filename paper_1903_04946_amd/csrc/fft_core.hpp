@@ -409,6 +409,78 @@ __device__ __forceinline__ void run_stages(cx<T> (*v)[E], cx<T>* lds, const Lay&
   }
 }
 
+// Two pencils through one single-pencil LDS buffer, the second half a stage
+// behind the first: while one pencil's exchange reads are in flight, the
+// other pencil's butterflies run, so that the arithmetic of one overlaps the
+// LDS traffic of the other (the buffer holds one pencil, as when the two do
+// not fit in LDS together; same stages, same arithmetic as two transforms in
+// turn).  Precondition of each level: pencil 0 has done stage (R, L),
+// pencil 1 has not.
+template <typename T, int N, int E, int R, int L, int R2, class Lay>
+__device__ __forceinline__ void exchange_write(const cx<T> (&v)[E], cx<T>* lds, const Lay& lay,
+                                               int t) {
+  constexpr int TPC = N / E;
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    const int j = t + TPC * b;
+    const int k = j % L;
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int m = 0; m < R; ++m) lds[lay.off(0, base + m * L)] = v[b * R + m];
+  }
+}
+template <typename T, int N, int E, int R2, class Lay>
+__device__ __forceinline__ void exchange_read(cx<T> (&v)[E], const cx<T>* lds, const Lay& lay,
+                                              int t) {
+  constexpr int TPC = N / E;
+#pragma unroll
+  for (int b = 0; b < E / R2; ++b) {
+    const int j = t + TPC * b;
+#pragma unroll
+    for (int m = 0; m < R2; ++m) v[b * R2 + m] = lds[lay.off(0, j + m * (N / R2))];
+  }
+}
+template <typename T, int N, int E, bool INV, int L, class Lay, int R, int... Rest>
+__device__ __forceinline__ void pair_levels(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
+                                            const cx<T>* __restrict__ tw, int t,
+                                            RList<R, Rest...>) {
+  if constexpr (sizeof...(Rest) == 0) {
+    stage<T, N, E, R, L, INV>(v[1], t, tw);
+  } else {
+    constexpr int R2 = RHead<Rest...>::value;
+    exchange_write<T, N, E, R, L, R2>(v[0], lds, lay, t);
+    __syncthreads();
+    exchange_read<T, N, E, R2>(v[0], lds, lay, t);
+    stage<T, N, E, R, L, INV>(v[1], t, tw);
+    __syncthreads();
+    exchange_write<T, N, E, R, L, R2>(v[1], lds, lay, t);
+    __syncthreads();
+    exchange_read<T, N, E, R2>(v[1], lds, lay, t);
+    stage<T, N, E, R2, L * R, INV>(v[0], t, tw);
+    __syncthreads();
+    pair_levels<T, N, E, INV, L * R, Lay>(v, lds, lay, tw, t, RList<Rest...>{});
+  }
+}
+template <typename T, int N, int E, bool INV, class Lay, int R, int... Rest>
+__device__ __forceinline__ void pair_stages(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
+                                            const cx<T>* __restrict__ tw, int t,
+                                            RList<R, Rest...> rl) {
+  stage<T, N, E, R, 1, INV>(v[0], t, tw);
+  pair_levels<T, N, E, INV, 1, Lay>(v, lds, lay, tw, t, rl);
+}
+// Forward / inverse transforms of the two pencils v[0], v[1] through a buffer
+// of one pencil (orderings as fft_forward / fft_inverse).
+template <class SC, typename T, class Lay>
+__device__ __forceinline__ void fft_forward_pair(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                                 const cx<T>* __restrict__ tw, int t) {
+  pair_stages<T, SC::N, SC::E, false, Lay>(v, lds, lay, tw, t, typename SC::Fwd{});
+}
+template <class SC, typename T, class Lay>
+__device__ __forceinline__ void fft_inverse_pair(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                                 const cx<T>* __restrict__ tw, int t) {
+  pair_stages<T, SC::N, SC::E, true, Lay>(v, lds, lay, tw, t, typename SC::Inv{});
+}
+
 // Forward transform of P pencils v[0..P-1]: input in radix-RF ownership,
 // output in radix-RL ownership.
 template <class SC, int P, typename T, class Lay>
