@@ -97,7 +97,9 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
           for (int s = 0; s < S; ++s) v[s][q] = w[s];
         }
       } else {
-        if constexpr (PL == S) {
+        if constexpr (PL == S && S == 2) {
+          fft_forward_pair2<SC>(v, lds, lay, tw, guard<GUARD>(t0));
+        } else if constexpr (PL == S) {
           fft_forward<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
         } else if constexpr (S == 2) {
           fft_forward_pair<SC>(v, lds, lay, tw, guard<GUARD>(t0));
@@ -112,7 +114,9 @@ __device__ __forceinline__ void run_1d(cx<T>* __restrict__ psi, const cx<T>* __r
 #pragma unroll
           for (int s = 0; s < S; ++s) v[s][q] = fmul(v[s][q], f);
         }
-        if constexpr (PL == S) {
+        if constexpr (PL == S && S == 2) {
+          fft_inverse_pair2<SC>(v, lds, lay, tw, guard<GUARD>(t0));
+        } else if constexpr (PL == S) {
           fft_inverse<SC, S>(v, lds, lay, tw, guard<GUARD>(t0));
         } else if constexpr (S == 2) {
           fft_inverse_pair<SC>(v, lds, lay, tw, guard<GUARD>(t0));

@@ -418,7 +418,7 @@ __device__ __forceinline__ void run_stages(cx<T> (*v)[E], cx<T>* lds, const Lay&
 // pencil 1 has not.
 template <typename T, int N, int E, int R, int L, int R2, class Lay>
 __device__ __forceinline__ void exchange_write(const cx<T> (&v)[E], cx<T>* lds, const Lay& lay,
-                                               int t) {
+                                               int t, int p = 0) {
   constexpr int TPC = N / E;
 #pragma unroll
   for (int b = 0; b < E / R; ++b) {
@@ -426,18 +426,18 @@ __device__ __forceinline__ void exchange_write(const cx<T> (&v)[E], cx<T>* lds, 
     const int k = j % L;
     const int base = (j - k) * R + k;
 #pragma unroll
-    for (int m = 0; m < R; ++m) lds[lay.off(0, base + m * L)] = v[b * R + m];
+    for (int m = 0; m < R; ++m) lds[lay.off(p, base + m * L)] = v[b * R + m];
   }
 }
 template <typename T, int N, int E, int R2, class Lay>
 __device__ __forceinline__ void exchange_read(cx<T> (&v)[E], const cx<T>* lds, const Lay& lay,
-                                              int t) {
+                                              int t, int p = 0) {
   constexpr int TPC = N / E;
 #pragma unroll
   for (int b = 0; b < E / R2; ++b) {
     const int j = t + TPC * b;
 #pragma unroll
-    for (int m = 0; m < R2; ++m) v[b * R2 + m] = lds[lay.off(0, j + m * (N / R2))];
+    for (int m = 0; m < R2; ++m) v[b * R2 + m] = lds[lay.off(p, j + m * (N / R2))];
   }
 }
 template <typename T, int N, int E, bool INV, int L, class Lay, int R, int... Rest>
@@ -461,6 +461,49 @@ __device__ __forceinline__ void pair_levels(cx<T> (*v)[E], cx<T>* lds, const Lay
     pair_levels<T, N, E, INV, L * R, Lay>(v, lds, lay, tw, t, RList<Rest...>{});
   }
 }
+// The same with a buffer for each pencil: two barriers a level, as when the
+// two go through together, with each pencil's exchange reads in flight while
+// the other pencil's butterflies run.
+template <typename T, int N, int E, bool INV, int L, class Lay, int R, int... Rest>
+__device__ __forceinline__ void pair2_levels(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
+                                             const cx<T>* __restrict__ tw, int t,
+                                             RList<R, Rest...>) {
+  if constexpr (sizeof...(Rest) == 0) {
+    stage<T, N, E, R, L, INV>(v[1], t, tw);
+  } else {
+    constexpr int R2 = RHead<Rest...>::value;
+    exchange_write<T, N, E, R, L, R2>(v[0], lds, lay, t, 0);
+    __syncthreads();
+    exchange_read<T, N, E, R2>(v[0], lds, lay, t, 0);
+    stage<T, N, E, R, L, INV>(v[1], t, tw);
+    exchange_write<T, N, E, R, L, R2>(v[1], lds, lay, t, 1);
+    __syncthreads();
+    exchange_read<T, N, E, R2>(v[1], lds, lay, t, 1);
+    stage<T, N, E, R2, L * R, INV>(v[0], t, tw);
+    pair2_levels<T, N, E, INV, L * R, Lay>(v, lds, lay, tw, t, RList<Rest...>{});
+  }
+}
+template <typename T, int N, int E, bool INV, class Lay, int R, int... Rest>
+__device__ __forceinline__ void pair2_stages(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
+                                             const cx<T>* __restrict__ tw, int t,
+                                             RList<R, Rest...> rl) {
+  stage<T, N, E, R, 1, INV>(v[0], t, tw);
+  // no barrier at the end: the last reads of each buffer precede a barrier
+  // that every thread passes before its next write to that buffer (the next
+  // transform writes pencil 0's buffer first, pencil 1's after a barrier)
+  pair2_levels<T, N, E, INV, 1, Lay>(v, lds, lay, tw, t, rl);
+}
+template <class SC, typename T, class Lay>
+__device__ __forceinline__ void fft_forward_pair2(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                                  const cx<T>* __restrict__ tw, int t) {
+  pair2_stages<T, SC::N, SC::E, false, Lay>(v, lds, lay, tw, t, typename SC::Fwd{});
+}
+template <class SC, typename T, class Lay>
+__device__ __forceinline__ void fft_inverse_pair2(cx<T> (*v)[SC::E], cx<T>* lds, const Lay& lay,
+                                                  const cx<T>* __restrict__ tw, int t) {
+  pair2_stages<T, SC::N, SC::E, true, Lay>(v, lds, lay, tw, t, typename SC::Inv{});
+}
+
 template <typename T, int N, int E, bool INV, class Lay, int R, int... Rest>
 __device__ __forceinline__ void pair_stages(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
                                             const cx<T>* __restrict__ tw, int t,
