@@ -368,6 +368,15 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
                                    next());
     if (e != hipSuccess) return e;
   }
+  // lockstep chains: [lo, hi) of a group's members, the stream, and the
+  // members still running at the current cycle (z-pass, y/x passes)
+  struct Chain {
+    const Group3* g;
+    int lo, hi;
+    hipStream_t st;
+    int nz = hi - lo, nyx = hi - lo;
+  };
+  std::vector<Chain> chains;
   for (Group3& g : b->groups) {
     if (b->use_queue) {
       if (g.tickets <= 0) continue;
@@ -377,32 +386,37 @@ hipError_t enqueue(sop_batch* b, const std::vector<int64_t>& nsteps, void* const
       if (e != hipSuccess) return e;
       continue;
     }
-    for (const auto& ch : g.chains) {
-      hipStream_t st = next();
-      const int lo = ch.first, hi = ch.second;
-      const int64_t maxc = g.cycles[lo];
-      BMember3* mem = g.d_mem + lo;
-      const bool plane = b->use_plane && sop::k3b_plane(g.n, g.f64);
-      int nz = hi - lo, nyx = hi - lo;  // members with cycles >= c, > c
-      for (int64_t c = 0; c <= maxc; ++c) {
-        while (nz > 0 && g.cycles[lo + nz - 1] < c) --nz;
-        while (nyx > 0 && g.cycles[lo + nyx - 1] <= c) --nyx;
-        hipError_t e = sop::k3b_launch(sop::B3_Z, g.n, g.S, g.f64, g.vz, mem, nz, c, st);
-        if (e != hipSuccess) return e;
-        if (c == maxc) break;
-        if (plane) {
-          if ((e = sop::k3b_launch(sop::B3_XY, g.n, g.S, g.f64, 0, mem, nyx, c, st)) !=
-              hipSuccess)
-            return e;
-          continue;
-        }
-        if ((e = sop::k3b_launch(sop::B3_Y, g.n, g.S, g.f64, g.vy, mem, nyx, c, st)) !=
+    for (const auto& ch : g.chains) chains.push_back({&g, ch.first, ch.second, next()});
+  }
+  // Every chain's cycle c is enqueued before any chain's cycle c + 1, so that
+  // the chains start together when the launches are enqueued eagerly (a long
+  // chain enqueued after all the others would start late); each chain keeps
+  // its own stream, so the order of its own launches is unchanged.
+  int64_t cmax = -1;
+  for (const Chain& ch : chains) cmax = std::max(cmax, ch.g->cycles[ch.lo]);
+  for (int64_t c = 0; c <= cmax; ++c) {
+    for (Chain& ch : chains) {
+      const Group3& g = *ch.g;
+      const int64_t maxc = g.cycles[ch.lo];
+      if (c > maxc) continue;
+      BMember3* mem = g.d_mem + ch.lo;
+      while (ch.nz > 0 && g.cycles[ch.lo + ch.nz - 1] < c) --ch.nz;
+      while (ch.nyx > 0 && g.cycles[ch.lo + ch.nyx - 1] <= c) --ch.nyx;
+      hipError_t e = sop::k3b_launch(sop::B3_Z, g.n, g.S, g.f64, g.vz, mem, ch.nz, c, ch.st);
+      if (e != hipSuccess) return e;
+      if (c == maxc) continue;
+      if (b->use_plane && sop::k3b_plane(g.n, g.f64)) {
+        if ((e = sop::k3b_launch(sop::B3_XY, g.n, g.S, g.f64, 0, mem, ch.nyx, c, ch.st)) !=
             hipSuccess)
           return e;
-        if ((e = sop::k3b_launch(sop::B3_X, g.n, g.S, g.f64, g.vx, mem, nyx, c, st)) !=
-            hipSuccess)
-          return e;
+        continue;
       }
+      if ((e = sop::k3b_launch(sop::B3_Y, g.n, g.S, g.f64, g.vy, mem, ch.nyx, c, ch.st)) !=
+          hipSuccess)
+        return e;
+      if ((e = sop::k3b_launch(sop::B3_X, g.n, g.S, g.f64, g.vx, mem, ch.nyx, c, ch.st)) !=
+          hipSuccess)
+        return e;
     }
   }
   for (int m : b->solo) {
