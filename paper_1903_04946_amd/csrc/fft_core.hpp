@@ -409,13 +409,9 @@ __device__ __forceinline__ void run_stages(cx<T> (*v)[E], cx<T>* lds, const Lay&
   }
 }
 
-// Two pencils through one single-pencil LDS buffer, the second half a stage
-// behind the first: while one pencil's exchange reads are in flight, the
-// other pencil's butterflies run, so that the arithmetic of one overlaps the
-// LDS traffic of the other (the buffer holds one pencil, as when the two do
-// not fit in LDS together; same stages, same arithmetic as two transforms in
-// turn).  Precondition of each level: pencil 0 has done stage (R, L),
-// pencil 1 has not.
+// The two halves of exchange() for one pencil, in pencil slot p of the
+// layout: the writes of a (R, L) stage's outputs, and the reads of the next
+// stage's (radix R2) inputs.  The caller places the barriers.
 template <typename T, int N, int E, int R, int L, int R2, class Lay>
 __device__ __forceinline__ void exchange_write(const cx<T> (&v)[E], cx<T>* lds, const Lay& lay,
                                                int t, int p = 0) {
@@ -440,6 +436,13 @@ __device__ __forceinline__ void exchange_read(cx<T> (&v)[E], const cx<T>* lds, c
     for (int m = 0; m < R2; ++m) v[b * R2 + m] = lds[lay.off(p, j + m * (N / R2))];
   }
 }
+// Two pencils through one single-pencil LDS buffer, the second half a stage
+// behind the first: while one pencil's exchange reads are in flight, the
+// other pencil's butterflies run, so that the arithmetic of one overlaps the
+// LDS traffic of the other (the buffer holds one pencil, as when the two do
+// not fit in LDS together; same stages, same arithmetic as two transforms in
+// turn).  Precondition of each level: pencil 0 has done stage (R, L),
+// pencil 1 has not.
 template <typename T, int N, int E, bool INV, int L, class Lay, int R, int... Rest>
 __device__ __forceinline__ void pair_levels(cx<T> (*v)[E], cx<T>* lds, const Lay& lay,
                                             const cx<T>* __restrict__ tw, int t,
