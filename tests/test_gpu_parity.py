@@ -203,6 +203,17 @@ def test_1d_lengths(torch_cuda, orc, n, S):
     assert_parity(got, ref, FP64_TOL)
 
 
+@pytest.mark.parametrize("n", [512, 2048, 4096, 8192])
+def test_1d_lengths_fp32(torch_cuda, orc, n):
+    """Two-surface FP32 states (their transforms run interleaved through LDS)
+    against the FP64 oracle: 27 substeps of FP32 round-off, held to 5e-6."""
+    torch = torch_cuda
+    m = synth.random_small([n], 2, seed=n + 7, lo=-8, hi=8)
+    got, _ = gpu_run(torch, m, "VTV", "triple_jump", 4, 0.02, 3, dtype=torch.complex64)
+    ref = oracle_run(orc, m, "VTV", "triple_jump", 4, 0.02, 3)
+    assert_parity(got, ref, 5e-6, f"1D FP32 n={n}")
+
+
 def test_1d_backward_direction(torch_cuda, orc):
     torch = torch_cuda
     m = synth.two_surface_1d(n=512)
