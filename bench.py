@@ -1380,6 +1380,12 @@ def main(argv=None) -> int:
                      "traffic": None if traffic is None else traffic,
                      "traffic_frac": None if traffic is None
                      else traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     # FETCH_SIZE / WRITE_SIZE count the L2's requests to the
+                     # memory fabric: HBM or the last-level cache (MALL) in
+                     # front of it, which no gfx950 counter tells apart; the
+                     # beyond-cache entry below is the DRAM-only figure
+                     "traffic_counts": None if traffic is None
+                     else "L2-to-fabric bytes (HBM or MALL)",
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": bytes_per_launch,
                      "stream_copy_GBps": copy_gbps}
         | ({} if no_mall is None else {"beyond_last_level_cache": no_mall}),
