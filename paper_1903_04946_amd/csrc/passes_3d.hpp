@@ -157,6 +157,9 @@ __device__ __forceinline__ void axis_phase(cx<T> (*v)[SC::E], const cx<T>* __res
 // once).  The action is computed in FP64 in both precisions: an FP32 state
 // is widened, rotated and phased in FP64 and rounded once, so the FP32 form
 // carries no rounded potential operator.
+// cache-policy bits of a buffer load: non-temporal
+constexpr int kCpolNT = 2;
+
 template <typename T, int S>
 __device__ __forceinline__ void rotation_from_slots(const cx<T>* q, T (&R)[S][S]) {
   if constexpr (S == 2) {
@@ -220,7 +223,14 @@ __device__ __forceinline__ void zpass_body(cx<T>* __restrict__ psi,
         const uint32_t pt = (uint32_t)own_idx<N, E, SC::RF>(t, q) * (NE * TC) + tcol;
         cx<double> sl[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) sl[e] = ld<double>(rq, pt + e * TC);
+        for (int e = 0; e < NE; ++e) {
+          // an eigen table larger than the last-level cache (256^3: 1.07 GB)
+          // is read with the non-temporal hint: read once a pass, it would
+          // only evict the state from the caches
+          const sop_u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(
+              rq, (int)((pt + e * TC) * 16u), 0, N >= 256 ? kCpolNT : 0);
+          sl[e] = __builtin_bit_cast(cx<double>, w);
+        }
         double R[S][S];
         rotation_from_slots<double, S>(sl, R);
         const double lam[3] = {sl[S == 3 ? 2 : 1].re, sl[S == 3 ? 2 : 1].im,
